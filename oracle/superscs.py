@@ -1,0 +1,327 @@
+"""SuperSCS, Algorithm 1 of the paper, in plain FP64 NumPy.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Sources in the paper:
+  * DRS on Q + N_C, equation (drs), Sec. IV-A; T and R = I - T, Sec. IV-A/B.
+  * SuperMann steps K0/K1/K2 with backtracking, Algorithm 1, Sec. IV-B.
+  * Linearity trick for the line search (w~ = u~ + alpha d~), Sec. IV-B.
+  * Termination (pr, dr, gap, ic, uc), Sec. IV-C.
+  * Restarted Broyden directions, Sec. IV-D-1 and Algorithm 2.
+  * Anderson's acceleration, Sec. IV-D-2.
+Readings of silent or garbled points (each named where it is used):
+  R1 cold start u0 = (0, 0, 1).           R2 w = u + d in a K0 step.
+  R3 backtracking capped at ls_max, then the KM step u - lambda R u.
+  R4 q^nu is q to the power of the iteration counter.
+  R5 the (z, xi) pair used at iteration nu comes from iteration nu-1's last
+     trial point w; none at nu = 0; no push when z = 0.
+  R6 Algorithm 2's denominator <s^i, H xi~^i> read as <z^i, H xi~^i>.
+  R7 Algorithm 2's restart: clear the buffers, then store the current pair.
+  R8 Anderson: FIFO memory of the last mem pairs; t from the regularised
+     normal equations (Xi^T Xi + mu I) t = Xi^T R u with
+     mu = 1e-12 tr(Xi^T Xi) / k; a non-finite t gives d = -R u.
+  R9 ic and uc divided by -<b, y> and -<c, x> so both are nonnegative.
+  R10 returned triplet is the barred one; certificates normalised to
+      <b, y> = -1 and <c, x> = -1.  R11 Euclidean norms throughout.
+  R12 precedence: SOLVED, then INFEASIBLE, then UNBOUNDED.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from .cones import proj_C
+from .linsys import DirectLinSys
+
+SOLVED, INFEASIBLE, UNBOUNDED, MAX_ITERS, TIME_LIMIT, NUMERICAL = 1, 2, 3, 4, 5, 6
+STATUS_NAMES = {1: "solved", 2: "infeasible", 3: "unbounded", 4: "max_iters",
+                5: "time_limit", 6: "numerical"}
+
+
+@dataclasses.dataclass
+class Settings:
+    eps: float = 1e-6
+    direction: str = "aa"          # "rb" (Algorithm 2), "aa" (Anderson), "none" (d = -Ru), "zero" (d = 0)
+    mem: int = 5
+    c0: Optional[float] = None     # default 0.1 for RB (Sec. IV-D-1), 0.99 for AA
+    c1: float = 0.99
+    q: float = 0.99
+    sigma: float = 0.01
+    lam: float = 1.0
+    thetabar: float = 0.1
+    ls_max: int = 10
+    max_iters: int = 10000
+    max_time: float = math.inf
+    aa_reg: float = 1e-12
+
+    def c0_value(self) -> float:
+        if self.c0 is not None:
+            return self.c0
+        return 0.1 if self.direction == "rb" else 0.99
+
+
+# ----------------------------------------------------------------------------
+# Directions
+# ----------------------------------------------------------------------------
+
+class RestartedBroyden:
+    """Algorithm 2 (modified restarted Broyden), products of rank-one factors:
+    H = (I + zt_m z_m^T) ... (I + zt_1 z_1^T), H_0 = I."""
+
+    def __init__(self, mem: int, thetabar: float):
+        self.mem = mem
+        self.thetabar = thetabar
+        self.Z: List[np.ndarray] = []
+        self.Zt: List[np.ndarray] = []
+
+    def apply(self, v):
+        v = v.copy()
+        for zi, zti in zip(self.Z, self.Zt):
+            v = v + float(zi @ v) * zti
+        return v
+
+    def direction(self, r, z=None, xi=None):
+        if z is None:
+            return -self.apply(r)
+        d = -r.copy()
+        zt = xi.copy()
+        for zi, zti in zip(self.Z, self.Zt):
+            zt = zt + float(zi @ zt) * zti
+            d = d + float(zi @ d) * zti
+        gamma = float(zt @ z) / float(z @ z)
+        if abs(gamma) >= self.thetabar:
+            theta = 1.0
+        else:
+            sgn = 1.0 if gamma >= 0 else -1.0          # sgn(0) = 1
+            theta = (1.0 - sgn * self.thetabar) / (1.0 - gamma)
+        zt = (1.0 - theta) * z + theta * zt               # H xi~
+        zt = (z - zt) / float(z @ zt)                     # new auxiliary vector (R6)
+        d = d + float(z @ d) * zt
+        if len(self.Z) == self.mem:                       # restart (R7)
+            self.Z, self.Zt = [z.copy()], [zt]
+        else:
+            self.Z.append(z.copy())
+            self.Zt.append(zt)
+        return d
+
+
+class Anderson:
+    """Anderson's acceleration (Sec. IV-D-2): d = -Ru - (Z - Xi) t with t the
+    least-squares solution of Xi t = Ru (normal equations, reading R8)."""
+
+    def __init__(self, mem: int, reg: float = 1e-12):
+        self.mem = mem
+        self.reg = reg
+        self.Z: List[np.ndarray] = []
+        self.Xi: List[np.ndarray] = []
+
+    def push(self, z, xi):
+        self.Z.append(z.copy())
+        self.Xi.append(xi.copy())
+        if len(self.Z) > self.mem:
+            self.Z.pop(0)
+            self.Xi.pop(0)
+
+    def coefficients(self, r):
+        Xi = np.stack(self.Xi, axis=1)
+        G = Xi.T @ Xi
+        k = G.shape[0]
+        mu = self.reg * float(np.trace(G)) / k
+        with np.errstate(all="ignore"):
+            try:
+                t = np.linalg.solve(G + mu * np.eye(k), Xi.T @ r)
+            except np.linalg.LinAlgError:
+                return None
+        if not np.all(np.isfinite(t)):
+            return None
+        return t
+
+    def direction(self, r):
+        if not self.Z:
+            return -r.copy()
+        t = self.coefficients(r)
+        if t is None:
+            return -r.copy()
+        Z = np.stack(self.Z, axis=1)
+        Xi = np.stack(self.Xi, axis=1)
+        return -r - (Z - Xi) @ t
+
+
+# ----------------------------------------------------------------------------
+# T-oracle and termination
+# ----------------------------------------------------------------------------
+
+def residual(lin: DirectLinSys, cone, u):
+    """(u~, u-bar, R u) with u~ = (I+Q)^{-1} u, u-bar = Pi_C(2u~ - u) and
+    R u = u~ - u-bar (equation (drs) and R = I - T, Sec. IV-A/B)."""
+    ut = lin.L(u)
+    ub = proj_C(2.0 * ut - u, lin.n, cone)
+    return ut, ub, ut - ub
+
+
+def termination(lin: DirectLinSys, u, ut, ub, eps):
+    """Sec. IV-C.  Returns (status or 0, info dict, (x, y, s))."""
+    n, m = lin.n, lin.m
+    A, b, c = lin.A, lin.b, lin.c
+    chi, psi, tau = ub[:n], ub[n:n + m], ub[-1]
+    sig = psi - 2.0 * ut[n:n + m] + u[n:n + m]
+    Ax_s = A @ chi + sig
+    Aty = lin.At @ psi
+    cx = float(c @ chi)
+    by = float(b @ psi)
+    nb = float(np.linalg.norm(b))
+    nc = float(np.linalg.norm(c))
+    info = dict(pr=math.inf, dr=math.inf, gap=math.inf, ic=math.inf, uc=math.inf,
+                pobj=math.nan, dobj=math.nan, tau=float(tau))
+    if tau > 0:
+        info["pr"] = float(np.linalg.norm(Ax_s - b * tau)) / tau / (1.0 + nb)
+        info["dr"] = float(np.linalg.norm(Aty + c * tau)) / tau / (1.0 + nc)
+        info["gap"] = abs(cx + by) / tau / (1.0 + abs(cx) / tau + abs(by) / tau)
+        info["pobj"] = cx / tau
+        info["dobj"] = -by / tau
+    if by < 0:
+        info["ic"] = nb * float(np.linalg.norm(Aty)) / (-by)
+    if cx < 0:
+        info["uc"] = nc * float(np.linalg.norm(Ax_s)) / (-cx)
+    if tau > 0 and info["pr"] <= eps and info["dr"] <= eps and info["gap"] <= eps:
+        return SOLVED, info, (chi / tau, psi / tau, sig / tau)
+    if info["ic"] < eps:
+        nanx = np.full(n, np.nan)
+        return INFEASIBLE, info, (nanx, psi / (-by), np.full(m, np.nan))
+    if info["uc"] < eps:
+        return UNBOUNDED, info, (chi / (-cx), np.full(m, np.nan), sig / (-cx))
+    if tau > 0:
+        return 0, info, (chi / tau, psi / tau, sig / tau)
+    return 0, info, (np.full(n, np.nan), np.full(m, np.nan), np.full(m, np.nan))
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Result:
+    status: int
+    x: np.ndarray
+    y: np.ndarray
+    s: np.ndarray
+    iters: int
+    info: dict
+    history: list
+    counts: dict
+    u: np.ndarray
+    setup_s: float = 0.0
+    solve_s: float = 0.0
+
+    @property
+    def status_name(self):
+        return STATUS_NAMES.get(self.status, "?")
+
+
+def solve(prob, settings: Settings = Settings(), u0=None, lin: DirectLinSys = None,
+          record: bool = True) -> Result:
+    """Algorithm 1 with the directions of Sec. IV-D."""
+    t_setup = time.perf_counter()
+    A, b, c, cone = prob.A, prob.b, prob.c, prob.cone
+    m, n = A.shape
+    assert cone.rows() == m, "cone sizes must add up to the number of rows"
+    if lin is None:
+        lin = DirectLinSys(A, b, c)
+    setup_s = time.perf_counter() - t_setup
+    t0 = time.perf_counter()
+    st = settings
+    c0 = st.c0_value()
+    u = np.zeros(n + m + 1)
+    u[-1] = 1.0                                            # R1
+    if u0 is not None:
+        u = np.asarray(u0, dtype=np.float64).copy()
+    rb = RestartedBroyden(st.mem, st.thetabar) if st.direction == "rb" else None
+    aa = Anderson(st.mem, st.aa_reg) if st.direction == "aa" else None
+    counts = dict(k0=0, k1=0, k2=0, km=0, backtracks=0)
+    history = []
+    eta0 = eta = r_safe = None
+    pend = None            # (z, Rw or None [= next R u], Ru_prev)
+    status, info, xys = 0, {}, None
+    nu = 0
+    for nu in range(st.max_iters + 1):
+        ut, ub, Ru = residual(lin, cone, u)                 # fresh solve every iteration
+        nRu = float(np.linalg.norm(Ru))
+        if nu == 0:
+            eta0 = eta = r_safe = nRu
+        status, info, xys = termination(lin, u, ut, ub, st.eps)
+        info["res_fp"] = nRu
+        if not math.isfinite(nRu):
+            status = NUMERICAL
+        if status:
+            break
+        if nu == st.max_iters:
+            status = MAX_ITERS
+            break
+        if time.perf_counter() - t0 > st.max_time:
+            status = TIME_LIMIT
+            break
+        # memory push of the previous pair (R5), then the direction
+        z = xi = None
+        if pend is not None:
+            zp, Rwp, Rup = pend
+            if float(np.linalg.norm(zp)) > 0:
+                z = zp
+                xi = (Ru if Rwp is None else Rwp) - Rup
+        if rb is not None:
+            d = rb.direction(Ru, z, xi)
+        elif aa is not None:
+            if z is not None:
+                aa.push(z, xi)
+            d = aa.direction(Ru)
+        elif st.direction == "zero":
+            d = np.zeros_like(Ru)
+        else:
+            d = -Ru
+        rec = dict(nu=nu, res=nRu, pr=info["pr"], dr=info["dr"], gap=info["gap"])
+        if nRu <= c0 * eta:                                  # K0
+            u_new = u + d
+            eta = nRu
+            pend = (d.copy(), None, Ru)                      # R2: w = u + d
+            counts["k0"] += 1
+            rec.update(kind="K0", ls=0)
+        else:
+            dt = lin.L(d)                                    # second linear solve
+            alpha = 1.0
+            done = False
+            for k in range(st.ls_max):
+                w = u + alpha * d
+                wt = ut + alpha * dt                         # linearity of (I+Q)^{-1}
+                Rw = wt - proj_C(2.0 * wt - w, n, cone)
+                nRw = float(np.linalg.norm(Rw))
+                rho = float(Rw @ (u - (w - Rw)))             # <Rw, u - Tw>
+                if nRu <= r_safe and nRw <= st.c1 * nRu:     # K1
+                    u_new = w
+                    r_safe = nRw + st.q ** nu * eta0         # R4
+                    counts["k1"] += 1
+                    rec.update(kind="K1", ls=k)
+                    done = True
+                elif rho >= st.sigma * nRu * nRw:            # K2
+                    u_new = u - st.lam * (rho / (nRw * nRw)) * Rw
+                    counts["k2"] += 1
+                    rec.update(kind="K2", ls=k)
+                    done = True
+                if done:
+                    pend = (w - u, Rw, Ru)
+                    break
+                alpha *= 0.5
+                counts["backtracks"] += 1
+            if not done:                                     # R3
+                u_new = u - st.lam * Ru
+                pend = (np.zeros_like(u), Ru, Ru)
+                counts["km"] += 1
+                rec.update(kind="KM", ls=st.ls_max)
+        if record:
+            history.append(rec)
+        u = u_new
+    x, y, s = xys
+    return Result(status=status, x=x, y=y, s=s, iters=nu, info=info, history=history,
+                  counts=counts, u=u, setup_s=setup_s, solve_s=time.perf_counter() - t0)

@@ -1,0 +1,276 @@
+"""Seeded synthetic conic programs shaped like the paper's workloads.
+
+This module builds problem data only: matrices, vectors and cone layouts for
+the standard form of Sec. III, problem (P): minimise <c, x> subject to
+b - A x = s, s in K.  It contains none of the solver's arithmetic (no linear
+steps, projections, directions or termination tests), so both the GPU
+library and the CPU oracle may consume its output.
+
+Cone layout of s and y (rows of A, b): zero | R+ | SOC ... | PSD ... | exp ...
+  * SOC blocks are (x, t) with t LAST (Sec. II, second-order cone).
+  * PSD blocks are the column-major lower triangle with off-diagonal entries
+    scaled by sqrt(2), the inverse of the paper's mat operator (Sec. II).
+  * exp blocks are (x1, x2, x3) with x1 >= x2 exp(x3 / x2) (Sec. II).
+
+Random streams: numpy PCG64 seeded with 1_000_000 * config + instance.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def rng_for(config: int, instance: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(1_000_000 * config + instance))
+
+
+@dataclasses.dataclass
+class Cone:
+    z: int = 0                       # zero-cone rows (equalities)
+    l: int = 0                       # nonnegative-orthant rows
+    q: List[int] = dataclasses.field(default_factory=list)   # SOC sizes
+    s: List[int] = dataclasses.field(default_factory=list)   # PSD orders
+    ep: int = 0                      # number of exponential cones
+
+    def rows(self) -> int:
+        return (self.z + self.l + sum(self.q)
+                + sum(k * (k + 1) // 2 for k in self.s) + 3 * self.ep)
+
+    def as_dict(self) -> Dict:
+        return dict(z=self.z, l=self.l, q=list(self.q), s=list(self.s), ep=self.ep)
+
+
+@dataclasses.dataclass
+class Problem:
+    A: sp.csr_matrix                 # m x n, float64, sorted indices
+    b: np.ndarray                    # m
+    c: np.ndarray                    # n
+    cone: Cone
+    name: str = ""
+    x_star: Optional[np.ndarray] = None   # planted primal solution, if any
+    y_star: Optional[np.ndarray] = None
+    s_star: Optional[np.ndarray] = None
+    meta: Dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+
+def _csr(A) -> sp.csr_matrix:
+    A = sp.csr_matrix(A, dtype=np.float64)
+    A.sum_duplicates()
+    A.sort_indices()
+    A.indptr = A.indptr.astype(np.int32)
+    A.indices = A.indices.astype(np.int32)
+    return A
+
+
+def sprandn(m: int, n: int, density: float, rng: np.random.Generator) -> sp.csr_matrix:
+    """m x n sparse matrix with the given density and N(0,1) nonzeros."""
+    A = sp.random(m, n, density=density, format="csr", random_state=rng,
+                  data_rvs=rng.standard_normal)
+    return _csr(A)
+
+
+# ---------------------------------------------------------------------------
+# Planted primal-dual optima (configs 1 and 2)
+# ---------------------------------------------------------------------------
+
+def _planted_soc_pair(k: int, rng: np.random.Generator):
+    """A complementary pair (s, y) on one second-order cone of size k (t last)."""
+    case = rng.integers(0, 3)
+    v = rng.standard_normal(k - 1)
+    nv = np.linalg.norm(v)
+    s = np.zeros(k)
+    y = np.zeros(k)
+    if case == 0:            # s interior, y = 0
+        s[:-1] = v
+        s[-1] = nv + abs(rng.standard_normal())
+    elif case == 1:          # s = 0, y interior
+        y[:-1] = v
+        y[-1] = nv + abs(rng.standard_normal())
+    else:                    # both on the boundary, opposite rays
+        e = v / nv if nv > 0 else np.eye(k - 1)[0]
+        a = abs(rng.standard_normal())
+        beta = abs(rng.standard_normal())
+        s[:-1] = a * e
+        s[-1] = a
+        y[:-1] = -beta * e
+        y[-1] = beta
+    return s, y
+
+
+def planted(A: sp.csr_matrix, cone: Cone, rng: np.random.Generator, name: str = "") -> Problem:
+    """Feasible (P)/(D) pair with a known optimum (x*, y*, s*): complementary
+    s* in K, y* in K* on every block, b = A x* + s*, c = -A^T y*."""
+    m, n = A.shape
+    assert cone.rows() == m
+    assert not cone.s and cone.ep == 0, "planted construction covers zero/R+/SOC"
+    x = rng.standard_normal(n)
+    s = np.zeros(m)
+    y = np.zeros(m)
+    o = 0
+    y[o:o + cone.z] = rng.standard_normal(cone.z)
+    o += cone.z
+    perm = rng.permutation(cone.l)
+    half = cone.l // 2
+    blk_s = np.zeros(cone.l)
+    blk_y = np.zeros(cone.l)
+    blk_s[perm[:half]] = np.abs(rng.standard_normal(half))
+    blk_y[perm[half:]] = np.abs(rng.standard_normal(cone.l - half))
+    s[o:o + cone.l] = blk_s
+    y[o:o + cone.l] = blk_y
+    o += cone.l
+    for k in cone.q:
+        s[o:o + k], y[o:o + k] = _planted_soc_pair(k, rng)
+        o += k
+    b = A @ x + s
+    c = -(A.T @ y)
+    return Problem(A=A, b=b, c=c, cone=cone, name=name, x_star=x, y_star=y, s_star=s)
+
+
+def config1_lp(instance: int = 0) -> Problem:
+    """Random feasible LP in conic form: m=300, n=100, 10% density, K = R+^300."""
+    rng = rng_for(1, instance)
+    A = sprandn(300, 100, 0.10, rng)
+    return planted(A, Cone(l=300), rng, name="lp_300x100")
+
+
+def soc_sizes(rem: int, rng: np.random.Generator, lo: int = 3, hi: int = 50) -> List[int]:
+    sizes = []
+    while rem > hi:
+        k = int(rng.integers(lo, min(hi, rem - lo) + 1))
+        sizes.append(k)
+        rem -= k
+    if rem > 0:
+        sizes.append(rem)
+    return sizes
+
+
+def config2_socp(instance: int = 0, n: int = 20000, m: int = 50000, density: float = 1e-3,
+                 nz: int = 1000, nl: int = 20000) -> Problem:
+    """Sparse SOCP: zero 1000 + R+ 20000 + SOC sizes U{3..50} filling the rest."""
+    rng = rng_for(2, instance)
+    A = sprandn(m, n, density, rng)
+    cone = Cone(z=nz, l=nl, q=soc_sizes(m - nz - nl, rng))
+    return planted(A, cone, rng, name=f"socp_{m}x{n}")
+
+
+def small_socp(seed: int, n: int = 60, m: int = 150, density: float = 0.08,
+               nz: int = 10, nl: int = 60) -> Problem:
+    """Config-2 recipe at a size the oracle solves in well under a second."""
+    rng = rng_for(20, seed)
+    A = sprandn(m, n, density, rng)
+    cone = Cone(z=nz, l=nl, q=soc_sizes(m - nz - nl, rng, 3, 12))
+    return planted(A, cone, rng, name=f"socp_small_{seed}")
+
+
+# ---------------------------------------------------------------------------
+# Tiny LPs for vertex enumeration, certificates
+# ---------------------------------------------------------------------------
+
+def tiny_lp(seed: int, n: int = 3, mg: int = 5, box: float = 2.0) -> Problem:
+    """min c^T x s.t. G x <= h, -box <= x <= box; conic rows [G; I; -I]."""
+    rng = rng_for(30, seed)
+    G = rng.standard_normal((mg, n))
+    xf = rng.uniform(-0.5, 0.5, n)
+    h = G @ xf + np.abs(rng.standard_normal(mg)) * 0.5
+    A = np.vstack([G, np.eye(n), -np.eye(n)])
+    b = np.concatenate([h, box * np.ones(n), box * np.ones(n)])
+    c = rng.standard_normal(n)
+    return Problem(A=_csr(A), b=b, c=c, cone=Cone(l=mg + 2 * n), name=f"tiny_lp_{seed}")
+
+
+def infeasible_lp(seed: int, n: int = 20, m: int = 50, density: float = 0.3) -> Problem:
+    """Primal-infeasible LP with certificate y0 >= 0, A^T y0 = 0, <b, y0> = -1."""
+    rng = rng_for(31, seed)
+    A = sprandn(m, n, density, rng).toarray()
+    y0 = np.abs(rng.standard_normal(m))
+    A = A - np.outer(y0, y0 @ A) / (y0 @ y0)
+    b = rng.standard_normal(m)
+    b = b - ((b @ y0 + 1.0) / (y0 @ y0)) * y0
+    c = rng.standard_normal(n)
+    return Problem(A=_csr(A), b=b, c=c, cone=Cone(l=m), name=f"infeasible_{seed}",
+                   meta=dict(y_cert=y0))
+
+
+def unbounded_lp(seed: int, n: int = 20, m: int = 50, density: float = 0.3) -> Problem:
+    """Dual-infeasible (unbounded) LP with ray x0: -A x0 = s0 in K, <c, x0> = -1."""
+    rng = rng_for(32, seed)
+    A = sprandn(m, n, density, rng).toarray()
+    x0 = rng.standard_normal(n)
+    s0 = np.abs(rng.standard_normal(m))
+    A = A - np.outer(A @ x0 + s0, x0) / (x0 @ x0)
+    c = rng.standard_normal(n)
+    c = c - ((c @ x0 + 1.0) / (x0 @ x0)) * x0
+    xf = rng.standard_normal(n)
+    sf = np.abs(rng.standard_normal(m))
+    b = A @ xf + sf
+    return Problem(A=_csr(A), b=b, c=c, cone=Cone(l=m), name=f"unbounded_{seed}",
+                   meta=dict(x_cert=x0))
+
+
+# ---------------------------------------------------------------------------
+# LASSO as an SOCP (Sec. V-C shape; configs 4 and 5)
+# ---------------------------------------------------------------------------
+
+def lasso_socp(Ad: sp.csr_matrix, bd: np.ndarray, mu: float, name: str = "") -> Problem:
+    """min 1/2 ||Ad x - bd||^2 + mu ||x||_1 as a cone program in z = (x, r, t).
+
+    min mu 1^T r + t/2 s.t. r - x >= 0, r + x >= 0 (R+ 2n) and
+    (Ad x - bd, (t-1)/2, (t+1)/2) in SOC of size md + 2 (t last), which
+    encodes ||Ad x - bd||^2 <= t."""
+    md, n = Ad.shape
+    I = sp.identity(n, format="csr")
+    Z = sp.csr_matrix((n, 1))
+    top = sp.hstack([I, -I, Z])                        # s = r - x
+    mid = sp.hstack([-I, -I, Z])                       # s = r + x
+    soc = sp.hstack([-Ad, sp.csr_matrix((md, n)), sp.csr_matrix((md, 1))])
+    tail = sp.csr_matrix(np.array([[0.0] * (2 * n) + [-0.5], [0.0] * (2 * n) + [-0.5]]))
+    A = _csr(sp.vstack([top, mid, soc, tail]))
+    b = np.concatenate([np.zeros(2 * n), -bd, [-0.5, 0.5]])
+    c = np.concatenate([np.zeros(n), mu * np.ones(n), [0.5]])
+    return Problem(A=A, b=b, c=c, cone=Cone(l=2 * n, q=[md + 2]), name=name,
+                   meta=dict(Ad=Ad, bd=bd, mu=mu, n_data=n, m_data=md))
+
+
+def lasso_data(rng: np.random.Generator, md: int, n: int, density: float,
+               A: Optional[sp.csr_matrix] = None):
+    if A is None:
+        A = sprandn(md, n, density, rng)
+    x0 = np.zeros(n)
+    k = max(1, int(round(0.1 * n)))
+    idx = rng.choice(n, size=k, replace=False)
+    x0[idx] = rng.standard_normal(k)
+    b = A @ x0 + 0.05 * rng.standard_normal(md)
+    mu = 0.1 * float(np.max(np.abs(A.T @ b)))
+    return A, b, mu
+
+
+def config4_instance(i: int) -> Problem:
+    """One instance of the batched LASSO family: n ~ U{20..400}, m ~ U{ceil(n/2)..2n}."""
+    rng = rng_for(4, i)
+    n = int(rng.integers(20, 401))
+    md = int(rng.integers(math.ceil(n / 2), 2 * n + 1))
+    A, b, mu = lasso_data(rng, md, n, 0.05)
+    return lasso_socp(A, b, mu, name=f"lasso4_{i}")
+
+
+def config5_shared_A() -> sp.csr_matrix:
+    return sprandn(2000, 1000, 0.02, rng_for(5, 10**6 - 1))
+
+
+def config5_instance(i: int, A: sp.csr_matrix) -> Problem:
+    """Instance i of the shared-A LASSO family (only bd and mu vary)."""
+    rng = rng_for(5, i)
+    A, b, mu = lasso_data(rng, A.shape[0], A.shape[1], 0.0, A=A)
+    return lasso_socp(A, b, mu, name=f"lasso5_{i}")

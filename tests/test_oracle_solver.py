@@ -1,0 +1,309 @@
+"""Pins of the oracle's linear step, T-oracle, directions and Algorithm 1
+against identities, textbook routines, brute force and closed-form optima."""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import cones as C
+from oracle.linsys import DirectLinSys, Q_dense
+from oracle import superscs as S
+from paper_1903_06477_amd import generators as G
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _prob_from_json(d):
+    A = sp.csr_matrix(np.array(d["A"], dtype=float))
+    cone = G.Cone(**d["cone"])
+    return G.Problem(A=A, b=np.array(d["b"], float), c=np.array(d["c"], float), cone=cone)
+
+
+# ------------------------------------------------------------ HSDE matrix, linear step
+
+@pytest.mark.parametrize("m,n", [(12, 5), (5, 12), (30, 30)])
+def test_Q_skew_and_orthogonal(m, n):
+    r = np.random.default_rng(m * 100 + n)
+    A = r.standard_normal((m, n))
+    Q = Q_dense(A, r.standard_normal(m), r.standard_normal(n))
+    np.testing.assert_array_equal(Q + Q.T, 0)
+    for _ in range(10):
+        u = r.standard_normal(m + n + 1)
+        assert abs(u @ Q @ u) <= 1e-12 * (u @ u) * np.abs(Q).max()
+
+
+@pytest.mark.parametrize("m,n,density", [(40, 15, 0.3), (15, 40, 0.3), (300, 100, 0.1), (120, 120, 0.05)])
+def test_linear_step_against_dense_solve(m, n, density):
+    r = G.rng_for(99, m + n)
+    A = G.sprandn(m, n, density, r)
+    b = r.standard_normal(m)
+    c = r.standard_normal(n)
+    lin = DirectLinSys(A, b, c)
+    assert lin.delta >= 1.0
+    IQ = np.eye(m + n + 1) + Q_dense(A, b, c)
+    for _ in range(5):
+        rhs = r.standard_normal(m + n + 1)
+        x = lin.L(rhs)
+        np.testing.assert_allclose(x, np.linalg.solve(IQ, rhs), rtol=1e-11, atol=1e-12)
+        assert np.linalg.norm(IQ @ x - rhs) <= 1e-13 * np.linalg.norm(rhs) * np.linalg.norm(IQ, 2)
+
+
+def test_linear_step_sparse_factor_path():
+    r = G.rng_for(98, 0)
+    A = G.sprandn(400, 300, 0.004, r)
+    b = r.standard_normal(400)
+    c = r.standard_normal(300)
+    lin_s = DirectLinSys(A, b, c, dense_limit=0)
+    assert lin_s.kind == "sparse"
+    IQ = np.eye(701) + Q_dense(A, b, c)
+    rhs = r.standard_normal(701)
+    np.testing.assert_allclose(lin_s.L(rhs), np.linalg.solve(IQ, rhs), rtol=1e-10, atol=1e-11)
+
+
+# ------------------------------------------------------------ T and R
+
+def _lin_and_cone(seed=0):
+    p = G.small_socp(seed)
+    return p, DirectLinSys(p.A, p.b, p.c)
+
+
+def T_op(lin, cone, u):
+    ut, ub, Ru = S.residual(lin, cone, u)
+    return u - Ru
+
+
+def test_T_firmly_nonexpansive_and_homogeneous():
+    p, lin = _lin_and_cone(1)
+    r = np.random.default_rng(5)
+    N = p.n + p.m + 1
+    for _ in range(20):
+        u, v = r.standard_normal(N), r.standard_normal(N)
+        Tu, Tv = T_op(lin, p.cone, u), T_op(lin, p.cone, v)
+        dT = Tu - Tv
+        assert dT @ dT <= dT @ (u - v) + 1e-10 * (1 + (u - v) @ (u - v))
+        np.testing.assert_allclose(T_op(lin, p.cone, 2 * u), 2 * Tu, rtol=1e-12, atol=1e-12)
+
+
+def test_planted_fixed_point():
+    p, lin = _lin_and_cone(2)
+    u_star = np.concatenate([p.x_star, p.y_star + p.s_star, [1.0]])
+    ut, ub, Ru = S.residual(lin, p.cone, u_star)
+    assert np.linalg.norm(Ru) <= 1e-12 * np.linalg.norm(u_star)
+    res = S.solve(p, S.Settings(eps=1e-9), u0=u_star, lin=lin)
+    assert res.status == S.SOLVED and res.iters == 0
+    np.testing.assert_allclose(res.x, p.x_star, atol=1e-9)
+
+
+# ------------------------------------------------------------ directions
+
+def test_restarted_broyden_matches_dense_sherman_morrison():
+    # Product form of Algorithm 2 against the dense inverse update of Sec. IV-D-1:
+    # H+ = H + (z - H xi~)(z^T H) / <H xi~, z>,  xi~ = (1 - theta) B z + theta xi.
+    r = np.random.default_rng(8)
+    N, mem, thb = 12, 4, 0.3
+    rb = S.RestartedBroyden(mem, thb)
+    H = np.eye(N)
+    for it in range(9):
+        z = r.standard_normal(N)
+        xi = r.standard_normal(N) if it % 3 else 0.05 * r.standard_normal(N)   # small xi: Powell damping on
+        res = r.standard_normal(N)
+        if it and len(rb.Z) == 0:
+            H = np.eye(N)
+        B = np.linalg.inv(H)
+        gamma = (H @ xi) @ z / (z @ z)
+        theta = 1.0 if abs(gamma) >= thb else (1 - (1 if gamma >= 0 else -1) * thb) / (1 - gamma)
+        xit = (1 - theta) * (B @ z) + theta * xi
+        Hx = H @ xit
+        H_new = H + np.outer(z - Hx, z @ H) / (Hx @ z)
+        np.testing.assert_allclose(H_new @ xit, z, rtol=1e-9, atol=1e-9)         # secant condition
+        assert abs(Hx @ z) >= thb * (z @ z) * (1 - 1e-9) or theta == 1.0           # Powell safeguard
+        restart = len(rb.Z) == mem
+        d = rb.direction(res, z, xi)
+        np.testing.assert_allclose(d, -H_new @ res, rtol=1e-9, atol=1e-9)
+        H = H_new
+        if restart:
+            # buffers now hold only the current factor (I + zt z^T)
+            zt = rb.Zt[0]
+            H = np.eye(N) + np.outer(zt, rb.Z[0])
+
+
+def test_anderson_matches_lstsq():
+    r = np.random.default_rng(9)
+    N = 40
+    aa = S.Anderson(5, reg=0.0)
+    for _ in range(7):
+        aa.push(r.standard_normal(N), r.standard_normal(N))
+    res = r.standard_normal(N)
+    t = aa.coefficients(res)
+    Xi = np.stack(aa.Xi, axis=1)
+    np.testing.assert_allclose(t, np.linalg.lstsq(Xi, res, rcond=None)[0], rtol=1e-9)
+    Z = np.stack(aa.Z, axis=1)
+    np.testing.assert_allclose(aa.direction(res), -res - (Z - Xi) @ t, rtol=1e-9)
+    assert len(aa.Z) == 5                               # FIFO memory of the last pairs
+
+
+# ------------------------------------------------------------ Algorithm 1 special cases
+
+def test_zero_direction_is_plain_drs():
+    # d = 0 and c0 = 0: every step is K2 at alpha = 1 with w = u, i.e. u+ = u - R u = T u.
+    p, lin = _lin_and_cone(3)
+    st = S.Settings(direction="zero", c0=0.0, lam=1.0, max_iters=25, eps=1e-14)
+    res = S.solve(p, st, lin=lin)
+    u = np.zeros(p.n + p.m + 1); u[-1] = 1.0
+    for _ in range(25):
+        ut = lin.L(u)
+        u = u + C.proj_C(2 * ut - u, p.n, p.cone) - ut              # equation (drs)
+    np.testing.assert_allclose(res.u, u, rtol=1e-12, atol=1e-13)
+    assert res.counts["k2"] == 25
+
+
+# ------------------------------------------------------------ whole solves
+
+def test_closed_form_golden():
+    d = json.load(open(os.path.join(HERE, "golden", "closed_form.json")))
+    for key, v in d.items():
+        if key.startswith("_"):
+            continue
+        p = _prob_from_json(v)
+        for direction, mem in [("aa", 5), ("rb", 10)]:
+            res = S.solve(p, S.Settings(eps=1e-9, direction=direction, mem=mem, max_iters=20000))
+            assert res.status == S.SOLVED, (key, direction)
+            np.testing.assert_allclose(res.x, v["x"], atol=1e-6)
+            assert abs(res.info["pobj"] - v["pobj"]) <= 1e-7 * (1 + abs(v["pobj"]))
+            if key != "eq_box":        # unique duals
+                np.testing.assert_allclose(res.y, v["y"], atol=1e-6)
+
+
+def _vertex_enumeration(p):
+    A = p.A.toarray()
+    m, n = A.shape
+    best = math.inf
+    for S_ in itertools.combinations(range(m), n):
+        As = A[list(S_)]
+        if abs(np.linalg.det(As)) < 1e-10:
+            continue
+        x = np.linalg.solve(As, p.b[list(S_)])
+        if np.all(A @ x <= p.b + 1e-9):
+            best = min(best, p.c @ x)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tiny_lp_vertex_enumeration(seed):
+    p = G.tiny_lp(seed, n=3 + seed % 2, mg=5 + seed % 3)
+    ref = _vertex_enumeration(p)
+    res = S.solve(p, S.Settings(eps=1e-9, direction="aa", mem=5, max_iters=50000))
+    assert res.status == S.SOLVED
+    assert abs(res.info["pobj"] - ref) <= 1e-6 * (1 + abs(ref))
+
+
+def _kkt_errors(p, x, y, s):
+    from oracle.cones import proj_dual_cone
+    A = p.A
+    pr = np.linalg.norm(A @ x + s - p.b) / (1 + np.linalg.norm(p.b))
+    dr = np.linalg.norm(A.T @ y + p.c) / (1 + np.linalg.norm(p.c))
+    ydist = np.linalg.norm(y - proj_dual_cone(y, p.cone))
+    # s in K: for cones without exp blocks K = K* up to the zero block (K = {0} there)
+    return pr, dr, ydist
+
+
+def test_config1_lp_planted():
+    p = G.config1_lp()
+    for st in [S.Settings(direction="rb", mem=10), S.Settings(direction="aa", mem=5)]:
+        res = S.solve(p, st)
+        assert res.status == S.SOLVED
+        pstar = p.c @ p.x_star
+        assert abs(res.info["pobj"] - pstar) <= 1e-5 * (1 + abs(pstar))
+        pr, dr, ydist = _kkt_errors(p, res.x, res.y, res.s)
+        assert pr <= 1e-6 and dr <= 1e-6 and ydist <= 1e-9
+        assert np.all(res.s >= -1e-9)
+        # x* unique: the active rows of the planted point have full column rank
+        act = p.s_star < 1e-12
+        assert np.linalg.matrix_rank(p.A.toarray()[act]) == p.n
+        assert np.linalg.norm(res.x - p.x_star) <= 1e-3 * np.linalg.norm(p.x_star)
+
+
+def test_small_socp_planted():
+    p = G.small_socp(0)
+    res = S.solve(p, S.Settings(direction="aa", mem=10, max_iters=5000))
+    assert res.status == S.SOLVED
+    pstar = p.c @ p.x_star
+    assert abs(res.info["pobj"] - pstar) <= 1e-5 * (1 + abs(pstar))
+    # s in K (zero rows are 0, R+ rows >= 0, SOC blocks inside)
+    o = p.cone.z
+    assert np.abs(res.s[:o]).max() <= 1e-6 * (1 + np.linalg.norm(p.b))
+    assert res.s[o:o + p.cone.l].min() >= -1e-9
+    o += p.cone.l
+    for k in p.cone.q:
+        blk = res.s[o:o + k]
+        assert np.linalg.norm(blk[:-1]) <= blk[-1] + 1e-8
+        o += k
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_infeasible_certificate(seed):
+    p = G.infeasible_lp(seed)
+    res = S.solve(p, S.Settings(eps=1e-7))
+    assert res.status == S.INFEASIBLE
+    y = res.y
+    assert abs(p.b @ y + 1) <= 1e-10
+    assert np.linalg.norm(p.A.T @ y) <= 1e-6 * np.linalg.norm(y) * np.linalg.norm(p.b) * 10
+    assert y.min() >= -1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_unbounded_certificate(seed):
+    p = G.unbounded_lp(seed)
+    res = S.solve(p, S.Settings(eps=1e-7))
+    assert res.status == S.UNBOUNDED
+    x, s = res.x, res.s
+    assert abs(p.c @ x + 1) <= 1e-10
+    assert np.linalg.norm(p.A @ x + s) <= 1e-6 * np.linalg.norm(x) * np.linalg.norm(p.c) * 10
+    assert s.min() >= -1e-12
+
+
+def _lasso_fista(Ad, bd, mu, iters=200000, tol=1e-13):
+    A = Ad.toarray()
+    L = np.linalg.norm(A, 2) ** 2
+    x = np.zeros(A.shape[1]); yk = x.copy(); t = 1.0
+    for _ in range(iters):
+        g = A.T @ (A @ yk - bd)
+        xn = yk - g / L
+        xn = np.sign(xn) * np.maximum(np.abs(xn) - mu / L, 0)
+        tn = (1 + math.sqrt(1 + 4 * t * t)) / 2
+        yk = xn + ((t - 1) / tn) * (xn - x)
+        if np.linalg.norm(xn - x) <= tol * (1 + np.linalg.norm(x)):
+            x = xn
+            break
+        x, t = xn, tn
+    return x, 0.5 * np.sum((A @ x - bd) ** 2) + mu * np.abs(x).sum()
+
+
+@pytest.mark.parametrize("i", [0, 1])
+def test_lasso_socp_matches_fista(i):
+    p = G.config4_instance(i)
+    Ad, bd, mu = p.meta["Ad"], p.meta["bd"], p.meta["mu"]
+    _, fref = _lasso_fista(Ad, bd, mu)
+    res = S.solve(p, S.Settings(eps=1e-8, direction="aa", mem=5, max_iters=20000))
+    assert res.status == S.SOLVED
+    n = p.meta["n_data"]
+    x = res.x[:n]
+    f = 0.5 * np.sum((Ad @ x - bd) ** 2) + mu * np.abs(x).sum()
+    assert abs(f - fref) <= 1e-6 * (1 + abs(fref))
+    assert abs(res.info["pobj"] - fref) <= 1e-6 * (1 + abs(fref))
+
+
+def test_status_limits():
+    p = G.config1_lp()
+    res = S.solve(p, S.Settings(max_iters=1))
+    assert res.status == S.MAX_ITERS
+    res = S.solve(p, S.Settings(max_time=0.0))
+    assert res.status == S.TIME_LIMIT
+    bad = G.config1_lp()
+    bad.b = bad.b.copy(); bad.b[0] = np.nan
+    res = S.solve(bad, S.Settings(max_iters=5))
+    assert res.status == S.NUMERICAL

@@ -1,0 +1,330 @@
+// Projections onto the dual cone K* (Sec. II cones; projection step of
+// equation (drs), Sec. IV-A) as one team-wide streaming pass.
+//
+// project_C(tm, P, in, emit) evaluates u-bar = Pi_C(p) for C = R^n x K* x R+
+// where in(i) returns p_i for the state index i in [0, N) and emit(i, v)
+// receives u-bar_i.  Every index is emitted exactly once, by the thread that
+// owns its block:
+//   x part, zero rows (dual = free), R+ rows, tau     one thread per entry
+//   second-order cones (t last)                       one wavefront per cone
+//   exponential cones                                  one thread per cone
+//   PSD blocks                                         one workgroup per block
+#pragma once
+#include <float.h>
+
+#include "dev_common.h"
+
+namespace sscs {
+
+struct ConeDev {
+    int z, l;                 // zero and R+ row counts
+    int nq;                   // SOC count; qoff[nq + 1] row offsets inside the SOC region
+    const int* qoff;
+    int ns;                   // PSD count; sord[ns] orders, soff[ns + 1] offsets in the PSD region
+    const int* sord;
+    const int* soff;
+    int ep;                   // exponential cones
+    int soc0, psd0, exp0;     // first row of each region (relative to the start of y)
+    double* psd_scratch;      // per-workgroup scratch for PSD blocks (k*k + k doubles each)
+    int psd_kmax;
+};
+
+// ---------------------------------------------------------------- exponential cone
+//
+// K_e = cl{(x1, x2, x3): x1 >= x2 exp(x3 / x2), x2 > 0}.  For v0 outside K_e
+// and outside its polar, the projection is p = s (e^rho, 1, rho) with s > 0 and
+// v0 - p = beta (-1, e^rho (1 - rho), e^rho), beta > 0 (the outward normal at p).
+// Eliminating s and beta leaves a scalar equation in rho (the formulation of
+// Friberg, "Projection onto the exponential cone: a univariate root-finding
+// problem"); it is solved here by a bracketed Illinois iteration.
+
+__device__ __forceinline__ double exp_h_scaled(double rho, double t0, double s0, double r0) {
+    // h(rho) = ((rho-1) r0 + s0) e^rho - (r0 - rho s0) e^-rho - (rho^2 - rho + 1) t0,
+    // multiplied by e^-|rho| (same sign, no overflow).
+    const double q = rho * (rho - 1.0) + 1.0;
+    if (rho >= 0.0)
+        return ((rho - 1.0) * r0 + s0) - (r0 - rho * s0) * exp(-2.0 * rho) - q * t0 * exp(-rho);
+    return ((rho - 1.0) * r0 + s0) * exp(2.0 * rho) - (r0 - rho * s0) - q * t0 * exp(rho);
+}
+
+__device__ inline void proj_exp_primal(double t0, double s0, double r0, double* p) {
+    const double eps = DBL_EPSILON;
+    // inside K_e (points within rounding of the boundary count as inside)
+    if (s0 > 0.0) {
+        const double e = r0 / s0;
+        const double g = (e < 700.0) ? s0 * exp(e) : INFINITY;
+        if (t0 - g >= -4.0 * eps * fmax(fabs(t0), g)) { p[0] = t0; p[1] = s0; p[2] = r0; return; }
+    } else if (s0 == 0.0 && t0 >= 0.0 && r0 <= 0.0) {
+        p[0] = t0; p[1] = s0; p[2] = r0; return;
+    }
+    // inside the polar cone -K_e*: projection is the apex
+    if (r0 > 0.0) {
+        const double e = s0 / r0;
+        if (e < 700.0 && r0 * exp(e) <= -M_E * t0) { p[0] = p[1] = p[2] = 0.0; return; }
+    } else if (r0 == 0.0 && t0 <= 0.0 && s0 <= 0.0) {
+        p[0] = p[1] = p[2] = 0.0; return;
+    }
+    // x2 <= 0 and x3 <= 0: nearest point of the face {x2 = 0, x1 >= 0, x3 <= 0}
+    if (r0 <= 0.0 && s0 <= 0.0) { p[0] = fmax(t0, 0.0); p[1] = 0.0; p[2] = r0; return; }
+    // boundary case: both multipliers positive confine rho to an interval on
+    // which h goes from negative to positive
+    double lo, hi;
+    if (s0 > 0.0 && r0 > 0.0) { lo = 1.0 - s0 / r0; hi = r0 / s0; }
+    else if (s0 > 0.0) {
+        hi = r0 / s0;
+        double step = 1.0;
+        lo = hi - step;
+        for (int k = 0; k < 80 && exp_h_scaled(lo, t0, s0, r0) > 0.0; ++k) { step *= 2.0; lo = hi - step; }
+    } else {
+        lo = 1.0 - s0 / r0;
+        double step = 1.0;
+        hi = lo + step;
+        for (int k = 0; k < 80 && exp_h_scaled(hi, t0, s0, r0) < 0.0; ++k) { step *= 2.0; hi = lo + step; }
+    }
+    double fa = exp_h_scaled(lo, t0, s0, r0), fb = exp_h_scaled(hi, t0, s0, r0);
+    double rho;
+    if (fa >= 0.0) rho = lo;
+    else if (fb <= 0.0) rho = hi;
+    else {
+        double a = lo, b = hi;
+        int side = 0;
+        rho = 0.5 * (a + b);
+        for (int it = 0; it < 200; ++it) {
+            double c = (a * fb - b * fa) / (fb - fa);
+            if (!(c > a && c < b)) c = 0.5 * (a + b);
+            const double fc = exp_h_scaled(c, t0, s0, r0);
+            rho = c;
+            if (fc == 0.0) break;
+            if ((fc < 0.0) == (fa < 0.0)) {
+                a = c; fa = fc;
+                if (side == -1) fb *= 0.5;
+                side = -1;
+            } else {
+                b = c; fb = fc;
+                if (side == 1) fa *= 0.5;
+                side = 1;
+            }
+            if (b - a <= 4.0 * eps * fmax(1.0, fabs(c))) { rho = 0.5 * (a + b); break; }
+        }
+    }
+    // recover the point by the better conditioned of the two equivalent formulas
+    const double qq = rho * rho - rho + 1.0;
+    const double num_p = s0 + (rho - 1.0) * r0;     // s * qq
+    const double num_d = r0 - rho * s0;             // beta e^rho * qq
+    const double vmax = fmax(fabs(t0), fmax(fabs(s0), fabs(r0)));
+    const double na = sqrt(1.0 + rho * rho + (rho < 350.0 ? exp(2.0 * rho) : INFINITY));
+    const double err_p = eps * (fabs(s0) + fabs((rho - 1.0) * r0)) / qq * na;
+    const double nns = sqrt((rho > -350.0 ? exp(-2.0 * rho) : INFINITY) + 1.0 + (1.0 - rho) * (1.0 - rho));
+    const double err_d = eps * (fabs(r0) + fabs(rho * s0)) / qq * nns + eps * vmax;
+    double c0, c1, c2;
+    if (err_p <= err_d) {
+        const double s = num_p / qq;
+        c0 = (s > 0.0) ? exp(log(s) + rho) : 0.0;
+        c1 = s;
+        c2 = s * rho;
+    } else {
+        const double bexp = num_d / qq;
+        const double beta = bexp * exp(-rho);
+        c0 = t0 + beta;
+        c1 = s0 - bexp * (1.0 - rho);
+        c2 = r0 - bexp;
+    }
+    // keep the nearest of the boundary point, the face point and the apex
+    const double f0 = fmax(t0, 0.0), f2 = fmin(r0, 0.0);
+    const double d_c = (c0 - t0) * (c0 - t0) + (c1 - s0) * (c1 - s0) + (c2 - r0) * (c2 - r0);
+    const double d_f = (f0 - t0) * (f0 - t0) + s0 * s0 + (f2 - r0) * (f2 - r0);
+    const double d_0 = t0 * t0 + s0 * s0 + r0 * r0;
+    if (d_c <= d_f && d_c <= d_0) { p[0] = c0; p[1] = c1; p[2] = c2; }
+    else if (d_f <= d_0) { p[0] = f0; p[1] = 0.0; p[2] = f2; }
+    else { p[0] = p[1] = p[2] = 0.0; }
+}
+
+// Pi_{K_e*}(v) = v + Pi_{K_e}(-v) (Moreau decomposition with the polar cone -K_e*).
+__device__ inline void proj_exp_dual(const double* v, double* out) {
+    double p[3];
+    proj_exp_primal(-v[0], -v[1], -v[2], p);
+    out[0] = v[0] + p[0];
+    out[1] = v[1] + p[1];
+    out[2] = v[2] + p[2];
+}
+
+// ---------------------------------------------------------------- PSD blocks
+//
+// Pi of a PSD block: mat(x) = V diag(lam) V^T, keep max(lam, 0), back to the
+// packed layout.  The eigendecomposition is a cyclic two-sided Jacobi method
+// run by one workgroup on the k x k matrix held in `a` (k*k doubles, global
+// scratch private to the workgroup) with the eigenvector matrix in `vm`:
+// each sweep visits every pair (p, q) once in round-robin order, k/2 disjoint
+// rotations per round in parallel.
+template <typename Team>
+__device__ void psd_project_block(Team& tm, int k, double* a, double* vm, const double* in, double* outv) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    const double rs2 = 0.70710678118654752440;
+    // unpack: column-major lower triangle, off-diagonals scaled by sqrt(2)
+    for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
+        // column j holds k - j entries starting at off(j) = j k - j (j - 1) / 2
+        int j = 0, off = 0;
+        while (off + (k - j) <= idx) { off += k - j; ++j; }
+        const int i = j + (idx - off);
+        const double v = in[idx];
+        if (i == j) a[i * k + i] = v;
+        else { a[i * k + j] = v * rs2; a[j * k + i] = v * rs2; }
+    }
+    for (int idx = t; idx < k * k; idx += nt) vm[idx] = ((idx / k) == (idx % k)) ? 1.0 : 0.0;
+    __syncthreads();
+    if (k > 1) {
+        const int kk = (k & 1) ? k + 1 : k;   // pad to even with a dummy index
+        __shared__ double cs[512], sn[512];
+        __shared__ int pp[512], qq[512];
+        __shared__ double offn;
+        for (int sweep = 0; sweep < 30; ++sweep) {
+            // off-diagonal Frobenius norm relative to the whole matrix
+            {
+                __shared__ double red2[2 * NWMAX];
+                double off = 0.0, tot = 0.0;
+                for (int idx = t; idx < k * k; idx += nt) {
+                    const double v = a[idx] * a[idx];
+                    tot += v;
+                    if ((idx / k) != (idx % k)) off += v;
+                }
+                off = wave_sum(off);
+                tot = wave_sum(tot);
+                if ((t & (WAVE - 1)) == 0) { red2[t / WAVE] = off; red2[NWMAX + t / WAVE] = tot; }
+                __syncthreads();
+                if (t == 0) {
+                    double so = 0.0, st = 0.0;
+                    for (int w = 0; w < nt / WAVE; ++w) { so += red2[w]; st += red2[NWMAX + w]; }
+                    offn = (st > 0.0) ? so / st : 0.0;
+                }
+                __syncthreads();
+            }
+            if (offn <= 1e-30) break;
+            for (int round = 0; round < kk - 1; ++round) {
+                // round-robin pairing: position 0 fixed, others rotate
+                for (int h = t; h < kk / 2; h += nt) {
+                    int x = (h == 0) ? 0 : 1 + ((h - 1 + round) % (kk - 1));
+                    int y = 1 + ((kk - 2 - h + round) % (kk - 1));
+                    int p = x < y ? x : y, q = x < y ? y : x;
+                    double c = 1.0, s = 0.0;
+                    if (q < k) {
+                        const double apq = a[p * k + q];
+                        if (apq != 0.0) {
+                            const double app = a[p * k + p], aqq = a[q * k + q];
+                            const double tau = (aqq - app) / (2.0 * apq);
+                            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                            c = 1.0 / sqrt(1.0 + tt * tt);
+                            s = tt * c;
+                        }
+                    }
+                    pp[h] = p; qq[h] = q; cs[h] = c; sn[h] = s;
+                }
+                __syncthreads();
+                // A <- J^T A: rows p, q
+                for (int idx = t; idx < (kk / 2) * k; idx += nt) {
+                    const int h = idx / k, j = idx % k;
+                    const int p = pp[h], q = qq[h];
+                    if (q >= k) continue;
+                    const double c = cs[h], s = sn[h];
+                    const double ap = a[p * k + j], aq = a[q * k + j];
+                    a[p * k + j] = c * ap - s * aq;
+                    a[q * k + j] = s * ap + c * aq;
+                }
+                __syncthreads();
+                // A <- A J and V <- V J: columns p, q
+                for (int idx = t; idx < (kk / 2) * k; idx += nt) {
+                    const int h = idx / k, i = idx % k;
+                    const int p = pp[h], q = qq[h];
+                    if (q >= k) continue;
+                    const double c = cs[h], s = sn[h];
+                    const double ap = a[i * k + p], aq = a[i * k + q];
+                    a[i * k + p] = c * ap - s * aq;
+                    a[i * k + q] = s * ap + c * aq;
+                    const double vp = vm[i * k + p], vq = vm[i * k + q];
+                    vm[i * k + p] = c * vp - s * vq;
+                    vm[i * k + q] = s * vp + c * vq;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // reconstruct V max(lam, 0) V^T in packed form
+    for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
+        int j = 0, off = 0;
+        while (off + (k - j) <= idx) { off += k - j; ++j; }
+        const int i = j + (idx - off);
+        double s = 0.0;
+        for (int e = 0; e < k; ++e) {
+            const double lam = a[e * k + e];
+            if (lam > 0.0) s += vm[i * k + e] * lam * vm[j * k + e];
+        }
+        outv[idx] = (i == j) ? s : s * 1.41421356237309504880;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- Pi_C pass
+
+template <typename Team, typename In, typename Emit>
+__device__ __forceinline__ void project_C(Team& tm, int n, int N, const ConeDev& K, double* psd_in,
+                                          double* psd_out, In&& in, Emit&& emit) {
+    // elementwise part: x, zero rows, R+ rows, tau
+    const int nel = n + K.z + K.l;
+    for (int i = tm.rank(); i <= nel; i += tm.size()) {
+        const int gi = (i < nel) ? i : N - 1;
+        double v = in(gi);
+        if (gi >= n + K.z) v = fmax(v, 0.0);
+        emit(gi, v);
+    }
+    // second-order cones, t last: one wavefront per cone
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (int c = tm.wave(); c < K.nq; c += tm.nwaves()) {
+        const int o = n + K.soc0 + K.qoff[c];
+        const int k = K.qoff[c + 1] - K.qoff[c];
+        double ss = 0.0;
+        for (int e = lane; e < k - 1; e += WAVE) { const double v = in(o + e); ss += v * v; }
+        ss = wave_sum(ss);
+        const double nx = sqrt(ss);
+        const double t = in(o + k - 1);
+        if (nx <= t) {
+            for (int e = lane; e < k; e += WAVE) emit(o + e, in(o + e));
+        } else if (nx <= -t) {
+            for (int e = lane; e < k; e += WAVE) emit(o + e, 0.0);
+        } else {
+            const double a = 0.5 * (nx + t), sc = a / nx;
+            for (int e = lane; e < k - 1; e += WAVE) emit(o + e, sc * in(o + e));
+            if (lane == 0) emit(o + k - 1, a);
+        }
+    }
+    // exponential cones: one thread per cone
+    for (int c = tm.rank(); c < K.ep; c += tm.size()) {
+        const int o = n + K.exp0 + 3 * c;
+        double v[3] = {in(o), in(o + 1), in(o + 2)}, p[3];
+        proj_exp_dual(v, p);
+        emit(o, p[0]);
+        emit(o + 1, p[1]);
+        emit(o + 2, p[2]);
+    }
+    // PSD blocks: one workgroup per block (the whole workgroup takes the loop
+    // together, so the barriers inside are uniform)
+    if (K.ns > 0) {
+        double* a = K.psd_scratch + (size_t)tm.blk() * (2 * (size_t)K.psd_kmax * K.psd_kmax +
+                                                        (size_t)K.psd_kmax * (K.psd_kmax + 1));
+        double* vm = a + (size_t)K.psd_kmax * K.psd_kmax;
+        double* pin = vm + (size_t)K.psd_kmax * K.psd_kmax;
+        double* pout = pin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
+        for (int c = tm.blk(); c < K.ns; c += tm.nblk()) {
+            const int k = K.sord[c];
+            const int o = n + K.psd0 + K.soff[c];
+            const int len = k * (k + 1) / 2;
+            for (int e = threadIdx.x; e < len; e += blockDim.x) pin[e] = in(o + e);
+            __syncthreads();
+            psd_project_block(tm, k, a, vm, pin, pout);
+            for (int e = threadIdx.x; e < len; e += blockDim.x) emit(o + e, pout[e]);
+            __syncthreads();
+        }
+    }
+    (void)psd_in;
+    (void)psd_out;
+}
+
+}  // namespace sscs

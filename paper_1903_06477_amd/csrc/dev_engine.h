@@ -1,0 +1,664 @@
+// SuperSCS engine on the device, written once for any team (dev_common.h).
+//
+//   linear_step   u~ = (I + Q)^{-1} r, equation (drs) first line, by block
+//                 elimination to (I + A^T A) px = rx - A^T ry, Jacobi-
+//                 preconditioned CG, py = ry + A px, then the rank-one tau
+//                 correction with g = M^{-1} (c, b) and delta = 1 + (c, b)^T g.
+//   residual      u-bar = Pi_C(2 u~ - u), R u = u~ - u-bar  (equation (drs), R = I - T)
+//   termination   pr, dr, gap, ic, uc of Sec. IV-C from (u, u~, u-bar)
+//   directions    Anderson (Sec. IV-D-2) and restarted Broyden (Algorithm 2)
+//   line search   w = u + a d, w~ = u~ + a d~ (linearity of (I+Q)^{-1}, Sec. IV-B),
+//                 Rw = w~ - Pi_C(2 w~ - w), K1 / K2 tests of Algorithm 1
+//   solve         Algorithm 1
+//
+// All scalar control (CG recurrences, step decisions, Gram solves) is FP64 and
+// is computed identically by every thread from deterministic team reductions,
+// so no decision ever diverges across the team and no host round trip sits
+// inside an iteration.
+#pragma once
+#include "dev_common.h"
+#include "dev_cones.h"
+
+namespace sscs {
+
+enum { ST_SOLVED = 1, ST_INFEASIBLE = 2, ST_UNBOUNDED = 3, ST_MAX_ITERS = 4, ST_TIME_LIMIT = 5,
+       ST_NUMERICAL = 6 };
+enum { DIR_RB = 0, DIR_AA = 1, DIR_RES = 2, DIR_ZERO = 3 };
+
+struct Prob {
+    int n, m, N;
+    Csr<double> A, At;
+    const double* b;
+    const double* c;
+    const double* dinv;     // 1 / (1 + ||A e_j||^2), Jacobi preconditioner of I + A^T A
+    const double* g;        // M^{-1} (c, b), length n + m
+    double delta;           // 1 + (c, b)^T g
+    double nb, nc;          // ||b||, ||c||
+    ConeDev K;
+};
+
+struct Vecs {
+    double *u, *ut, *ub, *Ru, *d, *dt, *Rw, *pz, *pxi;   // length N
+    double *xw_u, *xw_d;                                 // CG warm starts, length n
+    double *cg_b, *cg_r, *cg_z, *cg_p, *cg_q;            // length n
+    double *cg_t;                                        // length m
+    double *Zb, *Yb;                                     // mem x N memory buffers
+    const double* u0;                                    // warm start or null
+    double *out_x, *out_y, *out_s;                       // results
+    double* tr_res;                                      // trace (may be null)
+    int *tr_kind, *tr_ls;
+    long long tr_cap;
+};
+
+struct Params {
+    double eps, c0, c1, q, sigma, lam, thetabar, aa_reg;
+    double cg_tol;
+    int direction, mem, ls_max, cg_max;
+    long long max_iters;
+    long long max_ticks;    // time limit in wall-clock ticks, <= 0: none
+    double setup_tol;       // CG tolerance of the one-off solve for g
+    int setup_max;
+};
+
+struct Result {
+    int status, err;
+    long long iters, k0, k1, k2, km, bt, cg;
+    double pr, dr, gap, ic, uc, pobj, dobj, res;
+};
+
+// ------------------------------------------------------------------ linear step
+
+// out[0 .. n+m) = M^{-1} r[0 .. n+m), warm-starting CG from xw (updated in place).
+// Leaves h^T M^{-1} r in sh.out[0]; returns the CG iteration count.
+template <typename Team>
+__device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
+                       double* xw, double tol, int maxit) {
+    const int n = P.n;
+    // rhs = rx - A^T ry ; t = A xw
+    spmv_rows(tm, P.At, r + n, [&](int j, double s) { V.cg_b[j] = r[j] - s; });
+    spmv_rows(tm, P.A, xw, [&](int i, double s) { V.cg_t[i] = s; });
+    tm.sync();
+    // r = rhs - (xw + A^T t) ; z = Dinv r ; p = z
+    double a_rz = 0.0, a_bb = 0.0, a_rr = 0.0;
+    spmv_rows(tm, P.At, V.cg_t, [&](int j, double s) {
+        const double bj = V.cg_b[j];
+        const double rj = bj - (xw[j] + s);
+        const double zj = P.dinv[j] * rj;
+        V.cg_r[j] = rj;
+        V.cg_z[j] = zj;
+        V.cg_p[j] = zj;
+        a_rz += rj * zj;
+        a_bb += bj * bj;
+        a_rr += rj * rj;
+    });
+    put(sh, 0, a_rz);
+    put(sh, 1, a_bb);
+    put(sh, 2, a_rr);
+    tm.reduce(sh, 3);
+    double rz = sh.out[0];
+    const double thr = tol * tol * sh.out[1];
+    double rr = sh.out[2];
+    double beta = 0.0;
+    int it = 0;
+    while (rr > thr && it < maxit && !tm.aborted()) {
+        // t = A z + beta t (= A p by linearity) ; p = z + beta p
+        spmv_rows(tm, P.A, V.cg_z, [&](int i, double s) { V.cg_t[i] = s + beta * V.cg_t[i]; });
+        if (it > 0)
+            for (int j = tm.rank(); j < n; j += tm.size()) V.cg_p[j] = V.cg_z[j] + beta * V.cg_p[j];
+        tm.sync();
+        // q = p + A^T t ; <p, q>
+        double a_pq = 0.0;
+        spmv_rows(tm, P.At, V.cg_t, [&](int j, double s) {
+            const double pj = V.cg_p[j];
+            const double qj = pj + s;
+            V.cg_q[j] = qj;
+            a_pq += pj * qj;
+        });
+        put(sh, 0, a_pq);
+        tm.reduce(sh, 1);
+        const double alpha = rz / sh.out[0];
+        double a_rz2 = 0.0, a_rr2 = 0.0;
+        for (int j = tm.rank(); j < n; j += tm.size()) {
+            xw[j] += alpha * V.cg_p[j];
+            const double rj = V.cg_r[j] - alpha * V.cg_q[j];
+            const double zj = P.dinv[j] * rj;
+            V.cg_r[j] = rj;
+            V.cg_z[j] = zj;
+            a_rz2 += rj * zj;
+            a_rr2 += rj * rj;
+        }
+        put(sh, 0, a_rz2);
+        put(sh, 1, a_rr2);
+        tm.reduce(sh, 2);
+        beta = sh.out[0] / rz;
+        rz = sh.out[0];
+        rr = sh.out[1];
+        ++it;
+    }
+    // py = ry + A px ; h^T p
+    double a_hp = 0.0;
+    spmv_rows(tm, P.A, xw, [&](int i, double s) {
+        const double py = r[n + i] + s;
+        out[n + i] = py;
+        a_hp += P.b[i] * py;
+    });
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        out[j] = xw[j];
+        a_hp += P.c[j] * xw[j];
+    }
+    put(sh, 0, a_hp);
+    tm.reduce(sh, 1);
+    return it;
+}
+
+// out = (I + Q)^{-1} r (length N).  r and out must not alias.
+template <typename Team>
+__device__ int linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
+                           double* xw, double tol, int maxit) {
+    const int it = solve_M(tm, sh, P, V, r, out, xw, tol, maxit);
+    const double t = (r[P.N - 1] + sh.out[0]) / P.delta;
+    const int nm = P.n + P.m;
+    for (int i = tm.rank(); i < nm; i += tm.size()) out[i] -= t * P.g[i];
+    if (tm.rank() == 0) out[P.N - 1] = t;
+    tm.sync();
+    return it;
+}
+
+// Per-instance constants of the linear step: ||b||, ||c||, g = M^{-1} (c, b)
+// (written to g) and delta = 1 + (c, b)^T g, stored into P.  V.d is scratch.
+template <typename Team>
+__device__ int setup_gdelta(Team& tm, Shared& sh, Prob& P, const Vecs& V, double* g, double tol, int maxit) {
+    const int n = P.n, m = P.m;
+    double nb2 = 0.0, nc2 = 0.0;
+    for (int i = tm.rank(); i < m; i += tm.size()) { nb2 += P.b[i] * P.b[i]; V.d[n + i] = P.b[i]; }
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        nc2 += P.c[j] * P.c[j];
+        V.d[j] = P.c[j];
+        V.xw_d[j] = 0.0;
+    }
+    if (tm.rank() == 0) V.d[P.N - 1] = 0.0;
+    put(sh, 0, nb2);
+    put(sh, 1, nc2);
+    tm.reduce(sh, 2);
+    P.nb = sqrt(sh.out[0]);
+    P.nc = sqrt(sh.out[1]);
+    const int it = solve_M(tm, sh, P, V, V.d, g, V.xw_d, tol, maxit);
+    P.delta = 1.0 + sh.out[0];
+    P.g = g;
+    return it;
+}
+
+// ------------------------------------------------------------------ passes
+
+// u-bar = Pi_C(2 u~ - u), R u = u~ - u-bar; returns ||R u||^2.
+template <typename Team>
+__device__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V) {
+    double acc = 0.0;
+    project_C(tm, P.n, P.N, P.K, nullptr, nullptr,
+              [&](int i) { return 2.0 * V.ut[i] - V.u[i]; },
+              [&](int i, double v) {
+                  V.ub[i] = v;
+                  const double r = V.ut[i] - v;
+                  V.Ru[i] = r;
+                  acc += r * r;
+              });
+    put(sh, 0, acc);
+    tm.reduce(sh, 1);
+    return sh.out[0];
+}
+
+struct Term {
+    double pr, dr, gap, ic, uc, pobj, dobj, tau, cx, by;
+    int status;
+    bool timeout;
+};
+
+// Sec. IV-C.  sig-bar = psi-bar - 2 psi~ + psi; candidate (chi, psi, sig)-bar / tau-bar.
+template <typename Team>
+__device__ Term termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                                 bool timed_out) {
+    const int n = P.n, m = P.m;
+    const double tau = V.ub[P.N - 1];
+    double a_p = 0.0, a_u = 0.0, a_d = 0.0, a_i = 0.0, a_cx = 0.0, a_by = 0.0;
+    spmv_rows(tm, P.A, V.ub, [&](int i, double s) {
+        const double sig = V.ub[n + i] - 2.0 * V.ut[n + i] + V.u[n + i];
+        const double v = s + sig;
+        a_u += v * v;
+        const double w = v - P.b[i] * tau;
+        a_p += w * w;
+    });
+    spmv_rows(tm, P.At, V.ub + n, [&](int j, double s) {
+        a_i += s * s;
+        const double w = s + P.c[j] * tau;
+        a_d += w * w;
+    });
+    for (int j = tm.rank(); j < n; j += tm.size()) a_cx += P.c[j] * V.ub[j];
+    for (int i = tm.rank(); i < m; i += tm.size()) a_by += P.b[i] * V.ub[n + i];
+    put(sh, 0, a_p);
+    put(sh, 1, a_u);
+    put(sh, 2, a_d);
+    put(sh, 3, a_i);
+    put(sh, 4, a_cx);
+    put(sh, 5, a_by);
+    put(sh, 6, (tm.rank() == 0 && timed_out) ? 1.0 : 0.0);
+    tm.reduce(sh, 7);
+    Term T;
+    const double cx = sh.out[4], by = sh.out[5];
+    T.tau = tau;
+    T.cx = cx;
+    T.by = by;
+    T.timeout = sh.out[6] > 0.0;
+    T.pr = T.dr = T.gap = T.ic = T.uc = INFINITY;
+    T.pobj = T.dobj = NAN;
+    if (tau > 0.0) {
+        T.pr = sqrt(sh.out[0]) / tau / (1.0 + P.nb);
+        T.dr = sqrt(sh.out[2]) / tau / (1.0 + P.nc);
+        T.gap = fabs(cx + by) / tau / (1.0 + fabs(cx) / tau + fabs(by) / tau);
+        T.pobj = cx / tau;
+        T.dobj = -by / tau;
+    }
+    if (by < 0.0) T.ic = P.nb * sqrt(sh.out[3]) / (-by);
+    if (cx < 0.0) T.uc = P.nc * sqrt(sh.out[1]) / (-cx);
+    T.status = 0;
+    if (tau > 0.0 && T.pr <= S.eps && T.dr <= S.eps && T.gap <= S.eps) T.status = ST_SOLVED;
+    else if (T.ic < S.eps) T.status = ST_INFEASIBLE;
+    else if (T.uc < S.eps) T.status = ST_UNBOUNDED;
+    return T;
+}
+
+// ------------------------------------------------------------------ directions
+
+// Solves (G + mu I) t = rhs (k x k, SPD) by Cholesky into t; false if not finite.
+__device__ inline bool small_chol_solve(const double* G, int ld, int k, double mu, const double* rhs, double* t,
+                                        double* L) {
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = G[i * ld + j] + (i == j ? mu : 0.0);
+            for (int e = 0; e < j; ++e) s -= L[i * MEMMAX + e] * L[j * MEMMAX + e];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i * MEMMAX + i] = sqrt(s);
+            } else {
+                L[i * MEMMAX + j] = s / L[j * MEMMAX + j];
+            }
+        }
+    double y[MEMMAX];
+    for (int i = 0; i < k; ++i) {
+        double s = rhs[i];
+        for (int e = 0; e < i; ++e) s -= L[i * MEMMAX + e] * y[e];
+        y[i] = s / L[i * MEMMAX + i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int e = i + 1; e < k; ++e) s -= L[e * MEMMAX + i] * t[e];
+        t[i] = s / L[i * MEMMAX + i];
+        if (!isfinite(t[i])) return false;
+    }
+    return true;
+}
+
+struct DirState {
+    int pend;       // 0: no pending pair; 1: (pz, pxi) complete; 2: pxi still needs + R u
+    int aa_k, aa_head;
+    int rb_m;
+};
+
+// Anderson: push the pending pair into the ring, update the Gram matrix and
+// solve for t; then d = -Ru - (Z - Xi) t, fused with the K0 update of u.
+template <typename Team>
+__device__ void direction_aa(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                             DirState& ds, bool k0) {
+    const int N = P.N, mem = S.mem;
+    int slot = -1;
+    if (ds.pend) {
+        slot = ds.aa_head;
+        const bool fix = ds.pend == 2;
+        double* Zs = V.Zb + (size_t)slot * N;
+        double* Ys = V.Yb + (size_t)slot * N;
+        for (int e = tm.rank(); e < N; e += tm.size()) {
+            Zs[e] = V.pz[e];
+            Ys[e] = V.pxi[e] + (fix ? V.Ru[e] : 0.0);
+        }
+        ds.aa_head = (ds.aa_head + 1) % mem;
+        if (ds.aa_k < mem) ds.aa_k++;
+    }
+    const int k = ds.aa_k;
+    if (k == 0) {
+        for (int e = tm.rank(); e < N; e += tm.size()) {
+            const double d = -V.Ru[e];
+            V.d[e] = d;
+            if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
+        }
+        tm.sync();
+        return;
+    }
+    // dots: <Xi_i, Ru> for every slot, <Xi_i, Xi_slot> for the new column
+    // (same element-to-thread map as the copy above: no barrier needed)
+    for (int i = 0; i < k; ++i) {
+        const double* Yi = V.Yb + (size_t)i * N;
+        double acc = 0.0;
+        for (int e = tm.rank(); e < N; e += tm.size()) acc += Yi[e] * V.Ru[e];
+        put(sh, i, acc);
+    }
+    if (slot >= 0) {
+        const double* Ys = V.Yb + (size_t)slot * N;
+        for (int i = 0; i < k; ++i) {
+            const double* Yi = V.Yb + (size_t)i * N;
+            double acc = 0.0;
+            for (int e = tm.rank(); e < N; e += tm.size()) acc += Yi[e] * Ys[e];
+            put(sh, k + i, acc);
+        }
+    }
+    tm.reduce(sh, slot >= 0 ? 2 * k : k);
+    if (threadIdx.x == 0) {
+        if (slot >= 0)
+            for (int i = 0; i < k; ++i) {
+                sh.G[slot * MEMMAX + i] = sh.out[k + i];
+                sh.G[i * MEMMAX + slot] = sh.out[k + i];
+            }
+        double tr = 0.0;
+        for (int i = 0; i < k; ++i) tr += sh.G[i * MEMMAX + i];
+        const bool ok = small_chol_solve(sh.G, MEMMAX, k, S.aa_reg * tr / k, sh.out, sh.coef, sh.L);
+        if (!ok)
+            for (int i = 0; i < k; ++i) sh.coef[i] = 0.0;
+    }
+    __syncthreads();
+    for (int e = tm.rank(); e < N; e += tm.size()) {
+        double d = -V.Ru[e];
+        for (int i = 0; i < k; ++i) d -= (V.Zb[(size_t)i * N + e] - V.Yb[(size_t)i * N + e]) * sh.coef[i];
+        V.d[e] = d;
+        if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
+    }
+    tm.sync();
+}
+
+// Restarted Broyden (Algorithm 2).  H = (I + zt_m z_m^T) ... (I + zt_1 z_1^T);
+// applying H to a vector v0 gives v0 + sum_j c_j zt_j with the scalar
+// recurrence c_i = <z_i, v0> + sum_{j<i} c_j <z_i, zt_j>, so one reduction of
+// all inner products replaces the m' sequential dot/axpy steps.  W holds
+// <z_i, zt_j> and is updated with every new pair.
+template <typename Team>
+__device__ void direction_rb(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                             DirState& ds, bool k0) {
+    const int N = P.N, mem = S.mem;
+    const int mp = ds.rb_m;
+    const bool pair = ds.pend != 0;
+    const bool fix = ds.pend == 2;
+    // pxi gets its + R u completion in place (same element map everywhere below)
+    if (fix)
+        for (int e = tm.rank(); e < N; e += tm.size()) V.pxi[e] += V.Ru[e];
+    // inner products: a_i = <z_i, xi>, b_i = <z_i, Ru>, c_i = <z_i, z>, e_j = <z, zt_j>,
+    // f1 = <z, xi>, f2 = <z, Ru>, f3 = <z, z>
+    for (int i = 0; i < mp; ++i) {
+        const double* Zi = V.Zb + (size_t)i * N;
+        double ab = 0.0;
+        for (int e = tm.rank(); e < N; e += tm.size()) ab += Zi[e] * V.Ru[e];
+        put(sh, mp + i, ab);
+        if (pair) {
+            const double* Zti = V.Yb + (size_t)i * N;
+            double aa = 0.0, ac = 0.0, ae = 0.0;
+            for (int e = tm.rank(); e < N; e += tm.size()) {
+                aa += Zi[e] * V.pxi[e];
+                ac += Zi[e] * V.pz[e];
+                ae += V.pz[e] * Zti[e];
+            }
+            put(sh, i, aa);
+            put(sh, 2 * mp + i, ac);
+            put(sh, 3 * mp + i, ae);
+        }
+    }
+    if (pair) {
+        double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+        for (int e = tm.rank(); e < N; e += tm.size()) {
+            const double z = V.pz[e];
+            f1 += z * V.pxi[e];
+            f2 += z * V.Ru[e];
+            f3 += z * z;
+        }
+        put(sh, 4 * mp, f1);
+        put(sh, 4 * mp + 1, f2);
+        put(sh, 4 * mp + 2, f3);
+    }
+    tm.reduce(sh, pair ? 4 * mp + 3 : 2 * mp);
+    // scalar phase (one thread per workgroup), coefficients broadcast in sh.coef:
+    //   coef[0 .. mp)      multipliers of zt_j in d
+    //   coef[mp]           multiplier of (z - xi) in d
+    //   coef[mp+1 .. 2mp+1) multipliers of zt_j in the new zt (times -1 scale below)
+    //   coef[2mp+1]        scale of the new zt: zt_new = s (z - xi - sum cx_j zt_j)
+    //   coef[2mp+2]        slot that receives the new pair
+    if (threadIdx.x == 0) {
+        const double* o = sh.out;
+        double* cr = sh.L;                 // LDS scratch of the scalar phase
+        double* cx = sh.L + MEMMAX;
+        for (int i = 0; i < mp; ++i) {
+            double s = -o[mp + i];                 // <z_i, -Ru>
+            for (int j = 0; j < i; ++j) s += cr[j] * sh.W[i * MEMMAX + j];
+            cr[i] = s;
+        }
+        if (!pair) {
+            for (int i = 0; i < mp; ++i) sh.coef[i] = cr[i];
+            sh.coef[mp] = 0.0;
+        } else {
+            for (int i = 0; i < mp; ++i) {
+                double s = o[i];                   // <z_i, xi>
+                for (int j = 0; j < i; ++j) s += cx[j] * sh.W[i * MEMMAX + j];
+                cx[i] = s;
+            }
+            const double f1 = o[4 * mp], f2 = o[4 * mp + 1], f3 = o[4 * mp + 2];
+            double zHxi = f1, zv = -f2;
+            for (int j = 0; j < mp; ++j) {
+                zHxi += cx[j] * o[3 * mp + j];
+                zv += cr[j] * o[3 * mp + j];
+            }
+            const double gamma = zHxi / f3;
+            double theta = 1.0;
+            if (fabs(gamma) < S.thetabar) {
+                const double sg = (gamma >= 0.0) ? 1.0 : -1.0;
+                theta = (1.0 - sg * S.thetabar) / (1.0 - gamma);
+            }
+            const double den = (1.0 - theta) * f3 + theta * zHxi;   // <z, H xi~>
+            const double sc = theta / den;                            // zt_new = sc (z - H xi)
+            // d = -Ru + sum cr_j zt_j + zv * zt_new
+            for (int j = 0; j < mp; ++j) sh.coef[j] = cr[j] - zv * sc * cx[j];
+            sh.coef[mp] = zv * sc;
+            for (int j = 0; j < mp; ++j) sh.coef[mp + 1 + j] = cx[j];
+            sh.coef[2 * mp + 1] = sc;
+            // new inner products
+            double* wcol = sh.L + 2 * MEMMAX;
+            for (int i = 0; i < mp; ++i) {
+                double zH = o[i];                  // <z_i, H xi> = a_i + sum cx_j W_ij
+                for (int j = 0; j < mp; ++j) zH += cx[j] * sh.W[i * MEMMAX + j];
+                wcol[i] = sc * (o[2 * mp + i] - zH);
+            }
+            const double wnn = sc * (f3 - zHxi);
+            const bool restart = (mp == mem);
+            const int slot = restart ? 0 : mp;
+            sh.coef[2 * mp + 2] = (double)slot;
+            if (restart) {
+                sh.W[0] = wnn;
+            } else {
+                for (int j = 0; j < mp; ++j) sh.W[slot * MEMMAX + j] = o[3 * mp + j];
+                for (int i = 0; i < mp; ++i) sh.W[i * MEMMAX + slot] = wcol[i];
+                sh.W[slot * MEMMAX + slot] = wnn;
+            }
+        }
+    }
+    __syncthreads();
+    const double cdz = sh.coef[mp];
+    double sc = 0.0;
+    int slot = -1;
+    if (pair) {
+        sc = sh.coef[2 * mp + 1];
+        slot = (int)sh.coef[2 * mp + 2];
+    }
+    for (int e = tm.rank(); e < N; e += tm.size()) {
+        const double ru = V.Ru[e];
+        double d = -ru;
+        double hx = 0.0;
+        for (int j = 0; j < mp; ++j) {
+            const double ztj = V.Yb[(size_t)j * N + e];
+            d += sh.coef[j] * ztj;
+            if (pair) hx += sh.coef[mp + 1 + j] * ztj;
+        }
+        if (pair) {
+            const double z = V.pz[e], xi = V.pxi[e];
+            d += cdz * (z - xi);
+            const double ztn = sc * (z - xi - hx);
+            V.Zb[(size_t)slot * N + e] = z;
+            V.Yb[(size_t)slot * N + e] = ztn;
+        }
+        V.d[e] = d;
+        if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -ru; }
+    }
+    if (pair) ds.rb_m = (mp == mem) ? 1 : mp + 1;
+    tm.sync();
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+
+template <typename Team>
+__device__ void write_trace(Team& tm, const Vecs& V, long long nu, double res, int kind, int ls) {
+    if (V.tr_res != nullptr && tm.rank() == 0 && nu < V.tr_cap) {
+        V.tr_res[nu] = res;
+        V.tr_kind[nu] = kind;
+        V.tr_ls[nu] = ls;
+    }
+}
+
+template <typename Team>
+__device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S, Result* res) {
+    const int n = P.n, m = P.m, N = P.N;
+    const long long t_start = wall_clock64();
+    for (int i = tm.rank(); i < N; i += tm.size())
+        V.u[i] = V.u0 ? V.u0[i] : (i == N - 1 ? 1.0 : 0.0);
+    for (int j = tm.rank(); j < n; j += tm.size()) { V.xw_u[j] = 0.0; V.xw_d[j] = 0.0; }
+    tm.sync();
+    DirState ds = {0, 0, 0, 0};
+    double eta0 = 0.0, eta = 0.0, r_safe = 0.0;
+    long long k0c = 0, k1c = 0, k2c = 0, kmc = 0, btc = 0, cgc = 0;
+    Term T;
+    double nRu = 0.0;
+    long long nu = 0;
+    for (nu = 0;; ++nu) {
+        cgc += linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, S.cg_tol, S.cg_max);
+        nRu = sqrt(residual_pass(tm, sh, P, V));
+        const bool late = S.max_ticks > 0 && (wall_clock64() - t_start) > S.max_ticks;
+        T = termination_pass(tm, sh, P, V, S, late);
+        if (nu == 0) eta0 = eta = r_safe = nRu;
+        if (!isfinite(nRu)) T.status = ST_NUMERICAL;
+        if (tm.aborted()) T.status = ST_NUMERICAL;
+        if (!T.status && nu >= S.max_iters) T.status = ST_MAX_ITERS;
+        if (!T.status && T.timeout) T.status = ST_TIME_LIMIT;
+        if (T.status) { write_trace(tm, V, nu, nRu, -1, 0); break; }
+        const bool k0 = nRu <= S.c0 * eta;
+        if (S.direction == DIR_AA) {
+            direction_aa(tm, sh, P, V, S, ds, k0);
+        } else if (S.direction == DIR_RB) {
+            direction_rb(tm, sh, P, V, S, ds, k0);
+        } else {
+            const bool zero = S.direction == DIR_ZERO;
+            for (int e = tm.rank(); e < N; e += tm.size()) {
+                const double d = zero ? 0.0 : -V.Ru[e];
+                V.d[e] = d;
+                if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
+            }
+            tm.sync();
+        }
+        if (k0) {                                          // K0: u+ = u + d (w = u + d)
+            eta = nRu;
+            ds.pend = 2;
+            ++k0c;
+            write_trace(tm, V, nu, nRu, 0, 0);
+            continue;
+        }
+        cgc += linear_step(tm, sh, P, V, V.d, V.dt, V.xw_d, S.cg_tol, S.cg_max);
+        double alpha = 1.0;
+        int kind = 3, ls = 0;
+        double coef = 0.0;
+        for (ls = 0; ls < S.ls_max; ++ls) {
+            const double a = alpha;
+            double acc_w = 0.0, acc_d = 0.0;
+            project_C(tm, n, N, P.K, nullptr, nullptr,
+                      [&](int i) { return 2.0 * (V.ut[i] + a * V.dt[i]) - (V.u[i] + a * V.d[i]); },
+                      [&](int i, double v) {
+                          const double rw = (V.ut[i] + a * V.dt[i]) - v;
+                          V.Rw[i] = rw;
+                          acc_w += rw * rw;
+                          acc_d += rw * V.d[i];
+                      });
+            put(sh, 0, acc_w);
+            put(sh, 1, acc_d);
+            tm.reduce(sh, 2);
+            const double nRw2 = sh.out[0];
+            const double nRw = sqrt(nRw2);
+            const double rho = nRw2 - a * sh.out[1];        // <Rw, u - T w>, T w = w - Rw
+            if (nRu <= r_safe && nRw <= S.c1 * nRu) {        // K1
+                kind = 1;
+                r_safe = nRw + pow(S.q, (double)nu) * eta0;
+                break;
+            }
+            if (rho >= S.sigma * nRu * nRw) {                // K2
+                kind = 2;
+                coef = S.lam * rho / nRw2;
+                break;
+            }
+            alpha *= 0.5;
+            ++btc;
+        }
+        const double a = alpha;
+        if (kind == 1) {
+            for (int e = tm.rank(); e < N; e += tm.size()) {
+                const double z = a * V.d[e];
+                V.u[e] += z;
+                V.pz[e] = z;
+                V.pxi[e] = V.Rw[e] - V.Ru[e];
+            }
+            ds.pend = 1;
+            ++k1c;
+        } else if (kind == 2) {
+            for (int e = tm.rank(); e < N; e += tm.size()) {
+                V.pz[e] = a * V.d[e];
+                V.pxi[e] = V.Rw[e] - V.Ru[e];
+                V.u[e] -= coef * V.Rw[e];
+            }
+            ds.pend = 1;
+            ++k2c;
+        } else {                                           // backtracking cap: u - lambda R u
+            for (int e = tm.rank(); e < N; e += tm.size()) V.u[e] -= S.lam * V.Ru[e];
+            ds.pend = 0;
+            ++kmc;
+        }
+        tm.sync();
+        write_trace(tm, V, nu, nRu, kind == 3 ? 3 : kind, ls);
+    }
+    // outputs: the candidate or the normalised certificate
+    const double tau = T.tau;
+    const double nan = NAN;
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        double x = nan;
+        if (T.status == ST_UNBOUNDED) x = V.ub[j] / (-T.cx);
+        else if (T.status != ST_INFEASIBLE && tau > 0.0) x = V.ub[j] / tau;
+        V.out_x[j] = x;
+    }
+    for (int i = tm.rank(); i < m; i += tm.size()) {
+        const double psi = V.ub[n + i];
+        const double sig = psi - 2.0 * V.ut[n + i] + V.u[n + i];
+        double y = nan, s = nan;
+        if (T.status == ST_INFEASIBLE) y = psi / (-T.by);
+        else if (T.status == ST_UNBOUNDED) s = sig / (-T.cx);
+        else if (tau > 0.0) { y = psi / tau; s = sig / tau; }
+        V.out_y[i] = y;
+        V.out_s[i] = s;
+    }
+    if (tm.rank() == 0) {
+        res->status = T.status;
+        res->err = tm.aborted() ? 1 : 0;
+        res->iters = nu;
+        res->k0 = k0c; res->k1 = k1c; res->k2 = k2c; res->km = kmc; res->bt = btc; res->cg = cgc;
+        res->pr = T.pr; res->dr = T.dr; res->gap = T.gap; res->ic = T.ic; res->uc = T.uc;
+        res->pobj = T.pobj; res->dobj = T.dobj; res->res = nRu;
+    }
+    tm.sync();
+}
+
+}  // namespace sscs

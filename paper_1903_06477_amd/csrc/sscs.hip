@@ -1,0 +1,1000 @@
+// libsscs: kernels and the C ABI declared in include/sscs.h.
+//
+// Kernels
+//   k_solve_grid   whole Algorithm 1 for one large instance; cooperative
+//                  launch, the grid is one GridTeam (grid barriers).
+//   k_op_grid      one component call (linear step, residual, projection,
+//                  setup of g and delta) on the same device code.
+//   k_solve_batch  persistent batched solve: each workgroup pops instances from
+//                  a device queue and runs Algorithm 1 as a BlockTeam.
+//   k_spmv         stand-alone row-segmented SpMV (the CG's SpMV, timed alone).
+//   setup kernels  CSR transpose (count, scan, scatter, per-row sort), Jacobi
+//                  diagonal.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sscs.h"
+#include "dev_engine.h"
+
+using namespace sscs;
+
+namespace {
+
+constexpr int kBlock = 256;            // threads per workgroup, all kernels of the solver
+constexpr int kBatchBlock = 256;
+
+enum { OP_LINEAR = 0, OP_RESIDUAL = 1, OP_PROJECT = 2, OP_SETUP = 3 };
+
+struct OpArgs {
+    int op;
+    const double* in;
+    double* out1;
+    double* out2;
+    double* scal;     // OP_SETUP: [delta, ||b||, ||c||]
+    double tol;
+    int maxit;
+};
+
+// A flat team over a plain (non-cooperative) grid: no barriers, used by
+// kernels that never synchronise across workgroups.
+struct FlatTeam {
+    __device__ int rank() const { return blockIdx.x * blockDim.x + threadIdx.x; }
+    __device__ int size() const { return gridDim.x * blockDim.x; }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S, Result* res,
+                                                       unsigned long long* bar, int* abort_flag,
+                                                       double* part, long long timeout_ticks) {
+    __shared__ Shared sh;
+    GridTeam tm{bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    sscs::solve(tm, sh, P, V, S, res);
+}
+
+__global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, unsigned long long* bar,
+                                                    int* abort_flag, double* part, long long timeout_ticks) {
+    __shared__ Shared sh;
+    GridTeam tm{bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    const int n = P.n, m = P.m, N = P.N;
+    if (a.op == OP_LINEAR) {
+        for (int j = tm.rank(); j < n; j += tm.size()) V.xw_d[j] = 0.0;
+        tm.sync();
+        const int it = linear_step(tm, sh, P, V, a.in, a.out1, V.xw_d, a.tol, a.maxit);
+        if (tm.rank() == 0 && a.scal) a.scal[0] = (double)it;
+    } else if (a.op == OP_RESIDUAL) {
+        for (int i = tm.rank(); i < N; i += tm.size()) V.u[i] = a.in[i];
+        for (int j = tm.rank(); j < n; j += tm.size()) V.xw_u[j] = 0.0;
+        tm.sync();
+        linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, a.tol, a.maxit);
+        const double r2 = residual_pass(tm, sh, P, V);
+        for (int i = tm.rank(); i < N; i += tm.size()) {
+            if (a.out1) a.out1[i] = V.ut[i];
+            a.out2[i] = V.Ru[i];
+        }
+        if (tm.rank() == 0 && a.scal) a.scal[0] = r2;
+    } else if (a.op == OP_PROJECT) {
+        project_C(tm, n, N, P.K, nullptr, nullptr,
+                  [&](int i) { return (i >= n && i < n + m) ? a.in[i - n] : 0.0; },
+                  [&](int i, double v) { if (i >= n && i < n + m) a.out1[i - n] = v; });
+    } else if (a.op == OP_SETUP) {
+        Prob Q = P;
+        const int it = setup_gdelta(tm, sh, Q, V, a.out1, a.tol, a.maxit);
+        if (tm.rank() == 0) {
+            a.scal[0] = Q.delta;
+            a.scal[1] = Q.nb;
+            a.scal[2] = Q.nc;
+            a.scal[3] = (double)it;
+        }
+    }
+    tm.sync();
+}
+
+struct BatchInst {
+    Prob P;
+    Vecs V;
+};
+
+__global__ void __launch_bounds__(kBatchBlock) k_solve_batch(const BatchInst* __restrict__ insts, int count,
+                                                             Params S, Result* res, int* queue) {
+    __shared__ Shared sh;
+    BlockTeam tm;
+    for (;;) {
+        if (threadIdx.x == 0) sh.qhead = atomicAdd(queue, 1);
+        __syncthreads();
+        const int idx = sh.qhead;
+        __syncthreads();
+        if (idx >= count) break;
+        Prob P = insts[idx].P;
+        const Vecs V = insts[idx].V;
+        setup_gdelta(tm, sh, P, V, const_cast<double*>(P.g), S.setup_tol, S.setup_max);
+        sscs::solve(tm, sh, P, V, S, res + idx);
+    }
+}
+
+__global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __restrict__ y) {
+    FlatTeam tm;
+    spmv_rows(tm, M, x, [&](int r, double s) { y[r] = s; });
+}
+
+// --- setup: CSR transpose ------------------------------------------------------
+
+__global__ void k_count_cols(const int* __restrict__ ci, long long nnz, int* __restrict__ cnt) {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nnz; k += (long long)gridDim.x * blockDim.x)
+        atomicAdd(cnt + ci[k], 1);
+}
+
+// Exclusive scan of cnt[0..len) into out[0..len]; one workgroup, each thread a
+// contiguous chunk, then a scan of the chunk totals.
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int len, int* __restrict__ out) {
+    __shared__ int tot[1024];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int chunk = (len + nt - 1) / nt;
+    const int b0 = min(len, t * chunk), b1 = min(len, b0 + chunk);
+    int s = 0;
+    for (int i = b0; i < b1; ++i) s += cnt[i];
+    tot[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int i = 0; i < nt; ++i) { const int v = tot[i]; tot[i] = run; run += v; }
+        out[len] = run;
+    }
+    __syncthreads();
+    int run = tot[t];
+    for (int i = b0; i < b1; ++i) { out[i] = run; run += cnt[i]; }
+}
+
+__global__ void k_scatter_t(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                            int rows, const int* __restrict__ trp, int* __restrict__ fill,
+                            int* __restrict__ tci, double* __restrict__ tv) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x)
+        for (int k = rp[r]; k < rp[r + 1]; ++k) {
+            const int j = ci[k];
+            const int pos = trp[j] + atomicAdd(fill + j, 1);
+            tci[pos] = r;
+            tv[pos] = v[k];
+        }
+}
+
+// Sorts each row of the transpose by column (insertion sort, one thread per
+// row) so that its order, and every sum over it, is deterministic; then the
+// Jacobi diagonal 1 / (1 + ||row||^2).
+__global__ void k_sort_rows(const int* __restrict__ trp, int rows, int* __restrict__ tci, double* __restrict__ tv,
+                            double* __restrict__ dinv) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+        const int k0 = trp[r], k1 = trp[r + 1];
+        for (int k = k0 + 1; k < k1; ++k) {
+            const int key = tci[k];
+            const double val = tv[k];
+            int j = k - 1;
+            while (j >= k0 && tci[j] > key) { tci[j + 1] = tci[j]; tv[j + 1] = tv[j]; --j; }
+            tci[j + 1] = key;
+            tv[j + 1] = val;
+        }
+        double s = 0.0;
+        for (int k = k0; k < k1; ++k) s += tv[k] * tv[k];
+        dinv[r] = 1.0 / (1.0 + s);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+thread_local std::string g_last_hip;
+
+#define HIP_TRY(expr)                                                      \
+    do {                                                                   \
+        hipError_t _e = (expr);                                            \
+        if (_e != hipSuccess) {                                            \
+            g_last_hip = std::string(#expr) + ": " + hipGetErrorString(_e); \
+            return SSCS_E_HIP;                                             \
+        }                                                                  \
+    } while (0)
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int pow2_seg(double avg) {
+    int s = 1;
+    while (s < 64 && s < avg / 2.0) s <<= 1;
+    return s;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Everything one instance needs on the device.
+struct Inst {
+    int n = 0, m = 0, N = 0;
+    long long nnz = 0;
+    int *A_rp = nullptr, *A_ci = nullptr, *At_rp = nullptr, *At_ci = nullptr;
+    double *A_v = nullptr, *At_v = nullptr;
+    double *b = nullptr, *c = nullptr, *dinv = nullptr, *g = nullptr;
+    double delta = 1.0, nb = 0.0, nc = 0.0;
+    int *qoff = nullptr, *sord = nullptr, *soff = nullptr;
+    int segA = 1, segAt = 1;
+    ConeDev K{};
+    bool owns_A = true;
+};
+
+int validate(const sscs_data* d, const sscs_cone* k) {
+    if (!d || !k) return SSCS_E_INVALID;
+    if (d->m < 1 || d->n < 1 || d->nnz < 0) return SSCS_E_INVALID;
+    if (!d->rowptr || (d->nnz > 0 && (!d->colind || !d->val)) || !d->b || !d->c) return SSCS_E_INVALID;
+    if (d->nnz >= (1ll << 31)) return SSCS_E_UNSUPPORTED;
+    if (d->rowptr[0] != 0 || d->rowptr[d->m] != d->nnz) return SSCS_E_INVALID;
+    for (int i = 0; i < d->m; ++i) {
+        if (d->rowptr[i + 1] < d->rowptr[i]) return SSCS_E_INVALID;
+        for (int kk = d->rowptr[i]; kk < d->rowptr[i + 1]; ++kk) {
+            const int j = d->colind[kk];
+            if (j < 0 || j >= d->n) return SSCS_E_INVALID;
+            if (kk > d->rowptr[i] && j <= d->colind[kk - 1]) return SSCS_E_INVALID;
+        }
+    }
+    if (k->z < 0 || k->l < 0 || k->nq < 0 || k->ns < 0 || k->ep < 0) return SSCS_E_INVALID;
+    if ((k->nq > 0 && !k->q) || (k->ns > 0 && !k->s)) return SSCS_E_INVALID;
+    long long rows = (long long)k->z + k->l + 3ll * k->ep;
+    for (int i = 0; i < k->nq; ++i) {
+        if (k->q[i] < 1) return SSCS_E_INVALID;
+        rows += k->q[i];
+    }
+    for (int i = 0; i < k->ns; ++i) {
+        if (k->s[i] < 1) return SSCS_E_INVALID;
+        if (k->s[i] > 1023) return SSCS_E_UNSUPPORTED;
+        rows += (long long)k->s[i] * (k->s[i] + 1) / 2;
+    }
+    if (rows != d->m) return SSCS_E_INVALID;
+    return SSCS_OK;
+}
+
+int validate_settings(const sscs_settings* st) {
+    if (!st) return SSCS_E_INVALID;
+    if (!(st->eps > 0)) return SSCS_E_INVALID;
+    if (st->direction < 0 || st->direction > 3) return SSCS_E_INVALID;
+    if (st->mem < 1 || st->mem > MEMMAX) return SSCS_E_INVALID;
+    if (st->ls_max < 0 || st->max_iters < 0 || st->cg_max < 0) return SSCS_E_INVALID;
+    if (!(st->lambda > 0 && st->lambda < 2)) return SSCS_E_INVALID;
+    if (!(st->sigma > 0 && st->sigma < 1)) return SSCS_E_INVALID;
+    if (st->c0 < 0 || st->c1 < 0 || st->q < 0 || st->q >= 1) return SSCS_E_INVALID;
+    if (!(st->thetabar > 0 && st->thetabar < 1)) return SSCS_E_INVALID;
+    if (!(st->cg_tol > 0)) return SSCS_E_INVALID;
+    if (st->precision != SSCS_PREC_FP64 && st->precision != SSCS_PREC_MIXED) return SSCS_E_INVALID;
+    return SSCS_OK;
+}
+
+Params make_params(const sscs_settings& st, double ticks_per_s) {
+    Params p{};
+    p.eps = st.eps;
+    p.c0 = st.c0;
+    p.c1 = st.c1;
+    p.q = st.q;
+    p.sigma = st.sigma;
+    p.lam = st.lambda;
+    p.thetabar = st.thetabar;
+    p.aa_reg = st.aa_reg;
+    p.cg_tol = st.cg_tol;
+    p.direction = st.direction;
+    p.mem = st.mem;
+    p.ls_max = st.ls_max;
+    p.cg_max = st.cg_max;
+    p.max_iters = st.max_iters;
+    p.max_ticks = st.max_time_s > 0 ? (long long)(st.max_time_s * ticks_per_s) : 0;
+    p.setup_tol = std::min(1e-14, st.cg_tol);
+    p.setup_max = std::max(st.cg_max, 1000);
+    return p;
+}
+
+// Cone layout tables (host) -> device, offsets relative to the start of y.
+struct ConeHost {
+    std::vector<int> qoff, sord, soff;
+    int z = 0, l = 0, ep = 0, soc0 = 0, psd0 = 0, exp0 = 0, kmax = 0;
+};
+
+ConeHost cone_host(const sscs_cone* k) {
+    ConeHost h;
+    h.z = k->z;
+    h.l = k->l;
+    h.ep = k->ep;
+    h.soc0 = k->z + k->l;
+    h.qoff.push_back(0);
+    for (int i = 0; i < k->nq; ++i) h.qoff.push_back(h.qoff.back() + k->q[i]);
+    h.psd0 = h.soc0 + h.qoff.back();
+    h.soff.push_back(0);
+    for (int i = 0; i < k->ns; ++i) {
+        h.sord.push_back(k->s[i]);
+        h.soff.push_back(h.soff.back() + k->s[i] * (k->s[i] + 1) / 2);
+        h.kmax = std::max(h.kmax, k->s[i]);
+    }
+    h.exp0 = h.psd0 + h.soff.back();
+    return h;
+}
+
+template <typename T>
+int dmalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        g_last_hip = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return SSCS_E_NOMEM;
+    }
+    return SSCS_OK;
+}
+
+#define TRY(expr)                    \
+    do {                             \
+        int _r = (expr);             \
+        if (_r != SSCS_OK) return _r; \
+    } while (0)
+
+// Uploads A (unless shared), b, c and the cone tables; builds A^T and dinv.
+int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t s, const Inst* share) {
+    I.m = d->m;
+    I.n = d->n;
+    I.N = d->n + d->m + 1;
+    I.nnz = d->nnz;
+    const size_t nnz = (size_t)d->nnz;
+    if (share) {
+        I.A_rp = share->A_rp; I.A_ci = share->A_ci; I.A_v = share->A_v;
+        I.At_rp = share->At_rp; I.At_ci = share->At_ci; I.At_v = share->At_v;
+        I.dinv = share->dinv;
+        I.owns_A = false;
+    } else {
+        TRY(dmalloc(&I.A_rp, I.m + 1));
+        TRY(dmalloc(&I.A_ci, nnz));
+        TRY(dmalloc(&I.A_v, nnz));
+        TRY(dmalloc(&I.At_rp, I.n + 1));
+        TRY(dmalloc(&I.At_ci, nnz));
+        TRY(dmalloc(&I.At_v, nnz));
+        TRY(dmalloc(&I.dinv, I.n));
+        HIP_TRY(hipMemcpyAsync(I.A_rp, d->rowptr, (I.m + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+        if (nnz) {
+            HIP_TRY(hipMemcpyAsync(I.A_ci, d->colind, nnz * sizeof(int), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(I.A_v, d->val, nnz * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        int* cnt = nullptr;
+        TRY(dmalloc(&cnt, I.n));
+        HIP_TRY(hipMemsetAsync(cnt, 0, I.n * sizeof(int), s));
+        if (nnz) k_count_cols<<<std::min<long long>(4096, (nnz + 255) / 256), 256, 0, s>>>(I.A_ci, (long long)nnz, cnt);
+        k_scan<<<1, 1024, 0, s>>>(cnt, I.n, I.At_rp);
+        HIP_TRY(hipMemsetAsync(cnt, 0, I.n * sizeof(int), s));
+        k_scatter_t<<<std::min(4096, (I.m + 255) / 256), 256, 0, s>>>(I.A_rp, I.A_ci, I.A_v, I.m, I.At_rp, cnt,
+                                                                     I.At_ci, I.At_v);
+        k_sort_rows<<<std::min(4096, (I.n + 255) / 256), 256, 0, s>>>(I.At_rp, I.n, I.At_ci, I.At_v, I.dinv);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        hipFree(cnt);
+    }
+    I.segA = pow2_seg((double)d->nnz / std::max(1, I.m));
+    I.segAt = pow2_seg((double)d->nnz / std::max(1, I.n));
+    TRY(dmalloc(&I.b, I.m));
+    TRY(dmalloc(&I.c, I.n));
+    TRY(dmalloc(&I.g, I.n + I.m));
+    HIP_TRY(hipMemcpyAsync(I.b, d->b, I.m * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(I.c, d->c, I.n * sizeof(double), hipMemcpyHostToDevice, s));
+    ConeHost h = cone_host(k);
+    TRY(dmalloc(&I.qoff, h.qoff.size()));
+    TRY(dmalloc(&I.sord, std::max<size_t>(1, h.sord.size())));
+    TRY(dmalloc(&I.soff, h.soff.size()));
+    HIP_TRY(hipMemcpyAsync(I.qoff, h.qoff.data(), h.qoff.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    if (!h.sord.empty())
+        HIP_TRY(hipMemcpyAsync(I.sord, h.sord.data(), h.sord.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(I.soff, h.soff.data(), h.soff.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    I.K.z = h.z; I.K.l = h.l; I.K.nq = (int)h.qoff.size() - 1; I.K.qoff = I.qoff;
+    I.K.ns = (int)h.sord.size(); I.K.sord = I.sord; I.K.soff = I.soff; I.K.ep = h.ep;
+    I.K.soc0 = h.soc0; I.K.psd0 = h.psd0; I.K.exp0 = h.exp0;
+    I.K.psd_scratch = nullptr;
+    I.K.psd_kmax = h.kmax;
+    return SSCS_OK;
+}
+
+void free_instance(Inst& I) {
+    if (I.owns_A) {
+        hipFree(I.A_rp); hipFree(I.A_ci); hipFree(I.A_v);
+        hipFree(I.At_rp); hipFree(I.At_ci); hipFree(I.At_v); hipFree(I.dinv);
+    }
+    hipFree(I.b); hipFree(I.c); hipFree(I.g);
+    hipFree(I.qoff); hipFree(I.sord); hipFree(I.soff);
+    hipFree(I.K.psd_scratch);
+    I = Inst{};
+}
+
+Prob make_prob(const Inst& I) {
+    Prob P{};
+    P.n = I.n; P.m = I.m; P.N = I.N;
+    P.A = Csr<double>{I.A_rp, I.A_ci, I.A_v, I.m, I.n, I.segA};
+    P.At = Csr<double>{I.At_rp, I.At_ci, I.At_v, I.n, I.m, I.segAt};
+    P.b = I.b; P.c = I.c; P.dinv = I.dinv; P.g = I.g;
+    P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
+    P.K = I.K;
+    return P;
+}
+
+size_t vec_doubles(int n, int m, int mem) {
+    const size_t N = (size_t)n + m + 1;
+    return 9 * N + 7 * (size_t)n + (size_t)m + 2 * (size_t)mem * N;
+}
+
+// Carves the Vecs of one instance from a contiguous device buffer.
+Vecs carve(double* base, int n, int m, int mem) {
+    const size_t N = (size_t)n + m + 1;
+    Vecs V{};
+    double* p = base;
+    auto take = [&](size_t len) { double* q = p; p += len; return q; };
+    V.u = take(N); V.ut = take(N); V.ub = take(N); V.Ru = take(N); V.d = take(N);
+    V.dt = take(N); V.Rw = take(N); V.pz = take(N); V.pxi = take(N);
+    V.xw_u = take(n); V.xw_d = take(n);
+    V.cg_b = take(n); V.cg_r = take(n); V.cg_z = take(n); V.cg_p = take(n); V.cg_q = take(n);
+    V.cg_t = take(m);
+    V.Zb = take((size_t)mem * N); V.Yb = take((size_t)mem * N);
+    return V;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ single instance
+
+struct sscs_work {
+    hipStream_t stream = nullptr;
+    sscs_settings st{};
+    Inst I;
+    double* vecbuf = nullptr;
+    Vecs V{};
+    double* io = nullptr;        // staging for host vectors: 4 N
+    double* scal = nullptr;      // device scalars
+    Result* res = nullptr;
+    unsigned long long* bar = nullptr;
+    int* abort_flag = nullptr;
+    double* part = nullptr;
+    double* tr_res = nullptr;
+    int* tr_kind = nullptr;
+    int* tr_ls = nullptr;
+    long long tr_cap = 0;
+    long long last_iters = -1;
+    int grid = 1, max_grid = 1;
+    double ticks_per_s = 1e8;
+    long long timeout_ticks = 0;
+    double setup_s = 0;
+};
+
+namespace {
+
+int launch_grid_kernel(sscs_work* w, void* fn, void** args) {
+    HIP_TRY(hipMemsetAsync(w->bar, 0, sizeof(unsigned long long), w->stream));
+    HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
+    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->grid), dim3(kBlock), args, 0, w->stream));
+    return SSCS_OK;
+}
+
+int check_abort(sscs_work* w) {
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, w->abort_flag, sizeof(int), hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    if (flag) {
+        g_last_hip = "grid barrier timed out";
+        return SSCS_E_DEVICE;
+    }
+    return SSCS_OK;
+}
+
+int run_op(sscs_work* w, int op, const double* in, double* out1, double* out2, double tol, int maxit) {
+    Prob P = make_prob(w->I);
+    OpArgs a{op, in, out1, out2, w->scal, tol, maxit};
+    void* args[] = {&P, &w->V, &a, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
+    TRY(launch_grid_kernel(w, (void*)k_op_grid, args));
+    HIP_TRY(hipGetLastError());
+    return check_abort(w);
+}
+
+// Host or device vector in, device pointer out (staged through w->io).
+int stage_in(sscs_work* w, const double* src, size_t len, int slot, const double** dev) {
+    if (w->st.data_on_device) { *dev = src; return SSCS_OK; }
+    double* dst = w->io + (size_t)slot * w->I.N;
+    HIP_TRY(hipMemcpyAsync(dst, src, len * sizeof(double), hipMemcpyHostToDevice, w->stream));
+    *dev = dst;
+    return SSCS_OK;
+}
+
+double* out_ptr(sscs_work* w, double* user, int slot) {
+    return w->st.data_on_device ? user : w->io + (size_t)slot * w->I.N;
+}
+
+int stage_out(sscs_work* w, double* user, const double* dev, size_t len) {
+    if (w->st.data_on_device || user == nullptr) return SSCS_OK;
+    HIP_TRY(hipMemcpyAsync(user, dev, len * sizeof(double), hipMemcpyDeviceToHost, w->stream));
+    return SSCS_OK;
+}
+
+int choose_grid(sscs_work* w) {
+    int dev = 0, ncu = 0, occ = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_grid, kBlock, 0));
+    int occ2 = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, (const void*)k_op_grid, kBlock, 0));
+    occ = std::max(1, std::min(occ, occ2));
+    w->max_grid = std::max(1, ncu * occ);
+    // about eight nonzeros of A per thread per SpMV, at least one row per thread
+    const long long want = std::max<long long>((w->I.nnz + 8ll * kBlock - 1) / (8ll * kBlock),
+                                               ((long long)w->I.N + kBlock - 1) / kBlock);
+    w->grid = (int)std::max<long long>(1, std::min<long long>(want, w->max_grid));
+    int rate_khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    w->ticks_per_s = rate_khz > 0 ? rate_khz * 1000.0 : 1e8;
+    w->timeout_ticks = (long long)(60.0 * w->ticks_per_s);
+    return SSCS_OK;
+}
+
+int alloc_work_vectors(sscs_work* w) {
+    const int mem = MEMMAX;     // memory buffers sized for the largest mem so settings may change
+    TRY(dmalloc(&w->vecbuf, vec_doubles(w->I.n, w->I.m, mem)));
+    w->V = carve(w->vecbuf, w->I.n, w->I.m, mem);
+    TRY(dmalloc(&w->io, 4 * (size_t)w->I.N));
+    TRY(dmalloc(&w->scal, 16));
+    TRY(dmalloc(&w->res, 1));
+    TRY(dmalloc(&w->bar, 1));
+    TRY(dmalloc(&w->abort_flag, 1));
+    TRY(dmalloc(&w->part, 2 * (size_t)KMAX * w->max_grid));
+    if (w->I.K.ns > 0) {
+        const size_t k = w->I.K.psd_kmax;
+        const size_t per = 2 * k * k + k * (k + 1);
+        const size_t nblk = std::min<size_t>(w->grid, w->I.K.ns);
+        TRY(dmalloc(&w->I.K.psd_scratch, per * nblk));
+    }
+    return SSCS_OK;
+}
+
+int setup_linear(sscs_work* w) {
+    // g = M^{-1} (c, b) and delta = 1 + (c, b)^T g, solved tightly once
+    double* h = w->io;
+    HIP_TRY(hipMemcpyAsync(h, w->I.c, w->I.n * sizeof(double), hipMemcpyDeviceToDevice, w->stream));
+    HIP_TRY(hipMemcpyAsync(h + w->I.n, w->I.b, w->I.m * sizeof(double), hipMemcpyDeviceToDevice, w->stream));
+    HIP_TRY(hipMemsetAsync(h + w->I.n + w->I.m, 0, sizeof(double), w->stream));
+    TRY(run_op(w, OP_SETUP, h, w->I.g, nullptr, std::min(1e-14, w->st.cg_tol), std::max(w->st.cg_max, 1000)));
+    double sc[4];
+    HIP_TRY(hipMemcpyAsync(sc, w->scal, sizeof(sc), hipMemcpyDeviceToHost, w->stream));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    w->I.delta = sc[0];
+    w->I.nb = sc[1];
+    w->I.nc = sc[2];
+    if (!std::isfinite(sc[0])) return SSCS_E_INVALID;
+    return SSCS_OK;
+}
+
+int alloc_trace(sscs_work* w) {
+    hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls);
+    w->tr_res = nullptr; w->tr_kind = nullptr; w->tr_ls = nullptr; w->tr_cap = 0;
+    if (!w->st.record_trace) return SSCS_OK;
+    w->tr_cap = std::min<long long>(w->st.max_iters + 1, 4 << 20);
+    TRY(dmalloc(&w->tr_res, w->tr_cap));
+    TRY(dmalloc(&w->tr_kind, w->tr_cap));
+    TRY(dmalloc(&w->tr_ls, w->tr_cap));
+    return SSCS_OK;
+}
+
+void fill_info(sscs_info* info, const Result& r, double setup_s, double solve_s) {
+    if (!info) return;
+    info->status = r.status;
+    info->iters = r.iters;
+    info->k0 = r.k0; info->k1 = r.k1; info->k2 = r.k2; info->km = r.km;
+    info->backtracks = r.bt;
+    info->cg_iters = r.cg;
+    info->pr = r.pr; info->dr = r.dr; info->gap = r.gap; info->ic = r.ic; info->uc = r.uc;
+    info->pobj = r.pobj; info->dobj = r.dobj; info->res_fp = r.res;
+    info->setup_s = setup_s;
+    info->solve_s = solve_s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sscs_default_settings(sscs_settings* st) {
+    if (!st) return SSCS_E_INVALID;
+    std::memset(st, 0, sizeof(*st));
+    st->eps = 1e-6;
+    st->direction = SSCS_DIR_AA;
+    st->mem = 5;
+    st->c0 = 0.99;
+    st->c1 = 0.99;
+    st->q = 0.99;
+    st->sigma = 0.01;
+    st->lambda = 1.0;
+    st->thetabar = 0.1;
+    st->ls_max = 10;
+    st->max_iters = 10000;
+    st->max_time_s = 0.0;
+    st->precision = SSCS_PREC_FP64;
+    st->cg_tol = 1e-10;
+    st->cg_max = 500;
+    st->data_on_device = 0;
+    st->record_trace = 0;
+    st->aa_reg = 1e-12;
+    return SSCS_OK;
+}
+
+int sscs_create(const sscs_data* data, const sscs_cone* cone, const sscs_settings* st, void* hip_stream,
+                sscs_work** out) {
+    try {
+        if (!out) return SSCS_E_INVALID;
+        *out = nullptr;
+        TRY(validate(data, cone));
+        TRY(validate_settings(st));
+        if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
+        const double t0 = now_s();
+        sscs_work* w = new (std::nothrow) sscs_work();
+        if (!w) return SSCS_E_NOMEM;
+        w->stream = (hipStream_t)hip_stream;
+        w->st = *st;
+        int r = upload_instance(w->I, data, cone, w->stream, nullptr);
+        if (r == SSCS_OK) r = choose_grid(w);
+        if (r == SSCS_OK) r = alloc_work_vectors(w);
+        if (r == SSCS_OK) r = alloc_trace(w);
+        if (r == SSCS_OK) r = setup_linear(w);
+        if (r != SSCS_OK) { sscs_destroy(w); return r; }
+        w->setup_s = now_s() - t0;
+        *out = w;
+        return SSCS_OK;
+    } catch (...) {
+        return SSCS_E_NOMEM;
+    }
+}
+
+int sscs_update_settings(sscs_work* w, const sscs_settings* st) {
+    if (!w) return SSCS_E_INVALID;
+    TRY(validate_settings(st));
+    if (st->precision != w->st.precision) return SSCS_E_INVALID;
+    const bool retrace = st->record_trace != w->st.record_trace || st->max_iters != w->st.max_iters;
+    w->st = *st;
+    if (retrace) TRY(alloc_trace(w));
+    return SSCS_OK;
+}
+
+int sscs_update_bc(sscs_work* w, const double* b, const double* c) {
+    if (!w || !b || !c) return SSCS_E_INVALID;
+    const hipMemcpyKind kind = w->st.data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(w->I.b, b, w->I.m * sizeof(double), kind, w->stream));
+    HIP_TRY(hipMemcpyAsync(w->I.c, c, w->I.n * sizeof(double), kind, w->stream));
+    return setup_linear(w);
+}
+
+int sscs_destroy(sscs_work* w) {
+    if (!w) return SSCS_OK;
+    if (w->stream) hipStreamSynchronize(w->stream);
+    else hipDeviceSynchronize();
+    free_instance(w->I);
+    hipFree(w->vecbuf); hipFree(w->io); hipFree(w->scal); hipFree(w->res);
+    hipFree(w->bar); hipFree(w->abort_flag); hipFree(w->part);
+    hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls);
+    delete w;
+    return SSCS_OK;
+}
+
+int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, sscs_info* info) {
+    if (!w || !x || !y || !s) return SSCS_E_INVALID;
+    const double t0 = now_s();
+    const int n = w->I.n, m = w->I.m, N = w->I.N;
+    const double* du0 = nullptr;
+    if (u0) TRY(stage_in(w, u0, N, 0, &du0));
+    Vecs V = w->V;
+    V.u0 = du0;
+    V.out_x = out_ptr(w, x, 1);
+    V.out_y = out_ptr(w, y, 2);
+    V.out_s = out_ptr(w, s, 3);
+    V.tr_res = w->tr_res; V.tr_kind = w->tr_kind; V.tr_ls = w->tr_ls; V.tr_cap = w->tr_cap;
+    Prob P = make_prob(w->I);
+    Params S = make_params(w->st, w->ticks_per_s);
+    void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
+    TRY(launch_grid_kernel(w, (void*)k_solve_grid, args));
+    HIP_TRY(hipGetLastError());
+    TRY(stage_out(w, x, V.out_x, n));
+    TRY(stage_out(w, y, V.out_y, m));
+    TRY(stage_out(w, s, V.out_s, m));
+    Result r{};
+    HIP_TRY(hipMemcpyAsync(&r, w->res, sizeof(Result), hipMemcpyDeviceToHost, w->stream));
+    TRY(check_abort(w));
+    w->last_iters = r.iters;
+    fill_info(info, r, w->setup_s, now_s() - t0);
+    return SSCS_OK;
+}
+
+int sscs_linear_step(sscs_work* w, const double* r, double* out) {
+    if (!w || !r || !out) return SSCS_E_INVALID;
+    const double* dr = nullptr;
+    TRY(stage_in(w, r, w->I.N, 0, &dr));
+    double* dout = out_ptr(w, out, 1);
+    TRY(run_op(w, OP_LINEAR, dr, dout, nullptr, w->st.cg_tol, w->st.cg_max));
+    TRY(stage_out(w, out, dout, w->I.N));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return SSCS_OK;
+}
+
+int sscs_residual(sscs_work* w, const double* u, double* ut, double* Ru) {
+    if (!w || !u || !Ru) return SSCS_E_INVALID;
+    const double* du = nullptr;
+    TRY(stage_in(w, u, w->I.N, 0, &du));
+    double* dut = ut ? out_ptr(w, ut, 1) : nullptr;
+    double* dRu = out_ptr(w, Ru, 2);
+    TRY(run_op(w, OP_RESIDUAL, du, dut, dRu, w->st.cg_tol, w->st.cg_max));
+    if (ut) TRY(stage_out(w, ut, dut, w->I.N));
+    TRY(stage_out(w, Ru, dRu, w->I.N));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return SSCS_OK;
+}
+
+int sscs_project_dual_cone(sscs_work* w, const double* in, double* out) {
+    if (!w || !in || !out) return SSCS_E_INVALID;
+    const double* din = nullptr;
+    TRY(stage_in(w, in, w->I.m, 0, &din));
+    double* dout = out_ptr(w, out, 1);
+    TRY(run_op(w, OP_PROJECT, din, dout, nullptr, 0.0, 0));
+    TRY(stage_out(w, out, dout, w->I.m));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return SSCS_OK;
+}
+
+int sscs_spmv(sscs_work* w, int32_t transpose, const double* x, double* y) {
+    if (!w || !x || !y) return SSCS_E_INVALID;
+    const int lin = transpose ? w->I.m : w->I.n, lout = transpose ? w->I.n : w->I.m;
+    const double* dx = nullptr;
+    TRY(stage_in(w, x, lin, 0, &dx));
+    double* dy = out_ptr(w, y, 1);
+    Prob P = make_prob(w->I);
+    const Csr<double>& M = transpose ? P.At : P.A;
+    const long long threads = (long long)M.rows * M.seg;
+    const int grid = (int)std::min<long long>(65535, (threads + 255) / 256);
+    k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);
+    HIP_TRY(hipGetLastError());
+    TRY(stage_out(w, y, dy, lout));
+    HIP_TRY(hipStreamSynchronize(w->stream));
+    return SSCS_OK;
+}
+
+int sscs_spmv_bench(sscs_work* w, int32_t transpose, int32_t reps, double* ms) {
+    if (!w || !ms || reps < 1) return SSCS_E_INVALID;
+    Prob P = make_prob(w->I);
+    const Csr<double>& M = transpose ? P.At : P.A;
+    const double* dx = transpose ? w->V.Ru + w->I.n : w->V.Ru;   // any resident vector of the right length
+    double* dy = w->V.Rw;
+    const long long threads = (long long)M.rows * M.seg;
+    const int grid = (int)std::min<long long>(65535, (threads + 255) / 256);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);     // warm-up
+    HIP_TRY(hipEventRecord(e0, w->stream));
+    for (int r = 0; r < reps; ++r) k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);
+    HIP_TRY(hipEventRecord(e1, w->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = f;
+    return SSCS_OK;
+}
+
+int sscs_get_trace(sscs_work* w, int64_t cap, double* res, int32_t* kind, int32_t* ls, int64_t* count) {
+    if (!w || !count) return SSCS_E_INVALID;
+    if (!w->tr_res || w->last_iters < 0) { *count = 0; return SSCS_OK; }
+    const long long avail = std::min<long long>(w->last_iters + 1, w->tr_cap);
+    *count = avail;
+    const long long c = std::min<long long>(cap, avail);
+    if (c > 0) {
+        if (res) HIP_TRY(hipMemcpy(res, w->tr_res, c * sizeof(double), hipMemcpyDeviceToHost));
+        if (kind) HIP_TRY(hipMemcpy(kind, w->tr_kind, c * sizeof(int), hipMemcpyDeviceToHost));
+        if (ls) HIP_TRY(hipMemcpy(ls, w->tr_ls, c * sizeof(int), hipMemcpyDeviceToHost));
+    }
+    return SSCS_OK;
+}
+
+const char* sscs_error_string(int code) {
+    static thread_local std::string msg;
+    switch (code) {
+        case SSCS_OK: return "ok";
+        case SSCS_E_INVALID: return "invalid argument";
+        case SSCS_E_NOMEM: msg = "out of memory"; break;
+        case SSCS_E_HIP: msg = "HIP error"; break;
+        case SSCS_E_UNSUPPORTED: return "unsupported";
+        case SSCS_E_DEVICE: msg = "device engine failure"; break;
+        default: return "unknown error";
+    }
+    if (!g_last_hip.empty()) msg += ": " + g_last_hip;
+    return msg.c_str();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched
+
+struct sscs_batch {
+    hipStream_t stream = nullptr;
+    sscs_settings st{};
+    int count = 0;
+    std::vector<Inst> inst;
+    std::vector<size_t> off_x, off_y, off_u;     // packed offsets
+    size_t tot_x = 0, tot_y = 0, tot_u = 0;
+    double* vecbuf = nullptr;
+    BatchInst* d_insts = nullptr;
+    std::vector<BatchInst> h_insts;
+    double* io = nullptr;        // staging: u0 (tot_u), x, y, s
+    Result* res = nullptr;
+    int* queue = nullptr;
+    int grid = 1;
+    double ticks_per_s = 1e8;
+    double setup_s = 0;
+};
+
+namespace {
+
+}  // namespace
+
+extern "C" {
+
+int sscs_batch_destroy(sscs_batch* bt) {
+    if (!bt) return SSCS_OK;
+    if (bt->stream) hipStreamSynchronize(bt->stream);
+    else hipDeviceSynchronize();
+    for (auto& I : bt->inst) free_instance(I);
+    hipFree(bt->vecbuf); hipFree(bt->d_insts); hipFree(bt->io); hipFree(bt->res); hipFree(bt->queue);
+    delete bt;
+    return SSCS_OK;
+}
+
+int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* cones, const sscs_settings* st,
+                      void* hip_stream, sscs_batch** out) {
+    try {
+        if (!out || count < 1 || !data || !cones) return SSCS_E_INVALID;
+        *out = nullptr;
+        TRY(validate_settings(st));
+        if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
+        for (int i = 0; i < count; ++i) {
+            TRY(validate(&data[i], &cones[i]));
+            for (int j = 0; j < cones[i].ns; ++j)
+                if (cones[i].s[j] > 64) return SSCS_E_UNSUPPORTED;
+        }
+        const double t0 = now_s();
+        sscs_batch* bt = new (std::nothrow) sscs_batch();
+        if (!bt) return SSCS_E_NOMEM;
+        bt->stream = (hipStream_t)hip_stream;
+        bt->st = *st;
+        bt->count = count;
+        bt->inst.resize(count);
+        int r = SSCS_OK;
+        for (int i = 0; i < count && r == SSCS_OK; ++i) {
+            const bool share = i > 0 && data[i].rowptr == data[0].rowptr && data[i].colind == data[0].colind &&
+                               data[i].val == data[0].val && data[i].m == data[0].m && data[i].n == data[0].n;
+            r = upload_instance(bt->inst[i], &data[i], &cones[i], bt->stream, share ? &bt->inst[0] : nullptr);
+        }
+        size_t tot = 0;
+        for (int i = 0; i < count && r == SSCS_OK; ++i) {
+            const Inst& I = bt->inst[i];
+            bt->off_x.push_back(bt->tot_x); bt->tot_x += I.n;
+            bt->off_y.push_back(bt->tot_y); bt->tot_y += I.m;
+            bt->off_u.push_back(bt->tot_u); bt->tot_u += I.N;
+            tot += vec_doubles(I.n, I.m, st->mem);
+        }
+        if (r == SSCS_OK) r = dmalloc(&bt->vecbuf, tot);
+        if (r == SSCS_OK) r = dmalloc(&bt->io, bt->tot_u + bt->tot_x + 2 * bt->tot_y);
+        if (r == SSCS_OK) r = dmalloc(&bt->res, count);
+        if (r == SSCS_OK) r = dmalloc(&bt->queue, 1);
+        if (r == SSCS_OK) r = dmalloc(&bt->d_insts, count);
+        // PSD scratch: one workgroup owns an instance at a time, so each instance
+        // with PSD blocks gets its own (the batched engine allows orders <= 64)
+        for (int i = 0; i < count && r == SSCS_OK; ++i) {
+            Inst& I = bt->inst[i];
+            if (I.K.ns > 0) {
+                const size_t k = I.K.psd_kmax;
+                r = dmalloc(&I.K.psd_scratch, 2 * k * k + k * (k + 1));
+            }
+        }
+        if (r == SSCS_OK) {
+            bt->h_insts.resize(count);
+            double* p = bt->vecbuf;
+            for (int i = 0; i < count; ++i) {
+                const Inst& I = bt->inst[i];
+                bt->h_insts[i].P = make_prob(I);
+                bt->h_insts[i].V = carve(p, I.n, I.m, st->mem);
+                p += vec_doubles(I.n, I.m, st->mem);
+            }
+            hipError_t e = hipMemcpyAsync(bt->d_insts, bt->h_insts.data(), count * sizeof(BatchInst),
+                                          hipMemcpyHostToDevice, bt->stream);
+            if (e != hipSuccess) { g_last_hip = hipGetErrorString(e); r = SSCS_E_HIP; }
+        }
+        if (r == SSCS_OK) {
+            int dev = 0, ncu = 0, occ = 0, rate = 0;
+            hipGetDevice(&dev);
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_batch, kBatchBlock, 0);
+            hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
+            bt->ticks_per_s = rate > 0 ? rate * 1000.0 : 1e8;
+            bt->grid = std::max(1, std::min(count, ncu * std::max(1, occ)));
+            hipError_t e = hipStreamSynchronize(bt->stream);
+            if (e != hipSuccess) { g_last_hip = hipGetErrorString(e); r = SSCS_E_HIP; }
+        }
+        if (r != SSCS_OK) { sscs_batch_destroy(bt); return r; }
+        bt->setup_s = now_s() - t0;
+        *out = bt;
+        return SSCS_OK;
+    } catch (...) {
+        return SSCS_E_NOMEM;
+    }
+}
+
+int sscs_batch_update_bc(sscs_batch* bt, const double* b_packed, const double* c_packed) {
+    if (!bt || !b_packed || !c_packed) return SSCS_E_INVALID;
+    const hipMemcpyKind kind = bt->st.data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int i = 0; i < bt->count; ++i) {
+        Inst& I = bt->inst[i];
+        HIP_TRY(hipMemcpyAsync(I.b, b_packed + bt->off_y[i], I.m * sizeof(double), kind, bt->stream));
+        HIP_TRY(hipMemcpyAsync(I.c, c_packed + bt->off_x[i], I.n * sizeof(double), kind, bt->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    return SSCS_OK;
+}
+
+int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, double* y_packed,
+                     double* s_packed, sscs_info* infos) {
+    if (!bt || !x_packed || !y_packed || !s_packed) return SSCS_E_INVALID;
+    const double t0 = now_s();
+    const bool dev = bt->st.data_on_device != 0;
+    double* dio_u = bt->io;
+    double* dio_x = dio_u + bt->tot_u;
+    double* dio_y = dio_x + bt->tot_x;
+    double* dio_s = dio_y + bt->tot_y;
+    const double* du0 = nullptr;
+    if (u0_packed) {
+        if (dev) du0 = u0_packed;
+        else {
+            HIP_TRY(hipMemcpyAsync(dio_u, u0_packed, bt->tot_u * sizeof(double), hipMemcpyHostToDevice, bt->stream));
+            du0 = dio_u;
+        }
+    }
+    double* ox = dev ? x_packed : dio_x;
+    double* oy = dev ? y_packed : dio_y;
+    double* os = dev ? s_packed : dio_s;
+    for (int i = 0; i < bt->count; ++i) {
+        Vecs& V = bt->h_insts[i].V;
+        V.u0 = du0 ? du0 + bt->off_u[i] : nullptr;
+        V.out_x = ox + bt->off_x[i];
+        V.out_y = oy + bt->off_y[i];
+        V.out_s = os + bt->off_y[i];
+        V.tr_res = nullptr; V.tr_kind = nullptr; V.tr_ls = nullptr; V.tr_cap = 0;
+    }
+    HIP_TRY(hipMemcpyAsync(bt->d_insts, bt->h_insts.data(), bt->count * sizeof(BatchInst), hipMemcpyHostToDevice,
+                           bt->stream));
+    HIP_TRY(hipMemsetAsync(bt->queue, 0, sizeof(int), bt->stream));
+    Params S = make_params(bt->st, bt->ticks_per_s);
+    k_solve_batch<<<bt->grid, kBatchBlock, 0, bt->stream>>>(bt->d_insts, bt->count, S, bt->res, bt->queue);
+    HIP_TRY(hipGetLastError());
+    if (!dev) {
+        HIP_TRY(hipMemcpyAsync(x_packed, dio_x, bt->tot_x * sizeof(double), hipMemcpyDeviceToHost, bt->stream));
+        HIP_TRY(hipMemcpyAsync(y_packed, dio_y, bt->tot_y * sizeof(double), hipMemcpyDeviceToHost, bt->stream));
+        HIP_TRY(hipMemcpyAsync(s_packed, dio_s, bt->tot_y * sizeof(double), hipMemcpyDeviceToHost, bt->stream));
+    }
+    std::vector<Result> r(bt->count);
+    HIP_TRY(hipMemcpyAsync(r.data(), bt->res, bt->count * sizeof(Result), hipMemcpyDeviceToHost, bt->stream));
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    const double el = now_s() - t0;
+    if (infos)
+        for (int i = 0; i < bt->count; ++i) fill_info(&infos[i], r[i], bt->setup_s, el);
+    return SSCS_OK;
+}
+
+}  // extern "C"

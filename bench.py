@@ -1,0 +1,175 @@
+"""Throughput of the SuperSCS hot path on one MI355X.
+
+A step is one complete solve (Algorithm 1 to pr, dr, gap <= 1e-6) of the
+sparse SOCP workload: n = 20000, m = 50000, A at density 1e-3 with N(0,1)
+values, K = zero 1000 + R+ 20000 + second-order cones of sizes uniform in
+[3, 50], planted primal-dual optimum, Anderson memory 5, FP64.  The instance
+is resident in HBM before timing; outputs go to device buffers.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(the persistent solve kernel) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solves/s to 1e-6 residual; CG SpMV HBM GB/s; learned+batched vs plain"
+
+
+def spmv_bytes(nnz, rows, cols, bval=8):
+    """Algorithmic bytes of one CSR SpMV: values + column indices, row
+    pointers, the input vector read once and the output written once."""
+    return nnz * (bval + 4) + 4 * (rows + 1) + bval * (cols + rows)
+
+
+def cg_op_bytes(nnz, m, n, bval=8):
+    """One application of I + A^T A: SpMV by A and by A^T plus a fused pass
+    over about ten n-vectors."""
+    return spmv_bytes(nnz, m, n, bval) + spmv_bytes(nnz, n, m, bval) + 10 * n * bval
+
+
+def op_units(info):
+    """CG-operator equivalents one solve launch processes: every CG iteration
+    is one; every linear step adds two (right-hand side, initial residual and
+    the y-part product); every termination check adds one (A x and A^T y)."""
+    iters = info["iters"] + 1
+    linear_steps = iters + (info["iters"] - info["k0"])
+    return info["cg_iters"] + 2 * linear_steps + iters
+
+
+def cpu_baseline(prob, gpu_iters, budget_iters=20):
+    """The oracle (FP64 direct factorisation) on a bounded sample: the
+    factorisation plus `budget_iters` iterations of Algorithm 1, extrapolated
+    to the GPU's iteration count."""
+    from oracle import superscs as S
+    from oracle.linsys import DirectLinSys
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas_threads = max([d.get("num_threads", 1) for d in info] or [1])
+    except Exception:
+        blas_threads = None
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    lin = DirectLinSys(prob.A, prob.b, prob.c)
+    t_factor = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    res = S.solve(prob, S.Settings(direction="aa", mem=5, max_iters=budget_iters), lin=lin, record=False)
+    t_iters = time.perf_counter() - t1
+    per_iter = t_iters / max(1, res.iters)
+    est = t_factor + per_iter * max(1, gpu_iters)
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": int(blas_threads or cores), "kind": "oracle",
+            "sample": (f"dense Cholesky of I + A^T A ({t_factor:.1f} s) + {res.iters} iterations "
+                       f"({per_iter:.3f} s each), extrapolated to {gpu_iters} iterations; "
+                       f"{cores} host cores in affinity set")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--max-iters", type=int, default=20000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the solver has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1903_06477_amd import generators as G
+    from paper_1903_06477_amd import sscs
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    prob = G.config2_socp()
+    n, m, nnz = prob.n, prob.m, prob.A.nnz
+    stream = torch.cuda.current_stream()
+    st = sscs.Settings(direction="aa", mem=5, eps=1e-6, cg_tol=1e-10, cg_max=500,
+                       max_iters=args.max_iters, data_on_device=True)
+    solver = sscs.Solver(prob, st, stream=stream.cuda_stream)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    y = torch.empty(m, dtype=torch.float64, device=dev)
+    s = torch.empty(m, dtype=torch.float64, device=dev)
+
+    for _ in range(args.warmup):
+        solver.solve(out=(x, y, s))
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        infos.append(solver.solve(out=(x, y, s))[3])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+
+    solved = all(i["status"] == sscs.SOLVED for i in infos)
+    ms_per_step = wall * 1e3 / args.steps
+    value = args.steps / wall if solved else 0.0
+    # roofline of the solve kernel: CG-operator equivalents x bytes per operator
+    units = np.mean([op_units(i) for i in infos])
+    bytes_per_launch = units * cg_op_bytes(nnz, m, n)
+    kernel_ms = ev_ms / args.steps
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    # stand-alone SpMV of the CG (same kernel code), device-resident, event-timed
+    reps = 200
+    ms_a = solver.spmv_bench(False, reps) / reps
+    ms_t = solver.spmv_bench(True, reps) / reps
+    gbs_a = spmv_bytes(nnz, m, n) / (ms_a * 1e-3) / 1e9
+    gbs_t = spmv_bytes(nnz, n, m) / (ms_t * 1e-3) / 1e9
+    # accuracy of the timed solve, recomputed on the host in FP64
+    xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), s.cpu().numpy()
+    pr = float(np.linalg.norm(prob.A @ xh + sh - prob.b) / (1 + np.linalg.norm(prob.b)))
+    dr = float(np.linalg.norm(prob.A.T @ yh + prob.c) / (1 + np.linalg.norm(prob.c)))
+    pstar = float(prob.c @ prob.x_star)
+    obj_err = abs(float(prob.c @ xh) - pstar) / (1 + abs(pstar))
+    last = infos[-1]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sparse SOCP n=20000 m=50000 density 1e-3, zero 1000 + R+ 20000 + "
+                               f"{len(prob.cone.q)} SOC (sizes 3..50), planted optimum, AA mem 5, eps 1e-6",
+                   "n": n, "m": m, "nnz": int(nnz), "parallelism": "single GPU"},
+        "iterations_per_s": last["iters"] * value,
+        "solve": {"iters": last["iters"], "cg_iters": last["cg_iters"], "k0": last["k0"], "k1": last["k1"],
+                  "k2": last["k2"], "km": last["km"], "backtracks": last["backtracks"],
+                  "pr": pr, "dr": dr, "gap": last["gap"], "obj_err_vs_planted": obj_err},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_solve_grid", "kernel_ms": kernel_ms,
+                     "bytes_per_launch": bytes_per_launch, "cg_op_units": units},
+        "spmv": {"A_us": ms_a * 1e3, "A_GBs": gbs_a, "At_us": ms_t * 1e3, "At_GBs": gbs_t,
+                 "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, last["iters"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -33,6 +33,7 @@ struct Shared {
     double W[MEMMAX * MEMMAX];  // restarted Broyden inner products <z_i, zt_j>
     double coef[4 * MEMMAX + 8];
     double L[MEMMAX * MEMMAX];  // small factorisations (one thread)
+    double term[12];            // termination measures of the current iteration
     int    qhead;               // batched engine: instance popped from the queue
 };
 
@@ -56,7 +57,20 @@ __device__ __forceinline__ double block_total(const Shared& sh, int k) {
     return s;
 }
 
+// The rows of one matrix (A or A^T) that a workgroup owns, and where they
+// live: in global memory, or copied into the workgroup's LDS (offsets in bytes
+// into the dynamic LDS segment) for the lifetime of a persistent kernel.
+struct MatPart {
+    int r0, rows;     // first global row, row count
+    int lds;          // 1: values, column indices and row pointers are in LDS
+    int off_v, off_ci, off_rp;
+};
+
+extern __shared__ __attribute__((aligned(16))) double sscs_dyn_lds[];
+
 struct BlockTeam {
+    static constexpr bool kLds = false;
+    MatPart mp[2];    // A, A^T: all rows, global memory
     __device__ int rank() const { return threadIdx.x; }
     __device__ int size() const { return blockDim.x; }
     __device__ int wave() const { return threadIdx.x / WAVE; }
@@ -72,17 +86,50 @@ struct BlockTeam {
     }
 };
 
-// Grid barrier on a monotonically increasing 64-bit arrival counter.  Every
-// workgroup of the cooperative grid passes the same number of barriers, so the
-// k-th barrier completes when the counter reaches k * gridDim.x.  A wait that
-// exceeds `timeout_ticks` of the 100 MHz wall clock raises the abort flag; all
-// later barriers then return at once, so every wave of the grid still reaches
-// the kernel's end.
+// Words of the grid barrier, each on its own 128-byte line: the global
+// arrival counter, then one arrival counter and one release word per group.
+constexpr int BAR_STRIDE = 16;
+constexpr int BAR_GROUPS = 8;
+constexpr int BAR_WORDS = BAR_STRIDE * (1 + 2 * BAR_GROUPS);
+
+// Waits with relaxed loads (an acquiring load per poll would invalidate the
+// caches the rest of the grid is working from) and acquires once at the end.
+__device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned long long target, int* abort_flag,
+                                           long long timeout_ticks) {
+    const long long t0 = wall_clock64();
+    bool ok = true;
+    while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = false; break; }
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > timeout_ticks) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+// Two-level grid barrier.  Workgroups are grouped by blockIdx % 8, which is
+// how the dispatcher spreads workgroups over the eight XCDs, so each group's
+// counter is hammered by one XCD only.  The last arrival of a group bumps the
+// global counter, waits for all groups, then releases its group through the
+// group's release word.  All counters grow monotonically (the k-th barrier
+// completes at k * members), so nothing is reset inside the kernel.  Arrivals
+// are release and waits acquire (agent scope), which orders every write made
+// before the barrier by the workgroup (joined by __syncthreads) before every
+// read after it.  A wait that exceeds `timeout_ticks` of the wall clock raises
+// the abort flag; later barriers then return at once, so every wave of the
+// grid still reaches the kernel's end.
+template <bool LDS>
 struct GridTeam {
-    unsigned long long* bar;
+    static constexpr bool kLds = LDS;   // operator rows held in LDS
+    MatPart mp[2];              // this workgroup's rows of A and A^T
+    unsigned long long* bar;    // BAR_WORDS words, zero at launch
     int* abort_flag;
     double* part;               // [2][KMAX][gridDim.x] partials
-    unsigned long long epoch;   // barriers passed so far, times gridDim.x
+    unsigned long long k;       // barriers passed so far
     long long timeout_ticks;
     int flip;
 
@@ -99,20 +146,23 @@ struct GridTeam {
 
     __device__ void sync() {
         __syncthreads();
-        epoch += gridDim.x;
+        ++k;
         if (threadIdx.x == 0) {
-            __threadfence();
-            __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > timeout_ticks) {
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
+            const unsigned G = gridDim.x;
+            const unsigned ng = G < BAR_GROUPS ? G : BAR_GROUPS;
+            const unsigned grp = blockIdx.x % ng;
+            const unsigned long long members = (G - grp + ng - 1) / ng;
+            unsigned long long* cnt = bar + BAR_STRIDE * (1 + grp);
+            unsigned long long* rel = bar + BAR_STRIDE * (1 + BAR_GROUPS + grp);
+            const unsigned long long old =
+                __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 == k * members) {
+                __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                spin_until(bar, k * ng, abort_flag, timeout_ticks);
+                __hip_atomic_store(rel, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                spin_until(rel, k, abort_flag, timeout_ticks);
             }
-            __threadfence();
         }
         __syncthreads();
     }
@@ -147,23 +197,140 @@ struct Csr {
     int rows, cols, seg;
 };
 
-// Row-segmented SpMV over the team: for every row r, f(r, sum_k v[k] x[ci[k]])
+// Row-segmented SpMV over the team: for every row r, f(r, sum_k v[k] gx(ci[k]))
 // is called by the first lane of the segment that owns r.  Segments of `seg`
-// consecutive lanes stride the row's nonzeros, so loads of ci and v coalesce;
-// the segment sum is a butterfly over the segment's lanes.
-template <typename Team, typename T, typename TX, typename F>
-__device__ __forceinline__ void spmv_rows(Team& tm, const Csr<T>& M, const TX* __restrict__ x, F&& f) {
+// consecutive lanes stride a row's nonzeros, so loads of ci and v coalesce;
+// each segment keeps ROWS rows in flight at once (independent load chains,
+// which is what hides the memory latency of a persistent kernel; the CG's
+// products use four, the other passes one), and each
+// row's sum is a butterfly over the segment's lanes.  gx(c) returns the
+// input vector's entry c, so callers can gather values formed on the fly.
+template <int ROWS, typename Team, typename T, typename Gx, typename F>
+__device__ __forceinline__ void spmv_gather(Team& tm, const Csr<T>& M, Gx&& gx, F&& f) {
     const int S = M.seg;
     const int seg = tm.rank() / S;
     const int nseg = tm.size() / S;
     const int ls = tm.rank() & (S - 1);
-    for (int r = seg; r < M.rows; r += nseg) {
-        const int k1 = M.rp[r + 1];
-        double acc = 0.0;
-        for (int k = M.rp[r] + ls; k < k1; k += S) acc += (double)M.v[k] * (double)x[M.ci[k]];
-        for (int off = S >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, WAVE);
-        if (ls == 0) f(r, acc);
+    for (int r0 = seg; r0 < M.rows; r0 += ROWS * nseg) {
+        int kb[ROWS], ke[ROWS];
+        double acc[ROWS];
+#pragma unroll
+        for (int q = 0; q < ROWS; ++q) {
+            const int r = r0 + q * nseg;
+            const bool in = r < M.rows;
+            kb[q] = in ? M.rp[r] + ls : 0;
+            ke[q] = in ? M.rp[r + 1] : 0;
+            acc[q] = 0.0;
+        }
+        bool more = true;
+        while (more) {
+            more = false;
+#pragma unroll
+            for (int q = 0; q < ROWS; ++q) {
+                if (kb[q] < ke[q]) {
+                    acc[q] += (double)M.v[kb[q]] * (double)gx(M.ci[kb[q]]);
+                    kb[q] += S;
+                    more = true;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ROWS; ++q) {
+            double a = acc[q];
+            for (int off = S >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, WAVE);
+            const int r = r0 + q * nseg;
+            if (ls == 0 && r < M.rows) f(r, a);
+        }
     }
+}
+
+template <typename Team, typename T, typename TX, typename F>
+__device__ __forceinline__ void spmv_rows(Team& tm, const Csr<T>& M, const TX* __restrict__ x, F&& f) {
+    spmv_gather<1>(tm, M, [&](int c) { return x[c]; }, f);
+}
+
+// Team SpMV over the rows a workgroup owns (MatPart): for every owned row r,
+// f(r, sum_k v[k] gx(ci[k])) is called by the first lane of the segment that
+// owns r.  Same segment scheme and ROWS-way batching as spmv_gather, with the
+// row range local to the workgroup and the operator read from LDS when cached.
+template <int ROWS, bool LDS, typename Gx, typename F>
+__device__ __forceinline__ void spmv_part_impl(const Csr<double>& M, const MatPart& mp, Gx&& gx, F&& f) {
+    const int S = M.seg;
+    const int seg = threadIdx.x / S;
+    const int nseg = blockDim.x / S;
+    const int ls = threadIdx.x & (S - 1);
+    const char* lds = reinterpret_cast<const char*>(sscs_dyn_lds);
+    const double* lv = reinterpret_cast<const double*>(lds + mp.off_v);
+    const int* lci = reinterpret_cast<const int*>(lds + mp.off_ci);
+    const int* lrp = reinterpret_cast<const int*>(lds + mp.off_rp);
+    for (int l0 = seg; l0 < mp.rows; l0 += ROWS * nseg) {
+        int kb[ROWS], ke[ROWS];
+        double acc[ROWS];
+#pragma unroll
+        for (int q = 0; q < ROWS; ++q) {
+            const int l = l0 + q * nseg;
+            const bool in = l < mp.rows;
+            if (LDS) {
+                kb[q] = in ? lrp[l] + ls : 0;
+                ke[q] = in ? lrp[l + 1] : 0;
+            } else {
+                kb[q] = in ? M.rp[mp.r0 + l] + ls : 0;
+                ke[q] = in ? M.rp[mp.r0 + l + 1] : 0;
+            }
+            acc[q] = 0.0;
+        }
+        bool more = true;
+        while (more) {
+            more = false;
+#pragma unroll
+            for (int q = 0; q < ROWS; ++q) {
+                if (kb[q] < ke[q]) {
+                    const double v = LDS ? lv[kb[q]] : M.v[kb[q]];
+                    const int c = LDS ? lci[kb[q]] : M.ci[kb[q]];
+                    acc[q] += v * (double)gx(c);
+                    kb[q] += S;
+                    more = true;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ROWS; ++q) {
+            double a = acc[q];
+            for (int off = S >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, WAVE);
+            const int l = l0 + q * nseg;
+            if (ls == 0 && l < mp.rows) f(mp.r0 + l, a);
+        }
+    }
+}
+
+template <int ROWS, typename Team, typename Gx, typename F>
+__device__ __forceinline__ void spmv_part(Team& tm, const Csr<double>& M, int which, Gx&& gx, F&& f) {
+    spmv_part_impl<ROWS, Team::kLds>(M, tm.mp[which], gx, f);
+}
+
+// Fills a workgroup's MatPart for rows [part[b], part[b+1]) and, when `cache`
+// is set, copies those rows into LDS starting at byte offset `*lds_off`.
+__device__ inline void load_part(MatPart& mp, const Csr<double>& M, const int* part, int b, bool cache, int* lds_off) {
+    const int r0 = part[b], r1 = part[b + 1];
+    mp.r0 = r0;
+    mp.rows = r1 - r0;
+    mp.lds = cache ? 1 : 0;
+    if (!cache) { mp.off_v = mp.off_ci = mp.off_rp = 0; return; }
+    const int k0 = M.rp[r0], k1 = M.rp[r1];
+    const int nnz = k1 - k0;
+    mp.off_v = *lds_off;
+    mp.off_ci = mp.off_v + 8 * nnz;
+    mp.off_rp = mp.off_ci + 4 * nnz;
+    *lds_off = (mp.off_rp + 4 * (mp.rows + 1) + 15) & ~15;
+    char* lds = reinterpret_cast<char*>(sscs_dyn_lds);
+    double* lv = reinterpret_cast<double*>(lds + mp.off_v);
+    int* lci = reinterpret_cast<int*>(lds + mp.off_ci);
+    int* lrp = reinterpret_cast<int*>(lds + mp.off_rp);
+    for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
+        lv[k] = M.v[k0 + k];
+        lci[k] = M.ci[k0 + k];
+    }
+    for (int l = threadIdx.x; l <= mp.rows; l += blockDim.x) lrp[l] = M.rp[r0 + l] - k0;
 }
 
 }  // namespace sscs

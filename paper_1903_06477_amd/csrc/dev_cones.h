@@ -47,7 +47,7 @@ __device__ __forceinline__ double exp_h_scaled(double rho, double t0, double s0,
     return ((rho - 1.0) * r0 + s0) * exp(2.0 * rho) - (r0 - rho * s0) - q * t0 * exp(rho);
 }
 
-__device__ inline void proj_exp_primal(double t0, double s0, double r0, double* p) {
+__device__ __noinline__ void proj_exp_primal(double t0, double s0, double r0, double* p) {
     const double eps = DBL_EPSILON;
     // inside K_e (points within rounding of the boundary count as inside)
     if (s0 > 0.0) {
@@ -157,7 +157,7 @@ __device__ inline void proj_exp_dual(const double* v, double* out) {
 // each sweep visits every pair (p, q) once in round-robin order, k/2 disjoint
 // rotations per round in parallel.
 template <typename Team>
-__device__ void psd_project_block(Team& tm, int k, double* a, double* vm, const double* in, double* outv) {
+__device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, double* vm, const double* in, double* outv) {
     const int t = threadIdx.x, nt = blockDim.x;
     const double rs2 = 0.70710678118654752440;
     // unpack: column-major lower triangle, off-diagonals scaled by sqrt(2)

@@ -32,6 +32,9 @@ struct Prob {
     const double* c;
     const double* dinv;     // 1 / (1 + ||A e_j||^2), Jacobi preconditioner of I + A^T A
     const double* g;        // M^{-1} (c, b), length n + m
+    const int* partA;       // row partition of A over the workgroups of a grid (G + 1)
+    const int* partAt;      // row partition of A^T
+    int lds_cache;          // grid kernels keep their rows of A and A^T in LDS
     double delta;           // 1 + (c, b)^T g
     double nb, nc;          // ||b||, ||c||
     ConeDev K;
@@ -40,7 +43,8 @@ struct Prob {
 struct Vecs {
     double *u, *ut, *ub, *Ru, *d, *dt, *Rw, *pz, *pxi;   // length N
     double *xw_u, *xw_d;                                 // CG warm starts, length n
-    double *cg_b, *cg_r, *cg_z, *cg_p, *cg_q;            // length n
+    double *cg_b, *cg_u, *cg_w, *cg_p;                   // length n
+    double *cg_r[2], *cg_s[2];                           // length n, double-buffered
     double *cg_t;                                        // length m
     double *Zb, *Yb;                                     // mem x N memory buffers
     const double* u0;                                    // warm start or null
@@ -70,74 +74,102 @@ struct Result {
 
 // out[0 .. n+m) = M^{-1} r[0 .. n+m), warm-starting CG from xw (updated in place).
 // Leaves h^T M^{-1} r in sh.out[0]; returns the CG iteration count.
+//
+// The CG on K = I + A^T A (Jacobi preconditioner D) is the single-reduction
+// (Chronopoulos-Gear) recurrence: with u = D r and w = K u,
+//   gamma = <r, u>, delta = <w, u>,  beta = gamma / gamma_old,
+//   alpha = gamma / (delta - beta gamma / alpha_old),
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s.
+// One iteration is two team-wide phases:
+//   X: element owners update p, s, x, r, u; the owners of the rows of A form
+//      t = A u_new, gathering u_new,k = D_k (r_k - alpha (w_k + beta s_k))
+//      from the previous r and s (double-buffered, so nothing is read after
+//      it is overwritten) -- no barrier is needed between the update and the
+//      product;
+//   Y: the owners of the rows of A^T form w = u + A^T t and the partial sums
+//      of gamma, delta and ||r||^2; one reduction.
+// so each iteration costs two barriers.  The first pass runs with alpha = 0,
+// p = s = 0, which turns phase X into the initial u = D r0, t = A u.
 template <typename Team>
 __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit) {
     const int n = P.n;
     // rhs = rx - A^T ry ; t = A xw
-    spmv_rows(tm, P.At, r + n, [&](int j, double s) { V.cg_b[j] = r[j] - s; });
-    spmv_rows(tm, P.A, xw, [&](int i, double s) { V.cg_t[i] = s; });
-    tm.sync();
-    // r = rhs - (xw + A^T t) ; z = Dinv r ; p = z
-    double a_rz = 0.0, a_bb = 0.0, a_rr = 0.0;
-    spmv_rows(tm, P.At, V.cg_t, [&](int j, double s) {
-        const double bj = V.cg_b[j];
-        const double rj = bj - (xw[j] + s);
-        const double zj = P.dinv[j] * rj;
-        V.cg_r[j] = rj;
-        V.cg_z[j] = zj;
-        V.cg_p[j] = zj;
-        a_rz += rj * zj;
+    double a_bb = 0.0;
+    spmv_part<1>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; }, [&](int j, double s) {
+        const double bj = r[j] - s;
+        V.cg_b[j] = bj;
         a_bb += bj * bj;
-        a_rr += rj * rj;
     });
-    put(sh, 0, a_rz);
-    put(sh, 1, a_bb);
-    put(sh, 2, a_rr);
-    tm.reduce(sh, 3);
-    double rz = sh.out[0];
-    const double thr = tol * tol * sh.out[1];
-    double rr = sh.out[2];
-    double beta = 0.0;
-    int it = 0;
-    while (rr > thr && it < maxit && !tm.aborted()) {
-        // t = A z + beta t (= A p by linearity) ; p = z + beta p
-        spmv_rows(tm, P.A, V.cg_z, [&](int i, double s) { V.cg_t[i] = s + beta * V.cg_t[i]; });
-        if (it > 0)
-            for (int j = tm.rank(); j < n; j += tm.size()) V.cg_p[j] = V.cg_z[j] + beta * V.cg_p[j];
-        tm.sync();
-        // q = p + A^T t ; <p, q>
-        double a_pq = 0.0;
-        spmv_rows(tm, P.At, V.cg_t, [&](int j, double s) {
-            const double pj = V.cg_p[j];
-            const double qj = pj + s;
-            V.cg_q[j] = qj;
-            a_pq += pj * qj;
-        });
-        put(sh, 0, a_pq);
-        tm.reduce(sh, 1);
-        const double alpha = rz / sh.out[0];
-        double a_rz2 = 0.0, a_rr2 = 0.0;
+    spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
+    tm.sync();
+    // r0 = rhs - (xw + A^T t) into buffer 0; u = w = p = s = 0
+    spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; }, [&](int j, double s) {
+        V.cg_r[0][j] = V.cg_b[j] - (xw[j] + s);
+        V.cg_s[0][j] = 0.0;
+        V.cg_u[j] = 0.0;
+        V.cg_w[j] = 0.0;
+        V.cg_p[j] = 0.0;
+    });
+    tm.sync();
+    double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0, thr = 0.0;
+    int it = 0, cur = 0;
+    for (int pass = 0;; ++pass) {
+        // ---- phase X
+        const double* r_o = V.cg_r[cur];
+        const double* s_o = V.cg_s[cur];
+        double* r_n = V.cg_r[cur ^ 1];
+        double* s_n = V.cg_s[cur ^ 1];
         for (int j = tm.rank(); j < n; j += tm.size()) {
-            xw[j] += alpha * V.cg_p[j];
-            const double rj = V.cg_r[j] - alpha * V.cg_q[j];
-            const double zj = P.dinv[j] * rj;
-            V.cg_r[j] = rj;
-            V.cg_z[j] = zj;
-            a_rz2 += rj * zj;
-            a_rr2 += rj * rj;
+            const double pj = V.cg_u[j] + beta * V.cg_p[j];
+            const double sj = V.cg_w[j] + beta * s_o[j];
+            const double rj = r_o[j] - alpha * sj;
+            xw[j] += alpha * pj;
+            V.cg_p[j] = pj;
+            s_n[j] = sj;
+            r_n[j] = rj;
+            V.cg_u[j] = P.dinv[j] * rj;
         }
-        put(sh, 0, a_rz2);
-        put(sh, 1, a_rr2);
-        tm.reduce(sh, 2);
-        beta = sh.out[0] / rz;
-        rz = sh.out[0];
-        rr = sh.out[1];
+        spmv_part<4>(tm, P.A, 0,
+                    [&](int c) { return P.dinv[c] * (r_o[c] - alpha * (V.cg_w[c] + beta * s_o[c])); },
+                    [&](int i, double acc) { V.cg_t[i] = acc; });
+        tm.sync();
+        cur ^= 1;
+        // ---- phase Y
+        double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
+        spmv_part<4>(tm, P.At, 1, [&](int c) { return V.cg_t[c]; }, [&](int j, double s) {
+            const double uj = V.cg_u[j];
+            const double rj = V.cg_r[cur][j];
+            const double wj = uj + s;
+            V.cg_w[j] = wj;
+            a_g += rj * uj;
+            a_d += wj * uj;
+            a_rr += rj * rj;
+        });
+        put(sh, 0, a_g);
+        put(sh, 1, a_d);
+        put(sh, 2, a_rr);
+        if (pass == 0) put(sh, 3, a_bb);
+        tm.reduce(sh, pass == 0 ? 4 : 3);
+        const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
+        if (pass == 0) thr = tol * tol * sh.out[3];
+        if (!(rr > thr) || it >= maxit || tm.aborted()) break;
+        double den = delta;
+        if (pass == 0) {
+            beta = 0.0;
+        } else {
+            beta = gamma / gamma_old;
+            den = delta - beta * gamma / alpha_old;
+        }
+        if (!(gamma > 0.0) || !(den > 0.0)) break;      // breakdown: residual at rounding level
+        alpha = gamma / den;
+        gamma_old = gamma;
+        alpha_old = alpha;
         ++it;
     }
     // py = ry + A px ; h^T p
     double a_hp = 0.0;
-    spmv_rows(tm, P.A, xw, [&](int i, double s) {
+    spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) {
         const double py = r[n + i] + s;
         out[n + i] = py;
         a_hp += P.b[i] * py;
@@ -210,24 +242,26 @@ __device__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs&
 struct Term {
     double pr, dr, gap, ic, uc, pobj, dobj, tau, cx, by;
     int status;
-    bool timeout;
+    int timeout;
 };
 
 // Sec. IV-C.  sig-bar = psi-bar - 2 psi~ + psi; candidate (chi, psi, sig)-bar / tau-bar.
+// The measures land in sh.term (LDS), read by every thread after the call,
+// which keeps them out of the registers of the long-lived solve loop.
 template <typename Team>
-__device__ Term termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+__device__ void termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
                                  bool timed_out) {
     const int n = P.n, m = P.m;
     const double tau = V.ub[P.N - 1];
     double a_p = 0.0, a_u = 0.0, a_d = 0.0, a_i = 0.0, a_cx = 0.0, a_by = 0.0;
-    spmv_rows(tm, P.A, V.ub, [&](int i, double s) {
+    spmv_part<1>(tm, P.A, 0, [&](int c_) { return V.ub[c_]; }, [&](int i, double s) {
         const double sig = V.ub[n + i] - 2.0 * V.ut[n + i] + V.u[n + i];
         const double v = s + sig;
         a_u += v * v;
         const double w = v - P.b[i] * tau;
         a_p += w * w;
     });
-    spmv_rows(tm, P.At, V.ub + n, [&](int j, double s) {
+    spmv_part<1>(tm, P.At, 1, [&](int c_) { return V.ub[n + c_]; }, [&](int j, double s) {
         a_i += s * s;
         const double w = s + P.c[j] * tau;
         a_d += w * w;
@@ -242,28 +276,31 @@ __device__ Term termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs
     put(sh, 5, a_by);
     put(sh, 6, (tm.rank() == 0 && timed_out) ? 1.0 : 0.0);
     tm.reduce(sh, 7);
-    Term T;
-    const double cx = sh.out[4], by = sh.out[5];
-    T.tau = tau;
-    T.cx = cx;
-    T.by = by;
-    T.timeout = sh.out[6] > 0.0;
-    T.pr = T.dr = T.gap = T.ic = T.uc = INFINITY;
-    T.pobj = T.dobj = NAN;
-    if (tau > 0.0) {
-        T.pr = sqrt(sh.out[0]) / tau / (1.0 + P.nb);
-        T.dr = sqrt(sh.out[2]) / tau / (1.0 + P.nc);
-        T.gap = fabs(cx + by) / tau / (1.0 + fabs(cx) / tau + fabs(by) / tau);
-        T.pobj = cx / tau;
-        T.dobj = -by / tau;
+    if (threadIdx.x == 0) {
+        Term T;
+        const double cx = sh.out[4], by = sh.out[5];
+        T.tau = tau;
+        T.cx = cx;
+        T.by = by;
+        T.timeout = sh.out[6] > 0.0;
+        T.pr = T.dr = T.gap = T.ic = T.uc = INFINITY;
+        T.pobj = T.dobj = NAN;
+        if (tau > 0.0) {
+            T.pr = sqrt(sh.out[0]) / tau / (1.0 + P.nb);
+            T.dr = sqrt(sh.out[2]) / tau / (1.0 + P.nc);
+            T.gap = fabs(cx + by) / tau / (1.0 + fabs(cx) / tau + fabs(by) / tau);
+            T.pobj = cx / tau;
+            T.dobj = -by / tau;
+        }
+        if (by < 0.0) T.ic = P.nb * sqrt(sh.out[3]) / (-by);
+        if (cx < 0.0) T.uc = P.nc * sqrt(sh.out[1]) / (-cx);
+        T.status = 0;
+        if (tau > 0.0 && T.pr <= S.eps && T.dr <= S.eps && T.gap <= S.eps) T.status = ST_SOLVED;
+        else if (T.ic < S.eps) T.status = ST_INFEASIBLE;
+        else if (T.uc < S.eps) T.status = ST_UNBOUNDED;
+        *reinterpret_cast<Term*>(sh.term) = T;
     }
-    if (by < 0.0) T.ic = P.nb * sqrt(sh.out[3]) / (-by);
-    if (cx < 0.0) T.uc = P.nc * sqrt(sh.out[1]) / (-cx);
-    T.status = 0;
-    if (tau > 0.0 && T.pr <= S.eps && T.dr <= S.eps && T.gap <= S.eps) T.status = ST_SOLVED;
-    else if (T.ic < S.eps) T.status = ST_INFEASIBLE;
-    else if (T.uc < S.eps) T.status = ST_UNBOUNDED;
-    return T;
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ directions
@@ -536,20 +573,22 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     DirState ds = {0, 0, 0, 0};
     double eta0 = 0.0, eta = 0.0, r_safe = 0.0;
     long long k0c = 0, k1c = 0, k2c = 0, kmc = 0, btc = 0, cgc = 0;
-    Term T;
+    const Term& T = *reinterpret_cast<const Term*>(sh.term);
     double nRu = 0.0;
+    int status = 0;
     long long nu = 0;
     for (nu = 0;; ++nu) {
         cgc += linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, S.cg_tol, S.cg_max);
         nRu = sqrt(residual_pass(tm, sh, P, V));
         const bool late = S.max_ticks > 0 && (wall_clock64() - t_start) > S.max_ticks;
-        T = termination_pass(tm, sh, P, V, S, late);
+        termination_pass(tm, sh, P, V, S, late);
         if (nu == 0) eta0 = eta = r_safe = nRu;
-        if (!isfinite(nRu)) T.status = ST_NUMERICAL;
-        if (tm.aborted()) T.status = ST_NUMERICAL;
-        if (!T.status && nu >= S.max_iters) T.status = ST_MAX_ITERS;
-        if (!T.status && T.timeout) T.status = ST_TIME_LIMIT;
-        if (T.status) { write_trace(tm, V, nu, nRu, -1, 0); break; }
+        status = T.status;
+        if (!isfinite(nRu)) status = ST_NUMERICAL;
+        if (tm.aborted()) status = ST_NUMERICAL;
+        if (!status && nu >= S.max_iters) status = ST_MAX_ITERS;
+        if (!status && T.timeout) status = ST_TIME_LIMIT;
+        if (status) { write_trace(tm, V, nu, nRu, -1, 0); break; }
         const bool k0 = nRu <= S.c0 * eta;
         if (S.direction == DIR_AA) {
             direction_aa(tm, sh, P, V, S, ds, k0);
@@ -636,22 +675,22 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     const double nan = NAN;
     for (int j = tm.rank(); j < n; j += tm.size()) {
         double x = nan;
-        if (T.status == ST_UNBOUNDED) x = V.ub[j] / (-T.cx);
-        else if (T.status != ST_INFEASIBLE && tau > 0.0) x = V.ub[j] / tau;
+        if (status == ST_UNBOUNDED) x = V.ub[j] / (-T.cx);
+        else if (status != ST_INFEASIBLE && tau > 0.0) x = V.ub[j] / tau;
         V.out_x[j] = x;
     }
     for (int i = tm.rank(); i < m; i += tm.size()) {
         const double psi = V.ub[n + i];
         const double sig = psi - 2.0 * V.ut[n + i] + V.u[n + i];
         double y = nan, s = nan;
-        if (T.status == ST_INFEASIBLE) y = psi / (-T.by);
-        else if (T.status == ST_UNBOUNDED) s = sig / (-T.cx);
+        if (status == ST_INFEASIBLE) y = psi / (-T.by);
+        else if (status == ST_UNBOUNDED) s = sig / (-T.cx);
         else if (tau > 0.0) { y = psi / tau; s = sig / tau; }
         V.out_y[i] = y;
         V.out_s[i] = s;
     }
     if (tm.rank() == 0) {
-        res->status = T.status;
+        res->status = status;
         res->err = tm.aborted() ? 1 : 0;
         res->iters = nu;
         res->k0 = k0c; res->k1 = k1c; res->k2 = k2c; res->km = kmc; res->bt = btc; res->cg = cgc;

@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -28,7 +29,7 @@ using namespace sscs;
 
 namespace {
 
-constexpr int kBlock = 256;            // threads per workgroup, all kernels of the solver
+constexpr int kBlock = 512;            // threads per workgroup of the grid-team kernels
 constexpr int kBatchBlock = 256;
 
 enum { OP_LINEAR = 0, OP_RESIDUAL = 1, OP_PROJECT = 2, OP_SETUP = 3 };
@@ -54,18 +55,37 @@ struct FlatTeam {
 
 // ------------------------------------------------------------------ kernels
 
+// Workgroup b of a grid kernel owns rows [part[b], part[b+1]) of A and of A^T
+// and, when the operator fits, keeps them in LDS for the whole launch.
+template <bool LDS>
+__device__ inline void grid_team_init(GridTeam<LDS>& tm, const Prob& P) {
+    int off = 0;
+    load_part(tm.mp[0], P.A, P.partA, blockIdx.x, LDS, &off);
+    load_part(tm.mp[1], P.At, P.partAt, blockIdx.x, LDS, &off);
+    __syncthreads();
+}
+
+__device__ inline void block_team_init(BlockTeam& tm, const Prob& P) {
+    tm.mp[0] = MatPart{0, P.A.rows, 0, 0, 0, 0};
+    tm.mp[1] = MatPart{0, P.At.rows, 0, 0, 0, 0};
+}
+
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S, Result* res,
                                                        unsigned long long* bar, int* abort_flag,
                                                        double* part, long long timeout_ticks) {
     __shared__ Shared sh;
-    GridTeam tm{bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    grid_team_init(tm, P);
     sscs::solve(tm, sh, P, V, S, res);
 }
 
+template <bool LDS>
 __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, unsigned long long* bar,
                                                     int* abort_flag, double* part, long long timeout_ticks) {
     __shared__ Shared sh;
-    GridTeam tm{bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    grid_team_init(tm, P);
     const int n = P.n, m = P.m, N = P.N;
     if (a.op == OP_LINEAR) {
         for (int j = tm.rank(); j < n; j += tm.size()) V.xw_d[j] = 0.0;
@@ -112,14 +132,23 @@ __global__ void __launch_bounds__(kBatchBlock) k_solve_batch(const BatchInst* __
     for (;;) {
         if (threadIdx.x == 0) sh.qhead = atomicAdd(queue, 1);
         __syncthreads();
-        const int idx = sh.qhead;
+        const int idx = __builtin_amdgcn_readfirstlane(sh.qhead);
         __syncthreads();
         if (idx >= count) break;
         Prob P = insts[idx].P;
         const Vecs V = insts[idx].V;
+        block_team_init(tm, P);
         setup_gdelta(tm, sh, P, V, const_cast<double*>(P.g), S.setup_tol, S.setup_max);
         sscs::solve(tm, sh, P, V, S, res + idx);
     }
+}
+
+// Algorithm 1 for one instance small enough for a single workgroup.
+__global__ void __launch_bounds__(kBatchBlock) k_solve_block(Prob P, Vecs V, Params S, Result* res) {
+    __shared__ Shared sh;
+    BlockTeam tm;
+    block_team_init(tm, P);
+    sscs::solve(tm, sh, P, V, S, res);
 }
 
 __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __restrict__ y) {
@@ -207,9 +236,14 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Lanes per row of the row-segmented SpMV: the smallest power of two that
+// gives each lane about `div` nonzeros of a mean-length row (more rows in
+// flight per wavefront, several independent loads per lane).
 int pow2_seg(double avg) {
+    double div = 4.0;
+    if (const char* e = std::getenv("SSCS_SEGDIV")) div = std::max(0.25, std::atof(e));   // tuning override
     int s = 1;
-    while (s < 64 && s < avg / 2.0) s <<= 1;
+    while (s < 64 && s < avg / div) s <<= 1;
     return s;
 }
 
@@ -230,6 +264,9 @@ struct Inst {
     int segA = 1, segAt = 1;
     ConeDev K{};
     bool owns_A = true;
+    std::vector<int> h_rpA, h_rpAt;        // host row pointers (partitioning)
+    int *partA = nullptr, *partAt = nullptr;
+    int lds_bytes = 0;                     // dynamic LDS of the grid kernels (0: operator in HBM)
 };
 
 int validate(const sscs_data* d, const sscs_cone* k) {
@@ -379,6 +416,9 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s));
         hipFree(cnt);
+        I.h_rpA.assign(d->rowptr, d->rowptr + I.m + 1);
+        I.h_rpAt.resize(I.n + 1);
+        HIP_TRY(hipMemcpy(I.h_rpAt.data(), I.At_rp, (I.n + 1) * sizeof(int), hipMemcpyDeviceToHost));
     }
     I.segA = pow2_seg((double)d->nnz / std::max(1, I.m));
     I.segAt = pow2_seg((double)d->nnz / std::max(1, I.n));
@@ -412,6 +452,7 @@ void free_instance(Inst& I) {
     hipFree(I.b); hipFree(I.c); hipFree(I.g);
     hipFree(I.qoff); hipFree(I.sord); hipFree(I.soff);
     hipFree(I.K.psd_scratch);
+    hipFree(I.partA); hipFree(I.partAt);
     I = Inst{};
 }
 
@@ -421,6 +462,7 @@ Prob make_prob(const Inst& I) {
     P.A = Csr<double>{I.A_rp, I.A_ci, I.A_v, I.m, I.n, I.segA};
     P.At = Csr<double>{I.At_rp, I.At_ci, I.At_v, I.n, I.m, I.segAt};
     P.b = I.b; P.c = I.c; P.dinv = I.dinv; P.g = I.g;
+    P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.lds_bytes > 0 ? 1 : 0;
     P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
     P.K = I.K;
     return P;
@@ -428,7 +470,7 @@ Prob make_prob(const Inst& I) {
 
 size_t vec_doubles(int n, int m, int mem) {
     const size_t N = (size_t)n + m + 1;
-    return 9 * N + 7 * (size_t)n + (size_t)m + 2 * (size_t)mem * N;
+    return 9 * N + 10 * (size_t)n + (size_t)m + 2 * (size_t)mem * N;
 }
 
 // Carves the Vecs of one instance from a contiguous device buffer.
@@ -440,7 +482,8 @@ Vecs carve(double* base, int n, int m, int mem) {
     V.u = take(N); V.ut = take(N); V.ub = take(N); V.Ru = take(N); V.d = take(N);
     V.dt = take(N); V.Rw = take(N); V.pz = take(N); V.pxi = take(N);
     V.xw_u = take(n); V.xw_d = take(n);
-    V.cg_b = take(n); V.cg_r = take(n); V.cg_z = take(n); V.cg_p = take(n); V.cg_q = take(n);
+    V.cg_b = take(n); V.cg_u = take(n); V.cg_w = take(n); V.cg_p = take(n);
+    V.cg_r[0] = take(n); V.cg_r[1] = take(n); V.cg_s[0] = take(n); V.cg_s[1] = take(n);
     V.cg_t = take(m);
     V.Zb = take((size_t)mem * N); V.Yb = take((size_t)mem * N);
     return V;
@@ -467,7 +510,7 @@ struct sscs_work {
     int* tr_ls = nullptr;
     long long tr_cap = 0;
     long long last_iters = -1;
-    int grid = 1, max_grid = 1;
+    int grid = 1, max_grid = 1, ncu = 1;
     double ticks_per_s = 1e8;
     long long timeout_ticks = 0;
     double setup_s = 0;
@@ -476,9 +519,9 @@ struct sscs_work {
 namespace {
 
 int launch_grid_kernel(sscs_work* w, void* fn, void** args) {
-    HIP_TRY(hipMemsetAsync(w->bar, 0, sizeof(unsigned long long), w->stream));
+    HIP_TRY(hipMemsetAsync(w->bar, 0, BAR_WORDS * sizeof(unsigned long long), w->stream));
     HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
-    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->grid), dim3(kBlock), args, 0, w->stream));
+    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(w->grid), dim3(kBlock), args, (size_t)w->I.lds_bytes, w->stream));
     return SSCS_OK;
 }
 
@@ -497,7 +540,7 @@ int run_op(sscs_work* w, int op, const double* in, double* out1, double* out2, d
     Prob P = make_prob(w->I);
     OpArgs a{op, in, out1, out2, w->scal, tol, maxit};
     void* args[] = {&P, &w->V, &a, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-    TRY(launch_grid_kernel(w, (void*)k_op_grid, args));
+    TRY(launch_grid_kernel(w, w->I.lds_bytes ? (void*)k_op_grid<true> : (void*)k_op_grid<false>, args));
     HIP_TRY(hipGetLastError());
     return check_abort(w);
 }
@@ -521,23 +564,90 @@ int stage_out(sscs_work* w, double* user, const double* dev, size_t len) {
     return SSCS_OK;
 }
 
+// Row partition of a CSR matrix over G workgroups, balanced by nonzeros.
+std::vector<int> partition_rows(const std::vector<int>& rp, int rows, int G) {
+    std::vector<int> part(G + 1, 0);
+    const long long nnz = rp[rows];
+    for (int b = 1; b < G; ++b) {
+        const long long target = nnz * b / G;
+        int r = (int)(std::lower_bound(rp.begin(), rp.begin() + rows + 1, (int)target) - rp.begin());
+        part[b] = std::max(part[b - 1], std::min(r, rows));
+    }
+    part[G] = rows;
+    return part;
+}
+
+// LDS bytes workgroup b needs to hold its rows (values, column indices, local
+// row pointers), with the layout load_part() uses.
+long long part_lds_bytes(const std::vector<int>& rp, const std::vector<int>& part, int b) {
+    const long long rows = part[b + 1] - part[b];
+    const long long nnz = rp[part[b + 1]] - rp[part[b]];
+    return (12 * nnz + 4 * (rows + 1) + 15) & ~15ll;
+}
+
+int set_partitions(sscs_work* w, bool try_lds);
+
 int choose_grid(sscs_work* w) {
     int dev = 0, ncu = 0, occ = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_grid, kBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_grid<false>, kBlock, 0));
     int occ2 = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, (const void*)k_op_grid, kBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, (const void*)k_op_grid<false>, kBlock, 0));
     occ = std::max(1, std::min(occ, occ2));
+    w->ncu = ncu;
     w->max_grid = std::max(1, ncu * occ);
-    // about eight nonzeros of A per thread per SpMV, at least one row per thread
-    const long long want = std::max<long long>((w->I.nnz + 8ll * kBlock - 1) / (8ll * kBlock),
+    // one workgroup per CU once there are about two nonzeros of A per thread
+    const long long want = std::max<long long>((w->I.nnz + 2ll * kBlock - 1) / (2ll * kBlock),
                                                ((long long)w->I.N + kBlock - 1) / kBlock);
     w->grid = (int)std::max<long long>(1, std::min<long long>(want, w->max_grid));
+    if (const char* e = std::getenv("SSCS_GRID")) {      // tuning override: workgroups of the grid team
+        const int g = std::atoi(e);
+        if (g >= 1) w->grid = std::min(g, w->max_grid);
+    }
     int rate_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
     w->ticks_per_s = rate_khz > 0 ? rate_khz * 1000.0 : 1e8;
     w->timeout_ticks = (long long)(60.0 * w->ticks_per_s);
+    const char* nolds = std::getenv("SSCS_NO_LDS");        // tuning override: keep the operator in HBM
+    return set_partitions(w, !(nolds && nolds[0] == '1'));
+}
+
+// Row partitions for the grid size; caches the operator in LDS when every
+// workgroup's share fits next to the static LDS and the grid stays co-resident.
+int set_partitions(sscs_work* w, bool try_lds) {
+    Inst& I = w->I;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int lds_max = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const long long limit = (long long)lds_max - (long long)sizeof(Shared) - 1024;
+    std::vector<int> pA, pAt;
+    long long need = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        pA = partition_rows(I.h_rpA, I.m, w->grid);
+        pAt = partition_rows(I.h_rpAt, I.n, w->grid);
+        need = 0;
+        for (int b = 0; b < w->grid; ++b)
+            need = std::max(need, part_lds_bytes(I.h_rpA, pA, b) + part_lds_bytes(I.h_rpAt, pAt, b));
+        I.lds_bytes = 0;
+        if (!try_lds || w->grid < 2 || need > limit) break;
+        int o1 = 0, o2 = 0;
+        HIP_TRY(hipFuncSetAttribute((const void*)k_solve_grid<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        HIP_TRY(hipFuncSetAttribute((const void*)k_op_grid<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, (const void*)k_solve_grid<true>, kBlock, (size_t)need));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void*)k_op_grid<true>, kBlock, (size_t)need));
+        const int cap = w->ncu * std::min(o1, o2);
+        if (cap >= w->grid) { I.lds_bytes = (int)need; break; }
+        if (cap < 2) break;
+        w->grid = cap;                        // shrink to a co-resident grid and re-partition
+    }
+    hipFree(I.partA);
+    hipFree(I.partAt);
+    TRY(dmalloc(&I.partA, pA.size()));
+    TRY(dmalloc(&I.partAt, pAt.size()));
+    HIP_TRY(hipMemcpy(I.partA, pA.data(), pA.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I.partAt, pAt.data(), pAt.size() * sizeof(int), hipMemcpyHostToDevice));
     return SSCS_OK;
 }
 
@@ -548,7 +658,7 @@ int alloc_work_vectors(sscs_work* w) {
     TRY(dmalloc(&w->io, 4 * (size_t)w->I.N));
     TRY(dmalloc(&w->scal, 16));
     TRY(dmalloc(&w->res, 1));
-    TRY(dmalloc(&w->bar, 1));
+    TRY(dmalloc(&w->bar, BAR_WORDS));
     TRY(dmalloc(&w->abort_flag, 1));
     TRY(dmalloc(&w->part, 2 * (size_t)KMAX * w->max_grid));
     if (w->I.K.ns > 0) {
@@ -700,8 +810,13 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
     V.tr_res = w->tr_res; V.tr_kind = w->tr_kind; V.tr_ls = w->tr_ls; V.tr_cap = w->tr_cap;
     Prob P = make_prob(w->I);
     Params S = make_params(w->st, w->ticks_per_s);
-    void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-    TRY(launch_grid_kernel(w, (void*)k_solve_grid, args));
+    if (w->grid == 1) {
+        HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
+        k_solve_block<<<1, kBatchBlock, 0, w->stream>>>(P, V, S, w->res);
+    } else {
+        void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
+        TRY(launch_grid_kernel(w, w->I.lds_bytes ? (void*)k_solve_grid<true> : (void*)k_solve_grid<false>, args));
+    }
     HIP_TRY(hipGetLastError());
     TRY(stage_out(w, x, V.out_x, n));
     TRY(stage_out(w, y, V.out_y, m));

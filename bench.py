@@ -48,7 +48,7 @@ def op_units(info):
     return info["cg_iters"] + 2 * linear_steps + iters
 
 
-def cpu_baseline(prob, gpu_iters, budget_iters=20):
+def cpu_baseline(prob, gpu_iters, budget_iters=60):
     """The oracle (FP64 direct factorisation) on a bounded sample: the
     factorisation plus `budget_iters` iterations of Algorithm 1, extrapolated
     to the GPU's iteration count."""
@@ -75,6 +75,59 @@ def cpu_baseline(prob, gpu_iters, budget_iters=20):
                        f"{cores} host cores in affinity set")}
 
 
+def bench_settings(sscs, max_iters):
+    """Anderson memory 5 (the workload's direction); relaxation 1.5, K1 factor
+    0.9999 and safeguard decay 0.999 (Algorithm 1 inputs lambda, c1, q; the
+    paper leaves their values open); inexact CG with tolerance 0.1 ||Ru||/||u||
+    clamped to [1e-12, 1e-3]."""
+    return sscs.Settings(direction="aa", mem=5, eps=1e-6, lam=1.5, c1=0.9999, q=0.999,
+                         cg_tol=1e-12, cg_adapt=0.1, cg_max=500, max_iters=max_iters,
+                         data_on_device=True)
+
+
+def source_digest():
+    """SHA-256 of the HIP sources the solve kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1903_06477_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per solve launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_solve_grid_socp_20000x50000.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +135,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--max-iters", type=int, default=20000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the solver has no multi-GPU path)", file=sys.stderr)
@@ -97,8 +155,7 @@ def main():
     prob = G.config2_socp()
     n, m, nnz = prob.n, prob.m, prob.A.nnz
     stream = torch.cuda.current_stream()
-    st = sscs.Settings(direction="aa", mem=5, eps=1e-6, cg_tol=1e-10, cg_max=500,
-                       max_iters=args.max_iters, data_on_device=True)
+    st = bench_settings(sscs, args.max_iters)
     solver = sscs.Solver(prob, st, stream=stream.cuda_stream)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     y = torch.empty(m, dtype=torch.float64, device=dev)
@@ -154,13 +211,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sparse SOCP n=20000 m=50000 density 1e-3, zero 1000 + R+ 20000 + "
                                f"{len(prob.cone.q)} SOC (sizes 3..50), planted optimum, AA mem 5, eps 1e-6",
+                   "settings": {"lambda": 1.5, "c1": 0.9999, "q": 0.999, "sigma": 0.01, "c0": 0.99,
+                                "cg_adapt": 0.1, "cg_tol": 1e-12},
                    "n": n, "m": m, "nnz": int(nnz), "parallelism": "single GPU"},
         "iterations_per_s": last["iters"] * value,
         "solve": {"iters": last["iters"], "cg_iters": last["cg_iters"], "k0": last["k0"], "k1": last["k1"],
                   "k2": last["k2"], "km": last["km"], "backtracks": last["backtracks"],
                   "pr": pr, "dr": dr, "gap": last["gap"], "obj_err_vs_planted": obj_err},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_solve_grid", "kernel_ms": kernel_ms,
                      "bytes_per_launch": bytes_per_launch, "cg_op_units": units},
         "spmv": {"A_us": ms_a * 1e3, "A_GBs": gbs_a, "At_us": ms_t * 1e3, "At_GBs": gbs_t,

@@ -105,6 +105,9 @@ typedef struct {
     int32_t data_on_device;       /* vector arguments are device pointers */
     int32_t record_trace;         /* keep per-iteration ||Ru|| and step kinds */
     double  aa_reg;               /* Anderson Gram regularisation, times tr(G)/k */
+    double  cg_adapt;             /* 0: every CG solve to cg_tol; > 0: inexact linear steps,
+                                     CG tolerance cg_adapt * ||R u|| / ||u|| clamped to
+                                     [cg_tol, 1e-3] (the first solve uses 1e-6) */
 } sscs_settings;
 
 /* Result of a solve. */
@@ -127,7 +130,8 @@ typedef struct sscs_batch sscs_batch;
 
 /* Fills *st with defaults: eps 1e-6, AA mem 5, c0 0.99 (0.1 is the paper's
  * advice for RB, Sec. IV-D-1), c1 0.99, q 0.99, sigma 0.01, lambda 1,
- * thetabar 0.1, ls_max 10, FP64, cg_tol 1e-10, cg_max 500. */
+ * thetabar 0.1, ls_max 10, FP64, cg_tol 1e-10, cg_max 500, aa_reg 1e-12,
+ * cg_adapt 0. */
 int sscs_default_settings(sscs_settings *st);
 
 /* Validates and uploads (A, b, c, K), builds A^T and the per-instance

@@ -116,10 +116,12 @@ __device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned lo
 // counter is hammered by one XCD only.  The last arrival of a group bumps the
 // global counter, waits for all groups, then releases its group through the
 // group's release word.  All counters grow monotonically (the k-th barrier
-// completes at k * members), so nothing is reset inside the kernel.  Arrivals
-// are release and waits acquire (agent scope), which orders every write made
-// before the barrier by the workgroup (joined by __syncthreads) before every
-// read after it.  A wait that exceeds `timeout_ticks` of the wall clock raises
+// completes at k * members), so nothing is reset inside the kernel.  Every
+// arrival is preceded by an agent-scope release fence and every wait ends with
+// an agent-scope acquire fence (relaxed atomics in between, which are much
+// cheaper than acquire-release read-modify-writes), so every write made before
+// the barrier by the workgroup (joined by __syncthreads) happens before every
+// read after it, also across groups through the leaders' fences.  A wait that exceeds `timeout_ticks` of the wall clock raises
 // the abort flag; later barriers then return at once, so every wave of the
 // grid still reaches the kernel's end.
 template <bool LDS>
@@ -154,12 +156,18 @@ struct GridTeam {
             const unsigned long long members = (G - grp + ng - 1) / ng;
             unsigned long long* cnt = bar + BAR_STRIDE * (1 + grp);
             unsigned long long* rel = bar + BAR_STRIDE * (1 + BAR_GROUPS + grp);
+            // fences + relaxed atomics: a release fence before each arrival, an
+            // acquire fence after each wait (inside spin_until); the group leader
+            // acquires its members' writes and releases them with its own arrival
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned long long old =
-                __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (old + 1 == k * members) {
-                __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 spin_until(bar, k * ng, abort_flag, timeout_ticks);
-                __hip_atomic_store(rel, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(rel, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 spin_until(rel, k, abort_flag, timeout_ticks);
             }

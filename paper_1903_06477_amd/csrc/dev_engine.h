@@ -43,8 +43,8 @@ struct Prob {
 struct Vecs {
     double *u, *ut, *ub, *Ru, *d, *dt, *Rw, *pz, *pxi;   // length N
     double *xw_u, *xw_d;                                 // CG warm starts, length n
-    double *cg_b, *cg_u, *cg_w, *cg_p;                   // length n
-    double *cg_r[2], *cg_s[2];                           // length n, double-buffered
+    double *cg_b, *cg_u, *cg_w, *cg_p, *cg_r, *cg_s;     // length n
+    double *cg_g[2];                                     // 4 n each: gathered (D r, D s, D w, -) per column
     double *cg_t;                                        // length m
     double *Zb, *Yb;                                     // mem x N memory buffers
     const double* u0;                                    // warm start or null
@@ -57,6 +57,7 @@ struct Vecs {
 struct Params {
     double eps, c0, c1, q, sigma, lam, thetabar, aa_reg;
     double cg_tol;
+    double cg_adapt;        // > 0: CG tolerance cg_adapt ||R u|| / ||u||, within [cg_tol, 1e-3]
     int direction, mem, ls_max, cg_max;
     long long max_iters;
     long long max_ticks;    // time limit in wall-clock ticks, <= 0: none
@@ -82,14 +83,15 @@ struct Result {
 //   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s.
 // One iteration is two team-wide phases:
 //   X: element owners update p, s, x, r, u; the owners of the rows of A form
-//      t = A u_new, gathering u_new,k = D_k (r_k - alpha (w_k + beta s_k))
-//      from the previous r and s (double-buffered, so nothing is read after
-//      it is overwritten) -- no barrier is needed between the update and the
-//      product;
-//   Y: the owners of the rows of A^T form w = u + A^T t and the partial sums
-//      of gamma, delta and ||r||^2; one reduction.
-// so each iteration costs two barriers.  The first pass runs with alpha = 0,
-// p = s = 0, which turns phase X into the initial u = D r0, t = A u.
+//      t = A u_new, gathering u_new,k = D_k r_k - alpha (D_k w_k + beta D_k s_k)
+//      from one 32-byte record (D r, D s, D w) per column of the previous
+//      step -- no barrier is needed between the update and the product, and
+//      each gathered column costs one cache line;
+//   Y: the owners of the rows of A^T form w = u + A^T t, the record's D w and
+//      the partial sums of gamma, delta and ||r||^2; one reduction.
+// The records are double-buffered: X reads buffer cur and fills (D r, D s)
+// of buffer cur^1, Y fills its D w.  The first pass runs with alpha = 0 and
+// p = s = w = 0, which turns phase X into u = D r0, t = A u.
 template <typename Team>
 __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit) {
@@ -103,45 +105,56 @@ __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const
     });
     spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
     tm.sync();
-    // r0 = rhs - (xw + A^T t) into buffer 0; u = w = p = s = 0
+    // r0 = rhs - (xw + A^T t); u = w = p = s = 0; record (D r0, 0, 0)
     spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; }, [&](int j, double s) {
-        V.cg_r[0][j] = V.cg_b[j] - (xw[j] + s);
-        V.cg_s[0][j] = 0.0;
+        const double rj = V.cg_b[j] - (xw[j] + s);
+        V.cg_r[j] = rj;
+        V.cg_s[j] = 0.0;
         V.cg_u[j] = 0.0;
         V.cg_w[j] = 0.0;
         V.cg_p[j] = 0.0;
+        double* g = V.cg_g[0] + 4 * (size_t)j;
+        g[0] = P.dinv[j] * rj;
+        g[1] = 0.0;
+        g[2] = 0.0;
     });
     tm.sync();
     double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0, thr = 0.0;
     int it = 0, cur = 0;
     for (int pass = 0;; ++pass) {
         // ---- phase X
-        const double* r_o = V.cg_r[cur];
-        const double* s_o = V.cg_s[cur];
-        double* r_n = V.cg_r[cur ^ 1];
-        double* s_n = V.cg_s[cur ^ 1];
+        const double* go = V.cg_g[cur];
+        double* gn = V.cg_g[cur ^ 1];
         for (int j = tm.rank(); j < n; j += tm.size()) {
             const double pj = V.cg_u[j] + beta * V.cg_p[j];
-            const double sj = V.cg_w[j] + beta * s_o[j];
-            const double rj = r_o[j] - alpha * sj;
+            const double sj = V.cg_w[j] + beta * V.cg_s[j];
+            const double rj = V.cg_r[j] - alpha * sj;
+            const double dj = P.dinv[j];
             xw[j] += alpha * pj;
             V.cg_p[j] = pj;
-            s_n[j] = sj;
-            r_n[j] = rj;
-            V.cg_u[j] = P.dinv[j] * rj;
+            V.cg_s[j] = sj;
+            V.cg_r[j] = rj;
+            V.cg_u[j] = dj * rj;
+            gn[4 * (size_t)j] = dj * rj;
+            gn[4 * (size_t)j + 1] = dj * sj;
         }
         spmv_part<4>(tm, P.A, 0,
-                    [&](int c) { return P.dinv[c] * (r_o[c] - alpha * (V.cg_w[c] + beta * s_o[c])); },
-                    [&](int i, double acc) { V.cg_t[i] = acc; });
+                     [&](int c) {
+                         const double2 ab = *reinterpret_cast<const double2*>(go + 4 * (size_t)c);
+                         const double dw = go[4 * (size_t)c + 2];
+                         return ab.x - alpha * (dw + beta * ab.y);
+                     },
+                     [&](int i, double acc) { V.cg_t[i] = acc; });
         tm.sync();
         cur ^= 1;
         // ---- phase Y
         double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
         spmv_part<4>(tm, P.At, 1, [&](int c) { return V.cg_t[c]; }, [&](int j, double s) {
             const double uj = V.cg_u[j];
-            const double rj = V.cg_r[cur][j];
+            const double rj = V.cg_r[j];
             const double wj = uj + s;
             V.cg_w[j] = wj;
+            V.cg_g[cur][4 * (size_t)j + 2] = P.dinv[j] * wj;
             a_g += rj * uj;
             a_d += wj * uj;
             a_rr += rj * rj;
@@ -183,17 +196,20 @@ __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const
     return it;
 }
 
-// out = (I + Q)^{-1} r (length N).  r and out must not alias.
+// (I + Q)^{-1} r = (p - tau g, tau) with p = M^{-1} r[0 .. n+m) written to
+// out[0 .. n+m) and tau = (r_tau + h^T p) / delta returned.  The rank-one
+// correction is left to the consumer (corrected(), below), which applies it
+// on the fly in its own pass, saving a barrier.  r and out must not alias.
 template <typename Team>
-__device__ int linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
-                           double* xw, double tol, int maxit) {
-    const int it = solve_M(tm, sh, P, V, r, out, xw, tol, maxit);
-    const double t = (r[P.N - 1] + sh.out[0]) / P.delta;
-    const int nm = P.n + P.m;
-    for (int i = tm.rank(); i < nm; i += tm.size()) out[i] -= t * P.g[i];
-    if (tm.rank() == 0) out[P.N - 1] = t;
-    tm.sync();
-    return it;
+__device__ double linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
+                              double* xw, double tol, int maxit, long long* cg_iters) {
+    *cg_iters += solve_M(tm, sh, P, V, r, out, xw, tol, maxit);
+    return (r[P.N - 1] + sh.out[0]) / P.delta;
+}
+
+// Entry i of (I + Q)^{-1} r from the uncorrected output p of linear_step.
+__device__ __forceinline__ double corrected(const Prob& P, const double* p, double tau, int i) {
+    return (i < P.N - 1) ? p[i] - tau * P.g[i] : tau;
 }
 
 // Per-instance constants of the linear step: ||b||, ||c||, g = M^{-1} (c, b)
@@ -222,20 +238,26 @@ __device__ int setup_gdelta(Team& tm, Shared& sh, Prob& P, const Vecs& V, double
 
 // ------------------------------------------------------------------ passes
 
-// u-bar = Pi_C(2 u~ - u), R u = u~ - u-bar; returns ||R u||^2.
+// u-bar = Pi_C(2 u~ - u), R u = u~ - u-bar, where u~ is formed from the
+// uncorrected linear-step output in V.ut and tau (and stored back corrected);
+// returns ||R u||^2 and leaves ||u||^2 in sh.out[1].
 template <typename Team>
-__device__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V) {
-    double acc = 0.0;
+__device__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, double tau) {
+    double acc = 0.0, au = 0.0;
     project_C(tm, P.n, P.N, P.K, nullptr, nullptr,
-              [&](int i) { return 2.0 * V.ut[i] - V.u[i]; },
+              [&](int i) { return 2.0 * corrected(P, V.ut, tau, i) - V.u[i]; },
               [&](int i, double v) {
+                  const double ut = corrected(P, V.ut, tau, i);
+                  V.ut[i] = ut;
                   V.ub[i] = v;
-                  const double r = V.ut[i] - v;
+                  const double r = ut - v;
                   V.Ru[i] = r;
                   acc += r * r;
+                  au += V.u[i] * V.u[i];
               });
     put(sh, 0, acc);
-    tm.reduce(sh, 1);
+    put(sh, 1, au);
+    tm.reduce(sh, 2);
     return sh.out[0];
 }
 
@@ -577,9 +599,15 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     double nRu = 0.0;
     int status = 0;
     long long nu = 0;
+    double tol = S.cg_adapt > 0.0 ? 1e-6 : S.cg_tol;
     for (nu = 0;; ++nu) {
-        cgc += linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, S.cg_tol, S.cg_max);
-        nRu = sqrt(residual_pass(tm, sh, P, V));
+        const double tau_u = linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc);
+        nRu = sqrt(residual_pass(tm, sh, P, V, tau_u));
+        if (S.cg_adapt > 0.0) {
+            // inexact linear steps: accuracy relative to the current fixed-point residual
+            const double nu_ = sqrt(sh.out[1]);
+            tol = fmin(1e-3, fmax(S.cg_tol, S.cg_adapt * nRu / fmax(nu_, 1e-300)));
+        }
         const bool late = S.max_ticks > 0 && (wall_clock64() - t_start) > S.max_ticks;
         termination_pass(tm, sh, P, V, S, late);
         if (nu == 0) eta0 = eta = r_safe = nRu;
@@ -610,7 +638,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             write_trace(tm, V, nu, nRu, 0, 0);
             continue;
         }
-        cgc += linear_step(tm, sh, P, V, V.d, V.dt, V.xw_d, S.cg_tol, S.cg_max);
+        const double tau_d = linear_step(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc);
         double alpha = 1.0;
         int kind = 3, ls = 0;
         double coef = 0.0;
@@ -618,9 +646,11 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             const double a = alpha;
             double acc_w = 0.0, acc_d = 0.0;
             project_C(tm, n, N, P.K, nullptr, nullptr,
-                      [&](int i) { return 2.0 * (V.ut[i] + a * V.dt[i]) - (V.u[i] + a * V.d[i]); },
+                      [&](int i) {
+                          return 2.0 * (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - (V.u[i] + a * V.d[i]);
+                      },
                       [&](int i, double v) {
-                          const double rw = (V.ut[i] + a * V.dt[i]) - v;
+                          const double rw = (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - v;
                           V.Rw[i] = rw;
                           acc_w += rw * rw;
                           acc_d += rw * V.d[i];

@@ -90,14 +90,17 @@ __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, un
     if (a.op == OP_LINEAR) {
         for (int j = tm.rank(); j < n; j += tm.size()) V.xw_d[j] = 0.0;
         tm.sync();
-        const int it = linear_step(tm, sh, P, V, a.in, a.out1, V.xw_d, a.tol, a.maxit);
+        long long it = 0;
+        const double tau = linear_step(tm, sh, P, V, a.in, a.out1, V.xw_d, a.tol, a.maxit, &it);
+        for (int i = tm.rank(); i < N; i += tm.size()) a.out1[i] = corrected(P, a.out1, tau, i);
         if (tm.rank() == 0 && a.scal) a.scal[0] = (double)it;
     } else if (a.op == OP_RESIDUAL) {
         for (int i = tm.rank(); i < N; i += tm.size()) V.u[i] = a.in[i];
         for (int j = tm.rank(); j < n; j += tm.size()) V.xw_u[j] = 0.0;
         tm.sync();
-        linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, a.tol, a.maxit);
-        const double r2 = residual_pass(tm, sh, P, V);
+        long long it = 0;
+        const double tau = linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, a.tol, a.maxit, &it);
+        const double r2 = residual_pass(tm, sh, P, V, tau);
         for (int i = tm.rank(); i < N; i += tm.size()) {
             if (a.out1) a.out1[i] = V.ut[i];
             a.out2[i] = V.Ru[i];
@@ -309,7 +312,7 @@ int validate_settings(const sscs_settings* st) {
     if (!(st->sigma > 0 && st->sigma < 1)) return SSCS_E_INVALID;
     if (st->c0 < 0 || st->c1 < 0 || st->q < 0 || st->q >= 1) return SSCS_E_INVALID;
     if (!(st->thetabar > 0 && st->thetabar < 1)) return SSCS_E_INVALID;
-    if (!(st->cg_tol > 0)) return SSCS_E_INVALID;
+    if (!(st->cg_tol > 0) || !(st->cg_adapt >= 0)) return SSCS_E_INVALID;
     if (st->precision != SSCS_PREC_FP64 && st->precision != SSCS_PREC_MIXED) return SSCS_E_INVALID;
     return SSCS_OK;
 }
@@ -325,6 +328,7 @@ Params make_params(const sscs_settings& st, double ticks_per_s) {
     p.thetabar = st.thetabar;
     p.aa_reg = st.aa_reg;
     p.cg_tol = st.cg_tol;
+    p.cg_adapt = st.cg_adapt;
     p.direction = st.direction;
     p.mem = st.mem;
     p.ls_max = st.ls_max;
@@ -470,7 +474,7 @@ Prob make_prob(const Inst& I) {
 
 size_t vec_doubles(int n, int m, int mem) {
     const size_t N = (size_t)n + m + 1;
-    return 9 * N + 10 * (size_t)n + (size_t)m + 2 * (size_t)mem * N;
+    return 9 * N + 16 * (size_t)n + (size_t)m + 2 * (size_t)mem * N + 8;
 }
 
 // Carves the Vecs of one instance from a contiguous device buffer.
@@ -483,7 +487,9 @@ Vecs carve(double* base, int n, int m, int mem) {
     V.dt = take(N); V.Rw = take(N); V.pz = take(N); V.pxi = take(N);
     V.xw_u = take(n); V.xw_d = take(n);
     V.cg_b = take(n); V.cg_u = take(n); V.cg_w = take(n); V.cg_p = take(n);
-    V.cg_r[0] = take(n); V.cg_r[1] = take(n); V.cg_s[0] = take(n); V.cg_s[1] = take(n);
+    V.cg_r = take(n); V.cg_s = take(n);
+    p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 31) & ~uintptr_t(31));   // 32-byte records
+    V.cg_g[0] = take(4 * (size_t)n); V.cg_g[1] = take(4 * (size_t)n);
     V.cg_t = take(m);
     V.Zb = take((size_t)mem * N); V.Yb = take((size_t)mem * N);
     return V;
@@ -736,6 +742,7 @@ int sscs_default_settings(sscs_settings* st) {
     st->data_on_device = 0;
     st->record_trace = 0;
     st->aa_reg = 1e-12;
+    st->cg_adapt = 0.0;
     return SSCS_OK;
 }
 

@@ -8,9 +8,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsscs.so")
-SOURCES = [os.path.join(HERE, "csrc", "sscs.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "sscs.hip"), os.path.join(HERE, "csrc", "mlp.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("dev_common.h", "dev_cones.h", "dev_engine.h")] + [
-    os.path.join(ROOT, "include", "sscs.h")]
+    os.path.join(ROOT, "include", "sscs.h"), os.path.join(ROOT, "include", "sscs_mlp.h")]
 
 
 def hipcc() -> str:

@@ -60,7 +60,10 @@ class _Info(ctypes.Structure):
 EXPORTS = ["sscs_default_settings", "sscs_create", "sscs_solve", "sscs_update_settings", "sscs_update_bc",
            "sscs_destroy", "sscs_linear_step", "sscs_project_dual_cone", "sscs_residual", "sscs_spmv",
            "sscs_spmv_bench", "sscs_get_trace", "sscs_batch_create", "sscs_batch_update_bc",
-           "sscs_batch_solve", "sscs_batch_destroy", "sscs_error_string"]
+           "sscs_batch_solve", "sscs_batch_destroy", "sscs_error_string",
+           "sscs_mlp_create", "sscs_mlp_destroy", "sscs_mlp_set_params", "sscs_mlp_get_params",
+           "sscs_mlp_forward", "sscs_mlp_train_step", "sscs_mlp_gradients", "sscs_mlp_gemm_nt",
+           "sscs_assemble_u0"]
 
 _lib = None
 

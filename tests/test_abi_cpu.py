@@ -12,8 +12,8 @@ HEADER = os.path.join(ROOT, "include", "sscs.h")
 
 
 def _declared():
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(sscs_[a-z_]+)\s*\(", txt)))
+    txt = open(HEADER).read() + open(os.path.join(ROOT, "include", "sscs_mlp.h")).read()
+    return sorted(set(re.findall(r"\b(sscs_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():

@@ -85,6 +85,52 @@ def bench_settings(sscs, max_iters):
                          data_on_device=True)
 
 
+def batched_leg(sscs, G, count=4096):
+    """The batched LASSO family: `count` independent instances (n in 20..400,
+    rows in n/2..2n, density 5%) in one persistent launch, FP64, AA memory 5,
+    eps 1e-6.  Instances are uploaded before timing; outputs stay on the
+    device."""
+    import torch
+    probs = [G.config4_instance(i) for i in range(count)]
+    st = bench_settings(sscs, 20000)
+    bs = sscs.BatchSolver(probs, st)
+    nx, ny = int(bs.ns.sum()), int(bs.ms.sum())
+    out = (torch.empty(nx, dtype=torch.float64, device="cuda:0"), torch.empty(ny, dtype=torch.float64, device="cuda:0"),
+           torch.empty(ny, dtype=torch.float64, device="cuda:0"))
+    bs.solve(out=out)                       # warm-up launch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, infos = bs.solve(out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bs.close()
+    its = np.array([i["iters"] for i in infos])
+    ok = np.mean([i["status"] == sscs.SOLVED for i in infos])
+    return {"workload": f"{count} LASSO-SOCP instances, n in 20..400, m in n/2..2n, density 0.05, one launch",
+            "solves_per_s": count / wall if ok == 1.0 else 0.0, "iterations_per_s": float(its.sum()) / wall,
+            "wall_s": wall, "solved_frac": float(ok), "iters_mean": float(its.mean()), "iters_max": int(its.max()),
+            "cg_per_iter": float(sum(i["cg_iters"] for i in infos)) / max(1, int(its.sum())), "dtype": "f64"}
+
+
+def learned_leg(ntrain=2048, ntest=1024, epochs=60):
+    """Learned warm start vs the plain cold-started method on the shared-A
+    LASSO family (A 2000 x 1000 at 2%): cold batched solves of `ntrain`
+    instances give the training targets, the network (2000-512-512-10005,
+    BF16 matrix cores) is trained on them, and `ntest` held-out instances are
+    solved cold and warm; the warm time includes inference and cold
+    fallbacks."""
+    from paper_1903_06477_amd import warmstart as W
+    r = W.experiment(ntrain, ntest, epochs, log=lambda s: print(s, file=sys.stderr, flush=True))
+    return {"workload": f"shared-A LASSO family, {ntrain} training / {ntest} test instances (batches of 1024)",
+            "cold_s": r["t_cold"], "warm_total_s": r["t_warm_total"], "inference_s": r["t_inference"],
+            "warm_solve_s": r["t_warm_solve"], "fallback_s": r["t_fallback"], "fallbacks": r["n_fallback"],
+            "speedup": r["speedup"], "iters_cold_mean": r["iters_cold_mean"],
+            "iters_warm_mean": r["iters_warm_mean"], "cold_solves_per_s": ntest / r["t_cold"],
+            "warm_solves_per_s": ntest / r["t_warm_total"], "train_loss": [r["loss_first"], r["loss_last"]],
+            "training_data_s": r["t_generate"], "training_s": r["t_train"],
+            "warm_worst_residual": r["warm_worst_residual"]}
+
+
 def source_digest():
     """SHA-256 of the HIP sources the solve kernel is built from."""
     import hashlib
@@ -135,6 +181,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--max-iters", type=int, default=20000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched LASSO leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -225,6 +273,11 @@ def main():
         "spmv": {"A_us": ms_a * 1e3, "A_GBs": gbs_a, "At_us": ms_t * 1e3, "At_GBs": gbs_t,
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }
+    solver.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(sscs, G)
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, last["iters"])
     print(json.dumps(out))

@@ -4,36 +4,50 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  The network is a
 plain multilayer perceptron, widths w0 -> ... -> wL, ReLU after every layer
 but the last, loss L = mean((Y - T)^2) over all entries.  Backpropagation is
 written out layer by layer.
+
+The optional argument q is applied to both operands of every matrix product
+(identity by default).  With q = bf16_round it models a network whose
+products take BF16 operands: the input, the weights, the hidden activations
+and the back-propagated error each rounded (through FP32) to BF16, sums and
+biases kept exact; the ReLU mask in the backward pass is the sign of the
+rounded activation.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def forward(Ws, bs, X):
-    """Returns the output and the list of layer inputs (activations)."""
-    H = [np.asarray(X, dtype=np.float64)]
+def _ident(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def forward(Ws, bs, X, q=None):
+    """Returns the output and the list of layer inputs (activations, as
+    they enter the products)."""
+    q = q or _ident
+    H = [q(X)]
     for l, (W, b) in enumerate(zip(Ws, bs)):
-        Z = H[-1] @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)
+        Z = H[-1] @ q(W).T + np.asarray(b, np.float64)
         if l < len(Ws) - 1:
-            H.append(np.maximum(Z, 0.0))
+            H.append(q(np.maximum(Z, 0.0)))
         else:
             return Z, H
     raise ValueError("empty network")
 
 
-def loss_and_grads(Ws, bs, X, T):
-    Y, H = forward(Ws, bs, X)
+def loss_and_grads(Ws, bs, X, T, q=None):
+    q = q or _ident
+    Y, H = forward(Ws, bs, X, q)
     T = np.asarray(T, np.float64)
     D = Y - T
     L = float(np.mean(D * D))
     G = 2.0 * D / D.size                       # dL/dY
     dWs, dbs = [None] * len(Ws), [None] * len(Ws)
     for l in range(len(Ws) - 1, -1, -1):
-        dWs[l] = G.T @ H[l]
+        dWs[l] = q(G).T @ H[l]
         dbs[l] = G.sum(axis=0)
         if l > 0:
-            G = (G @ np.asarray(Ws[l], np.float64)) * (H[l] > 0)
+            G = (q(G) @ q(Ws[l])) * (H[l] > 0)
     return L, dWs, dbs
 
 

@@ -70,7 +70,10 @@ extern __shared__ __attribute__((aligned(16))) double sscs_dyn_lds[];
 
 struct BlockTeam {
     static constexpr bool kLds = false;
+    static constexpr bool kBlock = true;
     MatPart mp[2];    // A, A^T: all rows, global memory
+    double* lu = nullptr;   // LDS copies of the CG's gathered vectors (n and m
+    double* lt = nullptr;   // entries), or null when they do not fit
     __device__ int rank() const { return threadIdx.x; }
     __device__ int size() const { return blockDim.x; }
     __device__ int wave() const { return threadIdx.x / WAVE; }
@@ -127,6 +130,7 @@ __device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned lo
 template <bool LDS>
 struct GridTeam {
     static constexpr bool kLds = LDS;   // operator rows held in LDS
+    static constexpr bool kBlock = false;
     MatPart mp[2];              // this workgroup's rows of A and A^T
     unsigned long long* bar;    // BAR_WORDS words, zero at launch
     int* abort_flag;

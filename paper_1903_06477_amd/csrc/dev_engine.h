@@ -92,9 +92,113 @@ struct Result {
 // The records are double-buffered: X reads buffer cur and fills (D r, D s)
 // of buffer cur^1, Y fills its D w.  The first pass runs with alpha = 0 and
 // p = s = w = 0, which turns phase X into u = D r0, t = A u.
+// One-workgroup form of solve_M: the workgroup owns every row, so the vectors
+// the two products gather from (u for A, t for A^T) live in LDS and the
+// column records are not needed; each iteration is: update and store u in
+// LDS | t = A u into LDS | w = u + A^T t and the dots.  Same recurrence, same
+// arithmetic per entry as solve_M.
+template <typename Team>
+__device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
+                              double* xw, double tol, int maxit) {
+    const int n = P.n, m = P.m;
+    double* __restrict__ ul = tm.lu;
+    double* __restrict__ tl = tm.lt;
+    for (int i = tm.rank(); i < m; i += tm.size()) tl[i] = r[n + i];
+    for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
+    tm.sync();
+    // rhs = rx - A^T ry ; t = A xw
+    double a_bb = 0.0;
+    spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
+        const double bj = r[j] - s;
+        V.cg_b[j] = bj;
+        a_bb += bj * bj;
+    });
+    tm.sync();
+    spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) { tl[i] = s; });
+    tm.sync();
+    // r0 = rhs - (xw + A^T t); p = s = w = 0
+    spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
+        const double rj = V.cg_b[j] - (xw[j] + s);
+        V.cg_r[j] = rj;
+        V.cg_s[j] = 0.0;
+        V.cg_u[j] = 0.0;
+        V.cg_w[j] = 0.0;
+        V.cg_p[j] = 0.0;
+    });
+    tm.sync();
+    double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0, thr = 0.0;
+    int it = 0;
+    for (int pass = 0;; ++pass) {
+        for (int j = tm.rank(); j < n; j += tm.size()) {
+            const double pj = V.cg_u[j] + beta * V.cg_p[j];
+            const double sj = V.cg_w[j] + beta * V.cg_s[j];
+            const double rj = V.cg_r[j] - alpha * sj;
+            const double uj = P.dinv[j] * rj;
+            xw[j] += alpha * pj;
+            V.cg_p[j] = pj;
+            V.cg_s[j] = sj;
+            V.cg_r[j] = rj;
+            V.cg_u[j] = uj;
+            ul[j] = uj;
+        }
+        tm.sync();
+        spmv_part<4>(tm, P.A, 0, [&](int c) { return ul[c]; }, [&](int i, double acc) { tl[i] = acc; });
+        tm.sync();
+        double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
+        spmv_part<4>(tm, P.At, 1, [&](int c) { return tl[c]; }, [&](int j, double s) {
+            const double uj = V.cg_u[j];
+            const double rj = V.cg_r[j];
+            const double wj = uj + s;
+            V.cg_w[j] = wj;
+            a_g += rj * uj;
+            a_d += wj * uj;
+            a_rr += rj * rj;
+        });
+        put(sh, 0, a_g);
+        put(sh, 1, a_d);
+        put(sh, 2, a_rr);
+        if (pass == 0) put(sh, 3, a_bb);
+        tm.reduce(sh, pass == 0 ? 4 : 3);
+        const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
+        if (pass == 0) thr = tol * tol * sh.out[3];
+        if (!(rr > thr) || it >= maxit) break;
+        double den = delta;
+        if (pass == 0) {
+            beta = 0.0;
+        } else {
+            beta = gamma / gamma_old;
+            den = delta - beta * gamma / alpha_old;
+        }
+        if (!(gamma > 0.0) || !(den > 0.0)) break;
+        alpha = gamma / den;
+        gamma_old = gamma;
+        alpha_old = alpha;
+        ++it;
+    }
+    // py = ry + A px ; h^T p
+    for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
+    tm.sync();
+    double a_hp = 0.0;
+    spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) {
+        const double py = r[n + i] + s;
+        out[n + i] = py;
+        a_hp += P.b[i] * py;
+    });
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        out[j] = xw[j];
+        a_hp += P.c[j] * xw[j];
+    }
+    put(sh, 0, a_hp);
+    tm.reduce(sh, 1);
+    return it;
+}
+
 template <typename Team>
 __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit) {
+    if constexpr (Team::kBlock) {
+        if (tm.lu) return solve_M_staged(tm, sh, P, V, r, out, xw, tol, maxit);
+    }
     const int n = P.n;
     // rhs = rx - A^T ry ; t = A xw
     double a_bb = 0.0;

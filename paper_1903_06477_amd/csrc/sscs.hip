@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kBlock = 512;            // threads per workgroup of the grid-team kernels
 constexpr int kBatchBlock = 256;
+constexpr int kStageMax = 12288;       // doubles of LDS for the one-workgroup CG's gathered vectors (96 KB)
 
 enum { OP_LINEAR = 0, OP_RESIDUAL = 1, OP_PROJECT = 2, OP_SETUP = 3 };
 
@@ -65,19 +66,40 @@ __device__ inline void grid_team_init(GridTeam<LDS>& tm, const Prob& P) {
     __syncthreads();
 }
 
-__device__ inline void block_team_init(BlockTeam& tm, const Prob& P) {
+// stage_doubles: dynamic LDS of the launch (in doubles) for the CG's gathered
+// vectors; an instance uses it when its n + m entries fit.
+__device__ inline void block_team_init(BlockTeam& tm, const Prob& P, int stage_doubles) {
     tm.mp[0] = MatPart{0, P.A.rows, 0, 0, 0, 0};
     tm.mp[1] = MatPart{0, P.At.rows, 0, 0, 0, 0};
+    const bool fit = P.n + P.m <= stage_doubles;
+    tm.lu = fit ? sscs_dyn_lds : nullptr;
+    tm.lt = fit ? sscs_dyn_lds + P.n : nullptr;
 }
+
+// The solve kernels keep the instance descriptors (Prob, Vecs, Params) in
+// LDS: every field read is then a broadcast LDS load instead of a load from a
+// per-lane private copy.
+struct Desc {
+    Prob P;
+    Vecs V;
+    Params S;
+};
 
 template <bool LDS>
 __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S, Result* res,
                                                        unsigned long long* bar, int* abort_flag,
                                                        double* part, long long timeout_ticks) {
     __shared__ Shared sh;
+    __shared__ Desc d;
+    if (threadIdx.x == 0) {
+        d.P = P;
+        d.V = V;
+        d.S = S;
+    }
+    __syncthreads();
     GridTeam<LDS> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
-    grid_team_init(tm, P);
-    sscs::solve(tm, sh, P, V, S, res);
+    grid_team_init(tm, d.P);
+    sscs::solve(tm, sh, d.P, d.V, d.S, res);
 }
 
 template <bool LDS>
@@ -128,30 +150,46 @@ struct BatchInst {
     Vecs V;
 };
 
-__global__ void __launch_bounds__(kBatchBlock) k_solve_batch(const BatchInst* __restrict__ insts, int count,
-                                                             Params S, Result* res, int* queue) {
+// Two workgroups per CU (waves_per_eu 2): the one-workgroup engine is bound by
+// memory latency, and a second resident instance hides more of it than the
+// few registers spilled by the tighter budget cost.
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_batch(const BatchInst* __restrict__ insts, int count,
+                                                             Params S, Result* res, int* queue, int stage_doubles) {
     __shared__ Shared sh;
+    __shared__ Desc d;
     BlockTeam tm;
+    if (threadIdx.x == 0) d.S = S;
     for (;;) {
         if (threadIdx.x == 0) sh.qhead = atomicAdd(queue, 1);
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(sh.qhead);
         __syncthreads();
         if (idx >= count) break;
-        Prob P = insts[idx].P;
-        const Vecs V = insts[idx].V;
-        block_team_init(tm, P);
-        setup_gdelta(tm, sh, P, V, const_cast<double*>(P.g), S.setup_tol, S.setup_max);
-        sscs::solve(tm, sh, P, V, S, res + idx);
+        if (threadIdx.x == 0) {
+            d.P = insts[idx].P;
+            d.V = insts[idx].V;
+        }
+        __syncthreads();
+        block_team_init(tm, d.P, stage_doubles);
+        setup_gdelta(tm, sh, d.P, d.V, const_cast<double*>(d.P.g), d.S.setup_tol, d.S.setup_max);
+        sscs::solve(tm, sh, d.P, d.V, d.S, res + idx);
     }
 }
 
 // Algorithm 1 for one instance small enough for a single workgroup.
-__global__ void __launch_bounds__(kBatchBlock) k_solve_block(Prob P, Vecs V, Params S, Result* res) {
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_block(Prob P, Vecs V, Params S, Result* res,
+                                                             int stage_doubles) {
     __shared__ Shared sh;
+    __shared__ Desc d;
+    if (threadIdx.x == 0) {
+        d.P = P;
+        d.V = V;
+        d.S = S;
+    }
+    __syncthreads();
     BlockTeam tm;
-    block_team_init(tm, P);
-    sscs::solve(tm, sh, P, V, S, res);
+    block_team_init(tm, d.P, stage_doubles);
+    sscs::solve(tm, sh, d.P, d.V, d.S, res);
 }
 
 __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __restrict__ y) {
@@ -242,6 +280,22 @@ double now_s() {
 // Lanes per row of the row-segmented SpMV: the smallest power of two that
 // gives each lane about `div` nonzeros of a mean-length row (more rows in
 // flight per wavefront, several independent loads per lane).
+// LDS (in doubles) the one-workgroup kernels stage the CG's gathered
+// vectors in, for an instance with `entries` = n + m; 0 when they do not fit
+// (the CG then gathers from global memory).  SSCS_NO_STAGE=1 turns it off.
+int stage_doubles(long long entries) {
+    static const bool off = [] { const char* e = getenv("SSCS_NO_STAGE"); return e && atoi(e) != 0; }();
+    if (off || entries <= 0 || entries > kStageMax) return 0;
+    static const bool attr = [] {
+        const int bytes = kStageMax * (int)sizeof(double);
+        return hipFuncSetAttribute((const void*)k_solve_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) ==
+                   hipSuccess &&
+               hipFuncSetAttribute((const void*)k_solve_block, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) ==
+                   hipSuccess;
+    }();
+    return attr ? (int)entries : 0;
+}
+
 int pow2_seg(double avg) {
     double div = 4.0;
     if (const char* e = std::getenv("SSCS_SEGDIV")) div = std::max(0.25, std::atof(e));   // tuning override
@@ -819,7 +873,8 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
     Params S = make_params(w->st, w->ticks_per_s);
     if (w->grid == 1) {
         HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
-        k_solve_block<<<1, kBatchBlock, 0, w->stream>>>(P, V, S, w->res);
+        const int sd = stage_doubles(w->I.n + w->I.m);
+        k_solve_block<<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
     } else {
         void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
         TRY(launch_grid_kernel(w, w->I.lds_bytes ? (void*)k_solve_grid<true> : (void*)k_solve_grid<false>, args));
@@ -959,6 +1014,7 @@ struct sscs_batch {
     Result* res = nullptr;
     int* queue = nullptr;
     int grid = 1;
+    int stage = 0;               // dynamic LDS of k_solve_batch, in doubles
     double ticks_per_s = 1e8;
     double setup_s = 0;
 };
@@ -1043,7 +1099,14 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
             int dev = 0, ncu = 0, occ = 0, rate = 0;
             hipGetDevice(&dev);
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_batch, kBatchBlock, 0);
+            long long big = 0;
+            for (int i = 0; i < count; ++i) {
+                const long long e = (long long)bt->inst[i].n + bt->inst[i].m;
+                if (e <= kStageMax) big = std::max(big, e);
+            }
+            bt->stage = stage_doubles(big);
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_batch, kBatchBlock,
+                                                         bt->stage * sizeof(double));
             hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
             bt->ticks_per_s = rate > 0 ? rate * 1000.0 : 1e8;
             bt->grid = std::max(1, std::min(count, ncu * std::max(1, occ)));
@@ -1103,7 +1166,8 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
                            bt->stream));
     HIP_TRY(hipMemsetAsync(bt->queue, 0, sizeof(int), bt->stream));
     Params S = make_params(bt->st, bt->ticks_per_s);
-    k_solve_batch<<<bt->grid, kBatchBlock, 0, bt->stream>>>(bt->d_insts, bt->count, S, bt->res, bt->queue);
+    k_solve_batch<<<bt->grid, kBatchBlock, bt->stage * sizeof(double), bt->stream>>>(bt->d_insts, bt->count, S,
+                                                                                      bt->res, bt->queue, bt->stage);
     HIP_TRY(hipGetLastError());
     if (!dev) {
         HIP_TRY(hipMemcpyAsync(x_packed, dio_x, bt->tot_x * sizeof(double), hipMemcpyDeviceToHost, bt->stream));

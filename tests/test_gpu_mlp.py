@@ -2,10 +2,16 @@
 
 Bars: the matrix-core product equals the FP64 product of the BF16-rounded
 operands to FP32 accumulation error (|C - C_ref| <= 2^-20 K max|a||b| + 1e-6,
-element by element); forward outputs and all gradients agree with the FP64
-reference network (per layer: relative Frobenius error <= 2e-2 and cosine
->= 0.999 -- BF16 operands carry 2^-9 relative rounding); u0 assembly is exact
-in FP64 of the FP32 inputs; a few Adam steps on a fixed batch lower the loss;
+element by element).  Forward outputs, loss and every gradient are compared
+with the FP64 reference network twice: (i) with the reference's BF16 operand
+model (every product operand rounded to BF16 as the kernels do), where only
+FP32 accumulation and the FP32 -> BF16 double rounding of intermediates
+differ: relative Frobenius error <= 1e-3 per layer and max entry error <=
+2e-3 of the layer's largest entry; (ii) with exact FP64 arithmetic, which
+bounds what BF16 operands cost: relative Frobenius error <= 5e-2 (25 units of
+BF16 rounding, 2^-9, for an error that passes through up to five rounded
+products) and cosine >= 0.998.  u0 assembly is exact in FP64 of the FP32
+inputs; a few Adam steps on a fixed batch lower the loss;
 a small learned warm start reaches the solver's tolerance, checked on the host
 in FP64."""
 import numpy as np
@@ -54,7 +60,16 @@ def _cos(a, b):
     return float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("widths,batch", [([20, 33, 17, 9], 50), ([300, 128, 96, 700], 130)])
+def _close_model(a, b):
+    return _rel(a, b) <= 1e-3 and np.max(np.abs(a - b)) <= 2e-3 * np.max(np.abs(b))
+
+
+def _close_exact(a, b):
+    return _rel(a, b) <= 5e-2 and _cos(a, b) >= 0.998
+
+
+@pytest.mark.parametrize("widths,batch", [([20, 33, 17, 9], 50), ([300, 128, 96, 700], 130),
+                                          ([2000, 512, 512, 10005], 256)])
 def test_forward_and_gradients_match_oracle(M, widths, batch):
     from oracle import mlp as ref
     print(f"mlp widths={widths} batch={batch}", flush=True)
@@ -70,14 +85,17 @@ def test_forward_and_gradients_match_oracle(M, widths, batch):
     X = r.standard_normal((batch, widths[0])).astype(np.float32)
     T = r.standard_normal((batch, widths[-1])).astype(np.float32)
     Y = net.forward(_dev(X)).cpu().numpy()
-    Yr, _ = ref.forward(Ws, bs, X)
-    assert _rel(Y, Yr) <= 2e-2 and _cos(Y, Yr) >= 0.999
+    Yq, _ = ref.forward(Ws, bs, X, q=ref.bf16_round)
+    Ye, _ = ref.forward(Ws, bs, X)
+    assert _close_model(Y, Yq) and _close_exact(Y, Ye)
     L, dWs, dbs = net.gradients(_dev(X), _dev(T))
-    Lr, dWr, dbr = ref.loss_and_grads(Ws, bs, X, T)
-    assert abs(L - Lr) <= 2e-2 * Lr
+    Lq, dWq, dbq = ref.loss_and_grads(Ws, bs, X, T, q=ref.bf16_round)
+    Le, dWe, dbe = ref.loss_and_grads(Ws, bs, X, T)
+    assert abs(L - Lq) <= 1e-4 * Lq and abs(L - Le) <= 1e-2 * Le
     for l in range(len(Ws)):
-        assert _rel(dWs[l], dWr[l]) <= 2e-2 and _cos(dWs[l], dWr[l]) >= 0.999, l
-        assert _rel(dbs[l], dbr[l]) <= 2e-2 and _cos(dbs[l], dbr[l]) >= 0.999, l
+        print(f"layer {l}: dW rel vs model {_rel(dWs[l], dWq[l]):.2e}, vs exact {_rel(dWs[l], dWe[l]):.2e}")
+        assert _close_model(dWs[l], dWq[l]) and _close_exact(dWs[l], dWe[l]), l
+        assert _close_model(dbs[l], dbq[l]) and _close_exact(dbs[l], dbe[l]), l
     net.close()
 
 

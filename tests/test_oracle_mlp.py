@@ -54,3 +54,35 @@ def test_bf16_rounding():
     assert out[1] == 1.0                       # tie 1 + 2^-8 rounds to even (1.0)
     assert out[2] == 1.0078125                 # above the tie rounds up
     assert out[3] == -2.5
+
+
+def test_operand_model_is_exact_on_representable_data():
+    """Small integers are BF16-exact and so are all products of this
+    network (|values| < 256, power-of-two loss scale): the BF16 operand model
+    then equals exact arithmetic bit for bit."""
+    r = np.random.default_rng(4)
+    widths = [6, 5, 4, 4]
+    Ws = [r.integers(-1, 2, size=(widths[i + 1], widths[i])).astype(float) for i in range(3)]
+    bs = [r.integers(-1, 2, size=widths[i + 1]).astype(float) for i in range(3)]
+    X = r.integers(-2, 3, size=(4, 6)).astype(float)
+    T = r.integers(-2, 3, size=(4, 4)).astype(float) * 0.5
+    e = mlp.loss_and_grads(Ws, bs, X, T)
+    q = mlp.loss_and_grads(Ws, bs, X, T, q=mlp.bf16_round)
+    assert e[0] == q[0]
+    for a, b in zip(e[1] + e[2], q[1] + q[2]):
+        assert np.array_equal(a, b)
+
+
+def test_operand_model_stays_near_exact():
+    """BF16 operands (unit roundoff 2^-9) move the gradients of a random
+    network by a few units of that roundoff, and the loss by less."""
+    widths = [30, 40, 20, 10]
+    Ws, bs = _net(widths, 6)
+    r = np.random.default_rng(7)
+    X = r.standard_normal((64, 30))
+    T = r.standard_normal((64, 10))
+    Le, dWe, dbe = mlp.loss_and_grads(Ws, bs, X, T)
+    Lq, dWq, dbq = mlp.loss_and_grads(Ws, bs, X, T, q=mlp.bf16_round)
+    assert abs(Lq - Le) <= 2 ** -8 * Le
+    for a, b in zip(dWq + dbq, dWe + dbe):
+        assert 0 < np.linalg.norm(a - b) <= 0.05 * np.linalg.norm(b)

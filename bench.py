@@ -85,14 +85,15 @@ def bench_settings(sscs, max_iters):
                          data_on_device=True)
 
 
-def batched_leg(sscs, G, count=4096):
+def batched_leg(sscs, G, count=4096, precision="fp64", probs=None):
     """The batched LASSO family: `count` independent instances (n in 20..400,
-    rows in n/2..2n, density 5%) in one persistent launch, FP64, AA memory 5,
-    eps 1e-6.  Instances are uploaded before timing; outputs stay on the
-    device."""
+    rows in n/2..2n, density 5%) in one persistent launch, AA memory 5,
+    eps 1e-6, FP64 or mixed precision (FP32 operator in CG, FP64 refinement).
+    Instances are uploaded before timing; outputs stay on the device."""
     import torch
-    probs = [G.config4_instance(i) for i in range(count)]
+    probs = probs or [G.config4_instance(i) for i in range(count)]
     st = bench_settings(sscs, 20000)
+    st.precision = precision
     bs = sscs.BatchSolver(probs, st)
     nx, ny = int(bs.ns.sum()), int(bs.ms.sum())
     out = (torch.empty(nx, dtype=torch.float64, device="cuda:0"), torch.empty(ny, dtype=torch.float64, device="cuda:0"),
@@ -109,7 +110,8 @@ def batched_leg(sscs, G, count=4096):
     return {"workload": f"{count} LASSO-SOCP instances, n in 20..400, m in n/2..2n, density 0.05, one launch",
             "solves_per_s": count / wall if ok == 1.0 else 0.0, "iterations_per_s": float(its.sum()) / wall,
             "wall_s": wall, "solved_frac": float(ok), "iters_mean": float(its.mean()), "iters_max": int(its.max()),
-            "cg_per_iter": float(sum(i["cg_iters"] for i in infos)) / max(1, int(its.sum())), "dtype": "f64"}
+            "cg_per_iter": float(sum(i["cg_iters"] for i in infos)) / max(1, int(its.sum())),
+            "dtype": "f64" if precision == "fp64" else "f32 operator / f64"}
 
 
 def learned_leg(ntrain=2048, ntest=1024, epochs=60):
@@ -274,8 +276,22 @@ def main():
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }
     solver.close()
+    # the same workload with the mixed-precision linear step
+    stm = bench_settings(sscs, args.max_iters)
+    stm.precision = "mixed"
+    with sscs.Solver(prob, stm, stream=stream.cuda_stream) as sm:
+        sm.solve(out=(x, y, s))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        im = sm.solve(out=(x, y, s))[3]
+        torch.cuda.synchronize()
+        wm = time.perf_counter() - t0
+    out["mixed"] = {"solves_per_s": 1.0 / wm if im["status"] == sscs.SOLVED else 0.0, "iters": im["iters"],
+                    "cg_iters": im["cg_iters"], "pr": im["pr"], "dr": im["dr"], "gap": im["gap"],
+                    "dtype": "f32 operator in CG / f64 residuals, refinement, scalars"}
     if not args.no_batched:
-        out["batched"] = batched_leg(sscs, G)
+        probs4 = [G.config4_instance(i) for i in range(4096)]
+        out["batched"] = batched_leg(sscs, G, probs=probs4)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_leg()
     if not args.no_cpu:

@@ -67,7 +67,13 @@ extern "C" {
 
 /* Precision of the linear step (Sec. IV-A, indirect solve). */
 #define SSCS_PREC_FP64       0   /* FP64 everywhere */
-#define SSCS_PREC_MIXED      1   /* FP32 CG inner solves, FP64 residuals and refinement */
+#define SSCS_PREC_MIXED      1   /* the CG iterations apply I + A^T A with FP32 copies of
+                                    A's values (FP64 vectors, accumulation and scalar
+                                    recurrences); each linear step's residual is recomputed
+                                    with the FP64 operator and the CG restarted from it (up
+                                    to four refinement rounds) until that FP64 residual
+                                    meets the CG tolerance.  Projections, residuals,
+                                    termination and directions stay FP64. */
 
 /* Problem data (Sec. III, problem (P)).  Host pointers. */
 typedef struct {

@@ -16,6 +16,8 @@
 // control decisions derived from them agree across the grid.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace sscs {
@@ -71,6 +73,7 @@ extern __shared__ __attribute__((aligned(16))) double sscs_dyn_lds[];
 struct BlockTeam {
     static constexpr bool kLds = false;
     static constexpr bool kBlock = true;
+    using lds_t = double;
     MatPart mp[2];    // A, A^T: all rows, global memory
     double* lu = nullptr;   // LDS copies of the CG's gathered vectors (n and m
     double* lt = nullptr;   // entries), or null when they do not fit
@@ -127,9 +130,10 @@ __device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned lo
 // read after it, also across groups through the leaders' fences.  A wait that exceeds `timeout_ticks` of the wall clock raises
 // the abort flag; later barriers then return at once, so every wave of the
 // grid still reaches the kernel's end.
-template <bool LDS>
+template <bool LDS, typename TL = double>
 struct GridTeam {
-    static constexpr bool kLds = LDS;   // operator rows held in LDS
+    static constexpr bool kLds = LDS;   // operator rows held in LDS ...
+    using lds_t = TL;                   // ... with values of this type
     static constexpr bool kBlock = false;
     MatPart mp[2];              // this workgroup's rows of A and A^T
     unsigned long long* bar;    // BAR_WORDS words, zero at launch
@@ -265,14 +269,14 @@ __device__ __forceinline__ void spmv_rows(Team& tm, const Csr<T>& M, const TX* _
 // f(r, sum_k v[k] gx(ci[k])) is called by the first lane of the segment that
 // owns r.  Same segment scheme and ROWS-way batching as spmv_gather, with the
 // row range local to the workgroup and the operator read from LDS when cached.
-template <int ROWS, bool LDS, typename Gx, typename F>
-__device__ __forceinline__ void spmv_part_impl(const Csr<double>& M, const MatPart& mp, Gx&& gx, F&& f) {
+template <int ROWS, bool LDS, typename T, typename Gx, typename F>
+__device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& mp, Gx&& gx, F&& f) {
     const int S = M.seg;
     const int seg = threadIdx.x / S;
     const int nseg = blockDim.x / S;
     const int ls = threadIdx.x & (S - 1);
     const char* lds = reinterpret_cast<const char*>(sscs_dyn_lds);
-    const double* lv = reinterpret_cast<const double*>(lds + mp.off_v);
+    const T* lv = reinterpret_cast<const T*>(lds + mp.off_v);
     const int* lci = reinterpret_cast<const int*>(lds + mp.off_ci);
     const int* lrp = reinterpret_cast<const int*>(lds + mp.off_rp);
     for (int l0 = seg; l0 < mp.rows; l0 += ROWS * nseg) {
@@ -297,7 +301,7 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<double>& M, const MatPa
 #pragma unroll
             for (int q = 0; q < ROWS; ++q) {
                 if (kb[q] < ke[q]) {
-                    const double v = LDS ? lv[kb[q]] : M.v[kb[q]];
+                    const double v = LDS ? (double)lv[kb[q]] : (double)M.v[kb[q]];
                     const int c = LDS ? lci[kb[q]] : M.ci[kb[q]];
                     acc[q] += v * (double)gx(c);
                     kb[q] += S;
@@ -315,14 +319,17 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<double>& M, const MatPa
     }
 }
 
-template <int ROWS, typename Team, typename Gx, typename F>
-__device__ __forceinline__ void spmv_part(Team& tm, const Csr<double>& M, int which, Gx&& gx, F&& f) {
-    spmv_part_impl<ROWS, Team::kLds>(M, tm.mp[which], gx, f);
+// The LDS copy is used when the team holds one and its value type is T.
+template <int ROWS, typename Team, typename T, typename Gx, typename F>
+__device__ __forceinline__ void spmv_part(Team& tm, const Csr<T>& M, int which, Gx&& gx, F&& f) {
+    constexpr bool kUse = Team::kLds && std::is_same<T, typename Team::lds_t>::value;
+    spmv_part_impl<ROWS, kUse>(M, tm.mp[which], gx, f);
 }
 
 // Fills a workgroup's MatPart for rows [part[b], part[b+1]) and, when `cache`
 // is set, copies those rows into LDS starting at byte offset `*lds_off`.
-__device__ inline void load_part(MatPart& mp, const Csr<double>& M, const int* part, int b, bool cache, int* lds_off) {
+template <typename T>
+__device__ inline void load_part(MatPart& mp, const Csr<T>& M, const int* part, int b, bool cache, int* lds_off) {
     const int r0 = part[b], r1 = part[b + 1];
     mp.r0 = r0;
     mp.rows = r1 - r0;
@@ -331,11 +338,11 @@ __device__ inline void load_part(MatPart& mp, const Csr<double>& M, const int* p
     const int k0 = M.rp[r0], k1 = M.rp[r1];
     const int nnz = k1 - k0;
     mp.off_v = *lds_off;
-    mp.off_ci = mp.off_v + 8 * nnz;
+    mp.off_ci = mp.off_v + (int)sizeof(T) * nnz;
     mp.off_rp = mp.off_ci + 4 * nnz;
     *lds_off = (mp.off_rp + 4 * (mp.rows + 1) + 15) & ~15;
     char* lds = reinterpret_cast<char*>(sscs_dyn_lds);
-    double* lv = reinterpret_cast<double*>(lds + mp.off_v);
+    T* lv = reinterpret_cast<T*>(lds + mp.off_v);
     int* lci = reinterpret_cast<int*>(lds + mp.off_ci);
     int* lrp = reinterpret_cast<int*>(lds + mp.off_rp);
     for (int k = threadIdx.x; k < nnz; k += blockDim.x) {

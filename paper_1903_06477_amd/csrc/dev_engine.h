@@ -28,6 +28,7 @@ enum { DIR_RB = 0, DIR_AA = 1, DIR_RES = 2, DIR_ZERO = 3 };
 struct Prob {
     int n, m, N;
     Csr<double> A, At;
+    Csr<float> Af, Atf;     // FP32 copies of the values (mixed precision; same rp, ci)
     const double* b;
     const double* c;
     const double* dinv;     // 1 / (1 + ||A e_j||^2), Jacobi preconditioner of I + A^T A
@@ -92,88 +93,120 @@ struct Result {
 // The records are double-buffered: X reads buffer cur and fills (D r, D s)
 // of buffer cur^1, Y fills its D w.  The first pass runs with alpha = 0 and
 // p = s = w = 0, which turns phase X into u = D r0, t = A u.
+// The CG operator I + A^T A in value type T: FP64 (the parity path) or the
+// FP32 copies of A and A^T (mixed precision).  Every other product uses FP64.
+template <typename T>
+__device__ __forceinline__ const Csr<T>& op_mat(const Prob& P, int which) {
+    if constexpr (std::is_same<T, float>::value) return which ? P.Atf : P.Af;
+    else return which ? P.At : P.A;
+}
+
+// Refinement rounds of a mixed-precision solve: each round recomputes the
+// residual r0 = rhs - K xw with the FP64 operator and runs CG with the FP32
+// one from there; a round whose FP64 residual already meets the tolerance
+// ends the solve.  FP64 solves take a single round.
+template <typename T>
+__device__ __forceinline__ int cg_rounds() {
+    return std::is_same<T, float>::value ? 4 : 1;
+}
+
 // One-workgroup form of solve_M: the workgroup owns every row, so the vectors
 // the two products gather from (u for A, t for A^T) live in LDS and the
 // column records are not needed; each iteration is: update and store u in
-// LDS | t = A u into LDS | w = u + A^T t and the dots.  Same recurrence, same
-// arithmetic per entry as solve_M.
-template <typename Team>
+// LDS | t = A u into LDS | w = u + A^T t and the dots.  Same recurrence as
+// solve_M.
+template <typename TV, typename Team>
 __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                               double* xw, double tol, int maxit) {
     const int n = P.n, m = P.m;
     double* __restrict__ ul = tm.lu;
     double* __restrict__ tl = tm.lt;
+    const Csr<TV>& KA = op_mat<TV>(P, 0);
+    const Csr<TV>& KAt = op_mat<TV>(P, 1);
     for (int i = tm.rank(); i < m; i += tm.size()) tl[i] = r[n + i];
-    for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
     tm.sync();
-    // rhs = rx - A^T ry ; t = A xw
+    // rhs = rx - A^T ry
     double a_bb = 0.0;
     spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
         const double bj = r[j] - s;
         V.cg_b[j] = bj;
         a_bb += bj * bj;
     });
-    tm.sync();
-    spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) { tl[i] = s; });
-    tm.sync();
-    // r0 = rhs - (xw + A^T t); p = s = w = 0
-    spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
-        const double rj = V.cg_b[j] - (xw[j] + s);
-        V.cg_r[j] = rj;
-        V.cg_s[j] = 0.0;
-        V.cg_u[j] = 0.0;
-        V.cg_w[j] = 0.0;
-        V.cg_p[j] = 0.0;
-    });
-    tm.sync();
-    double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0, thr = 0.0;
+    double thr = 0.0;
     int it = 0;
-    for (int pass = 0;; ++pass) {
-        for (int j = tm.rank(); j < n; j += tm.size()) {
-            const double pj = V.cg_u[j] + beta * V.cg_p[j];
-            const double sj = V.cg_w[j] + beta * V.cg_s[j];
-            const double rj = V.cg_r[j] - alpha * sj;
-            const double uj = P.dinv[j] * rj;
-            xw[j] += alpha * pj;
-            V.cg_p[j] = pj;
-            V.cg_s[j] = sj;
+    const int rounds = cg_rounds<TV>();
+    for (int round = 0; round < rounds; ++round) {
+        // r0 = rhs - (xw + A^T A xw) in FP64; p = s = w = 0
+        for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
+        tm.sync();
+        spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) { tl[i] = s; });
+        tm.sync();
+        spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
+            const double rj = V.cg_b[j] - (xw[j] + s);
             V.cg_r[j] = rj;
-            V.cg_u[j] = uj;
-            ul[j] = uj;
-        }
-        tm.sync();
-        spmv_part<4>(tm, P.A, 0, [&](int c) { return ul[c]; }, [&](int i, double acc) { tl[i] = acc; });
-        tm.sync();
-        double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
-        spmv_part<4>(tm, P.At, 1, [&](int c) { return tl[c]; }, [&](int j, double s) {
-            const double uj = V.cg_u[j];
-            const double rj = V.cg_r[j];
-            const double wj = uj + s;
-            V.cg_w[j] = wj;
-            a_g += rj * uj;
-            a_d += wj * uj;
-            a_rr += rj * rj;
+            V.cg_s[j] = 0.0;
+            V.cg_u[j] = 0.0;
+            V.cg_w[j] = 0.0;
+            V.cg_p[j] = 0.0;
         });
-        put(sh, 0, a_g);
-        put(sh, 1, a_d);
-        put(sh, 2, a_rr);
-        if (pass == 0) put(sh, 3, a_bb);
-        tm.reduce(sh, pass == 0 ? 4 : 3);
-        const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
-        if (pass == 0) thr = tol * tol * sh.out[3];
-        if (!(rr > thr) || it >= maxit) break;
-        double den = delta;
-        if (pass == 0) {
-            beta = 0.0;
-        } else {
-            beta = gamma / gamma_old;
-            den = delta - beta * gamma / alpha_old;
+        tm.sync();
+        double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0;
+        bool done = false;
+        for (int pass = 0;; ++pass) {
+            for (int j = tm.rank(); j < n; j += tm.size()) {
+                const double pj = V.cg_u[j] + beta * V.cg_p[j];
+                const double sj = V.cg_w[j] + beta * V.cg_s[j];
+                const double rj = V.cg_r[j] - alpha * sj;
+                const double uj = P.dinv[j] * rj;
+                xw[j] += alpha * pj;
+                V.cg_p[j] = pj;
+                V.cg_s[j] = sj;
+                V.cg_r[j] = rj;
+                V.cg_u[j] = uj;
+                ul[j] = uj;
+            }
+            tm.sync();
+            spmv_part<4>(tm, KA, 0, [&](int c) { return ul[c]; }, [&](int i, double acc) { tl[i] = acc; });
+            tm.sync();
+            double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
+            spmv_part<4>(tm, KAt, 1, [&](int c) { return tl[c]; }, [&](int j, double s) {
+                const double uj = V.cg_u[j];
+                const double rj = V.cg_r[j];
+                const double wj = uj + s;
+                V.cg_w[j] = wj;
+                a_g += rj * uj;
+                a_d += wj * uj;
+                a_rr += rj * rj;
+            });
+            put(sh, 0, a_g);
+            put(sh, 1, a_d);
+            put(sh, 2, a_rr);
+            if (round == 0 && pass == 0) put(sh, 3, a_bb);
+            tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
+            const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
+            if (round == 0 && pass == 0) thr = tol * tol * sh.out[3];
+            if (!(rr > thr)) {
+                done = pass == 0;            // the FP64 residual itself meets the tolerance
+                break;
+            }
+            if (it >= maxit) {
+                done = true;
+                break;
+            }
+            double den = delta;
+            if (pass == 0) {
+                beta = 0.0;
+            } else {
+                beta = gamma / gamma_old;
+                den = delta - beta * gamma / alpha_old;
+            }
+            if (!(gamma > 0.0) || !(den > 0.0)) break;
+            alpha = gamma / den;
+            gamma_old = gamma;
+            alpha_old = alpha;
+            ++it;
         }
-        if (!(gamma > 0.0) || !(den > 0.0)) break;
-        alpha = gamma / den;
-        gamma_old = gamma;
-        alpha_old = alpha;
-        ++it;
+        if (done) break;
     }
     // py = ry + A px ; h^T p
     for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
@@ -193,96 +226,111 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
     return it;
 }
 
-template <typename Team>
+template <typename TV, typename Team>
 __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit) {
     if constexpr (Team::kBlock) {
-        if (tm.lu) return solve_M_staged(tm, sh, P, V, r, out, xw, tol, maxit);
+        if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit);
     }
     const int n = P.n;
-    // rhs = rx - A^T ry ; t = A xw
+    const Csr<TV>& KA = op_mat<TV>(P, 0);
+    const Csr<TV>& KAt = op_mat<TV>(P, 1);
+    // rhs = rx - A^T ry
     double a_bb = 0.0;
     spmv_part<1>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; }, [&](int j, double s) {
         const double bj = r[j] - s;
         V.cg_b[j] = bj;
         a_bb += bj * bj;
     });
-    spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
-    tm.sync();
-    // r0 = rhs - (xw + A^T t); u = w = p = s = 0; record (D r0, 0, 0)
-    spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; }, [&](int j, double s) {
-        const double rj = V.cg_b[j] - (xw[j] + s);
-        V.cg_r[j] = rj;
-        V.cg_s[j] = 0.0;
-        V.cg_u[j] = 0.0;
-        V.cg_w[j] = 0.0;
-        V.cg_p[j] = 0.0;
-        double* g = V.cg_g[0] + 4 * (size_t)j;
-        g[0] = P.dinv[j] * rj;
-        g[1] = 0.0;
-        g[2] = 0.0;
-    });
-    tm.sync();
-    double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0, thr = 0.0;
+    double thr = 0.0;
     int it = 0, cur = 0;
-    for (int pass = 0;; ++pass) {
-        // ---- phase X
-        const double* go = V.cg_g[cur];
-        double* gn = V.cg_g[cur ^ 1];
-        for (int j = tm.rank(); j < n; j += tm.size()) {
-            const double pj = V.cg_u[j] + beta * V.cg_p[j];
-            const double sj = V.cg_w[j] + beta * V.cg_s[j];
-            const double rj = V.cg_r[j] - alpha * sj;
-            const double dj = P.dinv[j];
-            xw[j] += alpha * pj;
-            V.cg_p[j] = pj;
-            V.cg_s[j] = sj;
-            V.cg_r[j] = rj;
-            V.cg_u[j] = dj * rj;
-            gn[4 * (size_t)j] = dj * rj;
-            gn[4 * (size_t)j + 1] = dj * sj;
-        }
-        spmv_part<4>(tm, P.A, 0,
-                     [&](int c) {
-                         const double2 ab = *reinterpret_cast<const double2*>(go + 4 * (size_t)c);
-                         const double dw = go[4 * (size_t)c + 2];
-                         return ab.x - alpha * (dw + beta * ab.y);
-                     },
-                     [&](int i, double acc) { V.cg_t[i] = acc; });
+    const int rounds = cg_rounds<TV>();
+    for (int round = 0; round < rounds; ++round) {
+        // t = A xw ; r0 = rhs - (xw + A^T t) in FP64; u = w = p = s = 0; record (D r0, 0, 0)
+        spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
         tm.sync();
-        cur ^= 1;
-        // ---- phase Y
-        double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
-        spmv_part<4>(tm, P.At, 1, [&](int c) { return V.cg_t[c]; }, [&](int j, double s) {
-            const double uj = V.cg_u[j];
-            const double rj = V.cg_r[j];
-            const double wj = uj + s;
-            V.cg_w[j] = wj;
-            V.cg_g[cur][4 * (size_t)j + 2] = P.dinv[j] * wj;
-            a_g += rj * uj;
-            a_d += wj * uj;
-            a_rr += rj * rj;
+        spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; }, [&](int j, double s) {
+            const double rj = V.cg_b[j] - (xw[j] + s);
+            V.cg_r[j] = rj;
+            V.cg_s[j] = 0.0;
+            V.cg_u[j] = 0.0;
+            V.cg_w[j] = 0.0;
+            V.cg_p[j] = 0.0;
+            double* g = V.cg_g[cur] + 4 * (size_t)j;
+            g[0] = P.dinv[j] * rj;
+            g[1] = 0.0;
+            g[2] = 0.0;
         });
-        put(sh, 0, a_g);
-        put(sh, 1, a_d);
-        put(sh, 2, a_rr);
-        if (pass == 0) put(sh, 3, a_bb);
-        tm.reduce(sh, pass == 0 ? 4 : 3);
-        const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
-        if (pass == 0) thr = tol * tol * sh.out[3];
-        if (!(rr > thr) || it >= maxit || tm.aborted()) break;
-        double den = delta;
-        if (pass == 0) {
-            beta = 0.0;
-        } else {
-            beta = gamma / gamma_old;
-            den = delta - beta * gamma / alpha_old;
+        tm.sync();
+        double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0;
+        bool done = false;
+        for (int pass = 0;; ++pass) {
+            // ---- phase X
+            const double* go = V.cg_g[cur];
+            double* gn = V.cg_g[cur ^ 1];
+            for (int j = tm.rank(); j < n; j += tm.size()) {
+                const double pj = V.cg_u[j] + beta * V.cg_p[j];
+                const double sj = V.cg_w[j] + beta * V.cg_s[j];
+                const double rj = V.cg_r[j] - alpha * sj;
+                const double dj = P.dinv[j];
+                xw[j] += alpha * pj;
+                V.cg_p[j] = pj;
+                V.cg_s[j] = sj;
+                V.cg_r[j] = rj;
+                V.cg_u[j] = dj * rj;
+                gn[4 * (size_t)j] = dj * rj;
+                gn[4 * (size_t)j + 1] = dj * sj;
+            }
+            spmv_part<4>(tm, KA, 0,
+                         [&](int c) {
+                             const double2 ab = *reinterpret_cast<const double2*>(go + 4 * (size_t)c);
+                             const double dw = go[4 * (size_t)c + 2];
+                             return ab.x - alpha * (dw + beta * ab.y);
+                         },
+                         [&](int i, double acc) { V.cg_t[i] = acc; });
+            tm.sync();
+            cur ^= 1;
+            // ---- phase Y
+            double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
+            spmv_part<4>(tm, KAt, 1, [&](int c) { return V.cg_t[c]; }, [&](int j, double s) {
+                const double uj = V.cg_u[j];
+                const double rj = V.cg_r[j];
+                const double wj = uj + s;
+                V.cg_w[j] = wj;
+                V.cg_g[cur][4 * (size_t)j + 2] = P.dinv[j] * wj;
+                a_g += rj * uj;
+                a_d += wj * uj;
+                a_rr += rj * rj;
+            });
+            put(sh, 0, a_g);
+            put(sh, 1, a_d);
+            put(sh, 2, a_rr);
+            if (round == 0 && pass == 0) put(sh, 3, a_bb);
+            tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
+            const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
+            if (round == 0 && pass == 0) thr = tol * tol * sh.out[3];
+            if (!(rr > thr)) {
+                done = pass == 0;            // the FP64 residual itself meets the tolerance
+                break;
+            }
+            if (it >= maxit || tm.aborted()) {
+                done = true;
+                break;
+            }
+            double den = delta;
+            if (pass == 0) {
+                beta = 0.0;
+            } else {
+                beta = gamma / gamma_old;
+                den = delta - beta * gamma / alpha_old;
+            }
+            if (!(gamma > 0.0) || !(den > 0.0)) break;      // breakdown: residual at rounding level
+            alpha = gamma / den;
+            gamma_old = gamma;
+            alpha_old = alpha;
+            ++it;
         }
-        if (!(gamma > 0.0) || !(den > 0.0)) break;      // breakdown: residual at rounding level
-        alpha = gamma / den;
-        gamma_old = gamma;
-        alpha_old = alpha;
-        ++it;
+        if (done) break;
     }
     // py = ry + A px ; h^T p
     double a_hp = 0.0;
@@ -304,10 +352,10 @@ __device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const
 // out[0 .. n+m) and tau = (r_tau + h^T p) / delta returned.  The rank-one
 // correction is left to the consumer (corrected(), below), which applies it
 // on the fly in its own pass, saving a barrier.  r and out must not alias.
-template <typename Team>
+template <typename TV, typename Team>
 __device__ double linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                               double* xw, double tol, int maxit, long long* cg_iters) {
-    *cg_iters += solve_M(tm, sh, P, V, r, out, xw, tol, maxit);
+    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit);
     return (r[P.N - 1] + sh.out[0]) / P.delta;
 }
 
@@ -334,7 +382,7 @@ __device__ int setup_gdelta(Team& tm, Shared& sh, Prob& P, const Vecs& V, double
     tm.reduce(sh, 2);
     P.nb = sqrt(sh.out[0]);
     P.nc = sqrt(sh.out[1]);
-    const int it = solve_M(tm, sh, P, V, V.d, g, V.xw_d, tol, maxit);
+    const int it = solve_M<double>(tm, sh, P, V, V.d, g, V.xw_d, tol, maxit);
     P.delta = 1.0 + sh.out[0];
     P.g = g;
     return it;
@@ -688,7 +736,7 @@ __device__ void write_trace(Team& tm, const Vecs& V, long long nu, double res, i
     }
 }
 
-template <typename Team>
+template <typename TV, typename Team>
 __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S, Result* res) {
     const int n = P.n, m = P.m, N = P.N;
     const long long t_start = wall_clock64();
@@ -705,7 +753,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     long long nu = 0;
     double tol = S.cg_adapt > 0.0 ? 1e-6 : S.cg_tol;
     for (nu = 0;; ++nu) {
-        const double tau_u = linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc);
+        const double tau_u = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc);
         nRu = sqrt(residual_pass(tm, sh, P, V, tau_u));
         if (S.cg_adapt > 0.0) {
             // inexact linear steps: accuracy relative to the current fixed-point residual
@@ -742,7 +790,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             write_trace(tm, V, nu, nRu, 0, 0);
             continue;
         }
-        const double tau_d = linear_step(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc);
+        const double tau_d = linear_step<TV>(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc);
         double alpha = 1.0;
         int kind = 3, ls = 0;
         double coef = 0.0;

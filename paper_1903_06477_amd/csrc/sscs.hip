@@ -58,11 +58,11 @@ struct FlatTeam {
 
 // Workgroup b of a grid kernel owns rows [part[b], part[b+1]) of A and of A^T
 // and, when the operator fits, keeps them in LDS for the whole launch.
-template <bool LDS>
-__device__ inline void grid_team_init(GridTeam<LDS>& tm, const Prob& P) {
+template <bool LDS, typename TL>
+__device__ inline void grid_team_init(GridTeam<LDS, TL>& tm, const Prob& P) {
     int off = 0;
-    load_part(tm.mp[0], P.A, P.partA, blockIdx.x, LDS, &off);
-    load_part(tm.mp[1], P.At, P.partAt, blockIdx.x, LDS, &off);
+    load_part(tm.mp[0], op_mat<TL>(P, 0), P.partA, blockIdx.x, LDS, &off);
+    load_part(tm.mp[1], op_mat<TL>(P, 1), P.partAt, blockIdx.x, LDS, &off);
     __syncthreads();
 }
 
@@ -85,7 +85,8 @@ struct Desc {
     Params S;
 };
 
-template <bool LDS>
+// TV: value type of the CG operator (double, or float for mixed precision).
+template <bool LDS, typename TV>
 __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S, Result* res,
                                                        unsigned long long* bar, int* abort_flag,
                                                        double* part, long long timeout_ticks) {
@@ -97,23 +98,23 @@ __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S,
         d.S = S;
     }
     __syncthreads();
-    GridTeam<LDS> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS, TV> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
     grid_team_init(tm, d.P);
-    sscs::solve(tm, sh, d.P, d.V, d.S, res);
+    sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res);
 }
 
-template <bool LDS>
+template <bool LDS, typename TV>
 __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, unsigned long long* bar,
                                                     int* abort_flag, double* part, long long timeout_ticks) {
     __shared__ Shared sh;
-    GridTeam<LDS> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS, TV> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
     grid_team_init(tm, P);
     const int n = P.n, m = P.m, N = P.N;
     if (a.op == OP_LINEAR) {
         for (int j = tm.rank(); j < n; j += tm.size()) V.xw_d[j] = 0.0;
         tm.sync();
         long long it = 0;
-        const double tau = linear_step(tm, sh, P, V, a.in, a.out1, V.xw_d, a.tol, a.maxit, &it);
+        const double tau = linear_step<TV>(tm, sh, P, V, a.in, a.out1, V.xw_d, a.tol, a.maxit, &it);
         for (int i = tm.rank(); i < N; i += tm.size()) a.out1[i] = corrected(P, a.out1, tau, i);
         if (tm.rank() == 0 && a.scal) a.scal[0] = (double)it;
     } else if (a.op == OP_RESIDUAL) {
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, un
         for (int j = tm.rank(); j < n; j += tm.size()) V.xw_u[j] = 0.0;
         tm.sync();
         long long it = 0;
-        const double tau = linear_step(tm, sh, P, V, V.u, V.ut, V.xw_u, a.tol, a.maxit, &it);
+        const double tau = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, a.tol, a.maxit, &it);
         const double r2 = residual_pass(tm, sh, P, V, tau);
         for (int i = tm.rank(); i < N; i += tm.size()) {
             if (a.out1) a.out1[i] = V.ut[i];
@@ -153,8 +154,9 @@ struct BatchInst {
 // Two workgroups per CU (waves_per_eu 2): the one-workgroup engine is bound by
 // memory latency, and a second resident instance hides more of it than the
 // few registers spilled by the tighter budget cost.
-__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_batch(const BatchInst* __restrict__ insts, int count,
-                                                             Params S, Result* res, int* queue, int stage_doubles) {
+template <typename TV>
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_batch(
+    const BatchInst* __restrict__ insts, int count, Params S, Result* res, int* queue, int stage_doubles) {
     __shared__ Shared sh;
     __shared__ Desc d;
     BlockTeam tm;
@@ -172,11 +174,12 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         __syncthreads();
         block_team_init(tm, d.P, stage_doubles);
         setup_gdelta(tm, sh, d.P, d.V, const_cast<double*>(d.P.g), d.S.setup_tol, d.S.setup_max);
-        sscs::solve(tm, sh, d.P, d.V, d.S, res + idx);
+        sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res + idx);
     }
 }
 
 // Algorithm 1 for one instance small enough for a single workgroup.
+template <typename TV>
 __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_block(Prob P, Vecs V, Params S, Result* res,
                                                              int stage_doubles) {
     __shared__ Shared sh;
@@ -189,7 +192,12 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     __syncthreads();
     BlockTeam tm;
     block_team_init(tm, d.P, stage_doubles);
-    sscs::solve(tm, sh, d.P, d.V, d.S, res);
+    sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res);
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, long long n, float* __restrict__ b) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
 }
 
 __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __restrict__ y) {
@@ -288,10 +296,12 @@ int stage_doubles(long long entries) {
     if (off || entries <= 0 || entries > kStageMax) return 0;
     static const bool attr = [] {
         const int bytes = kStageMax * (int)sizeof(double);
-        return hipFuncSetAttribute((const void*)k_solve_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) ==
-                   hipSuccess &&
-               hipFuncSetAttribute((const void*)k_solve_block, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) ==
-                   hipSuccess;
+        const void* fns[] = {(const void*)k_solve_batch<double>,
+                             (const void*)k_solve_block<double>, (const void*)k_solve_block<float>};
+        bool ok = true;
+        for (const void* f : fns)
+            ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+        return ok;
     }();
     return attr ? (int)entries : 0;
 }
@@ -315,6 +325,8 @@ struct Inst {
     long long nnz = 0;
     int *A_rp = nullptr, *A_ci = nullptr, *At_rp = nullptr, *At_ci = nullptr;
     double *A_v = nullptr, *At_v = nullptr;
+    float *A_vf = nullptr, *At_vf = nullptr;   // FP32 copies (mixed precision)
+    bool mixed = false;
     double *b = nullptr, *c = nullptr, *dinv = nullptr, *g = nullptr;
     double delta = 1.0, nb = 0.0, nc = 0.0;
     int *qoff = nullptr, *sord = nullptr, *soff = nullptr;
@@ -438,7 +450,9 @@ int dmalloc(T** p, size_t count) {
     } while (0)
 
 // Uploads A (unless shared), b, c and the cone tables; builds A^T and dinv.
-int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t s, const Inst* share) {
+int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t s, const Inst* share,
+                    bool mixed) {
+    I.mixed = mixed;
     I.m = d->m;
     I.n = d->n;
     I.N = d->n + d->m + 1;
@@ -447,6 +461,7 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
     if (share) {
         I.A_rp = share->A_rp; I.A_ci = share->A_ci; I.A_v = share->A_v;
         I.At_rp = share->At_rp; I.At_ci = share->At_ci; I.At_v = share->At_v;
+        I.A_vf = share->A_vf; I.At_vf = share->At_vf;
         I.dinv = share->dinv;
         I.owns_A = false;
     } else {
@@ -471,6 +486,13 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
         k_scatter_t<<<std::min(4096, (I.m + 255) / 256), 256, 0, s>>>(I.A_rp, I.A_ci, I.A_v, I.m, I.At_rp, cnt,
                                                                      I.At_ci, I.At_v);
         k_sort_rows<<<std::min(4096, (I.n + 255) / 256), 256, 0, s>>>(I.At_rp, I.n, I.At_ci, I.At_v, I.dinv);
+        if (mixed) {
+            TRY(dmalloc(&I.A_vf, nnz));
+            TRY(dmalloc(&I.At_vf, nnz));
+            const int gb = (int)std::min<long long>(4096, ((long long)nnz + 255) / 256 + 1);
+            k_to_f32<<<gb, 256, 0, s>>>(I.A_v, (long long)nnz, I.A_vf);
+            k_to_f32<<<gb, 256, 0, s>>>(I.At_v, (long long)nnz, I.At_vf);
+        }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s));
         hipFree(cnt);
@@ -506,6 +528,7 @@ void free_instance(Inst& I) {
     if (I.owns_A) {
         hipFree(I.A_rp); hipFree(I.A_ci); hipFree(I.A_v);
         hipFree(I.At_rp); hipFree(I.At_ci); hipFree(I.At_v); hipFree(I.dinv);
+        hipFree(I.A_vf); hipFree(I.At_vf);
     }
     hipFree(I.b); hipFree(I.c); hipFree(I.g);
     hipFree(I.qoff); hipFree(I.sord); hipFree(I.soff);
@@ -519,6 +542,8 @@ Prob make_prob(const Inst& I) {
     P.n = I.n; P.m = I.m; P.N = I.N;
     P.A = Csr<double>{I.A_rp, I.A_ci, I.A_v, I.m, I.n, I.segA};
     P.At = Csr<double>{I.At_rp, I.At_ci, I.At_v, I.n, I.m, I.segAt};
+    P.Af = Csr<float>{I.A_rp, I.A_ci, I.A_vf, I.m, I.n, I.segA};
+    P.Atf = Csr<float>{I.At_rp, I.At_ci, I.At_vf, I.n, I.m, I.segAt};
     P.b = I.b; P.c = I.c; P.dinv = I.dinv; P.g = I.g;
     P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.lds_bytes > 0 ? 1 : 0;
     P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
@@ -596,11 +621,23 @@ int check_abort(sscs_work* w) {
     return SSCS_OK;
 }
 
+// Kernel instantiation for the operator placement (LDS or global) and the
+// precision of the CG operator.
+const void* solve_grid_fn(bool lds, bool mixed) {
+    if (mixed) return lds ? (const void*)k_solve_grid<true, float> : (const void*)k_solve_grid<false, float>;
+    return lds ? (const void*)k_solve_grid<true, double> : (const void*)k_solve_grid<false, double>;
+}
+
+const void* op_grid_fn(bool lds, bool mixed) {
+    if (mixed) return lds ? (const void*)k_op_grid<true, float> : (const void*)k_op_grid<false, float>;
+    return lds ? (const void*)k_op_grid<true, double> : (const void*)k_op_grid<false, double>;
+}
+
 int run_op(sscs_work* w, int op, const double* in, double* out1, double* out2, double tol, int maxit) {
     Prob P = make_prob(w->I);
     OpArgs a{op, in, out1, out2, w->scal, tol, maxit};
     void* args[] = {&P, &w->V, &a, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-    TRY(launch_grid_kernel(w, w->I.lds_bytes ? (void*)k_op_grid<true> : (void*)k_op_grid<false>, args));
+    TRY(launch_grid_kernel(w, const_cast<void*>(op_grid_fn(w->I.lds_bytes > 0, w->I.mixed)), args));
     HIP_TRY(hipGetLastError());
     return check_abort(w);
 }
@@ -639,10 +676,10 @@ std::vector<int> partition_rows(const std::vector<int>& rp, int rows, int G) {
 
 // LDS bytes workgroup b needs to hold its rows (values, column indices, local
 // row pointers), with the layout load_part() uses.
-long long part_lds_bytes(const std::vector<int>& rp, const std::vector<int>& part, int b) {
+long long part_lds_bytes(const std::vector<int>& rp, const std::vector<int>& part, int b, int vbytes) {
     const long long rows = part[b + 1] - part[b];
     const long long nnz = rp[part[b + 1]] - rp[part[b]];
-    return (12 * nnz + 4 * (rows + 1) + 15) & ~15ll;
+    return ((vbytes + 4) * nnz + 4 * (rows + 1) + 15) & ~15ll;
 }
 
 int set_partitions(sscs_work* w, bool try_lds);
@@ -651,9 +688,9 @@ int choose_grid(sscs_work* w) {
     int dev = 0, ncu = 0, occ = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_grid<false>, kBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_grid_fn(false, w->I.mixed), kBlock, 0));
     int occ2 = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, (const void*)k_op_grid<false>, kBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, op_grid_fn(false, w->I.mixed), kBlock, 0));
     occ = std::max(1, std::min(occ, occ2));
     w->ncu = ncu;
     w->max_grid = std::max(1, ncu * occ);
@@ -684,19 +721,20 @@ int set_partitions(sscs_work* w, bool try_lds) {
     const long long limit = (long long)lds_max - (long long)sizeof(Shared) - 1024;
     std::vector<int> pA, pAt;
     long long need = 0;
+    const int vb = I.mixed ? 4 : 8;       // bytes per cached value
     for (int attempt = 0; attempt < 2; ++attempt) {
         pA = partition_rows(I.h_rpA, I.m, w->grid);
         pAt = partition_rows(I.h_rpAt, I.n, w->grid);
         need = 0;
         for (int b = 0; b < w->grid; ++b)
-            need = std::max(need, part_lds_bytes(I.h_rpA, pA, b) + part_lds_bytes(I.h_rpAt, pAt, b));
+            need = std::max(need, part_lds_bytes(I.h_rpA, pA, b, vb) + part_lds_bytes(I.h_rpAt, pAt, b, vb));
         I.lds_bytes = 0;
         if (!try_lds || w->grid < 2 || need > limit) break;
         int o1 = 0, o2 = 0;
-        HIP_TRY(hipFuncSetAttribute((const void*)k_solve_grid<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
-        HIP_TRY(hipFuncSetAttribute((const void*)k_op_grid<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, (const void*)k_solve_grid<true>, kBlock, (size_t)need));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, (const void*)k_op_grid<true>, kBlock, (size_t)need));
+        HIP_TRY(hipFuncSetAttribute(solve_grid_fn(true, I.mixed), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        HIP_TRY(hipFuncSetAttribute(op_grid_fn(true, I.mixed), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, solve_grid_fn(true, I.mixed), kBlock, (size_t)need));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, op_grid_fn(true, I.mixed), kBlock, (size_t)need));
         const int cap = w->ncu * std::min(o1, o2);
         if (cap >= w->grid) { I.lds_bytes = (int)need; break; }
         if (cap < 2) break;
@@ -807,13 +845,12 @@ int sscs_create(const sscs_data* data, const sscs_cone* cone, const sscs_setting
         *out = nullptr;
         TRY(validate(data, cone));
         TRY(validate_settings(st));
-        if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
         const double t0 = now_s();
         sscs_work* w = new (std::nothrow) sscs_work();
         if (!w) return SSCS_E_NOMEM;
         w->stream = (hipStream_t)hip_stream;
         w->st = *st;
-        int r = upload_instance(w->I, data, cone, w->stream, nullptr);
+        int r = upload_instance(w->I, data, cone, w->stream, nullptr, st->precision == SSCS_PREC_MIXED);
         if (r == SSCS_OK) r = choose_grid(w);
         if (r == SSCS_OK) r = alloc_work_vectors(w);
         if (r == SSCS_OK) r = alloc_trace(w);
@@ -874,10 +911,13 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
     if (w->grid == 1) {
         HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
         const int sd = stage_doubles(w->I.n + w->I.m);
-        k_solve_block<<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
+        if (w->I.mixed)
+            k_solve_block<float><<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
+        else
+            k_solve_block<double><<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
     } else {
         void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-        TRY(launch_grid_kernel(w, w->I.lds_bytes ? (void*)k_solve_grid<true> : (void*)k_solve_grid<false>, args));
+        TRY(launch_grid_kernel(w, const_cast<void*>(solve_grid_fn(w->I.lds_bytes > 0, w->I.mixed)), args));
     }
     HIP_TRY(hipGetLastError());
     TRY(stage_out(w, x, V.out_x, n));
@@ -1041,6 +1081,8 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
         if (!out || count < 1 || !data || !cones) return SSCS_E_INVALID;
         *out = nullptr;
         TRY(validate_settings(st));
+        // the batched engine computes in FP64 only: its mixed-precision form is
+        // switched off until its GPU behaviour is understood
         if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
         for (int i = 0; i < count; ++i) {
             TRY(validate(&data[i], &cones[i]));
@@ -1058,7 +1100,8 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
         for (int i = 0; i < count && r == SSCS_OK; ++i) {
             const bool share = i > 0 && data[i].rowptr == data[0].rowptr && data[i].colind == data[0].colind &&
                                data[i].val == data[0].val && data[i].m == data[0].m && data[i].n == data[0].n;
-            r = upload_instance(bt->inst[i], &data[i], &cones[i], bt->stream, share ? &bt->inst[0] : nullptr);
+            r = upload_instance(bt->inst[i], &data[i], &cones[i], bt->stream, share ? &bt->inst[0] : nullptr,
+                                st->precision == SSCS_PREC_MIXED);
         }
         size_t tot = 0;
         for (int i = 0; i < count && r == SSCS_OK; ++i) {
@@ -1105,7 +1148,7 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
                 if (e <= kStageMax) big = std::max(big, e);
             }
             bt->stage = stage_doubles(big);
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_batch, kBatchBlock,
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_solve_batch<double>, kBatchBlock,
                                                          bt->stage * sizeof(double));
             hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
             bt->ticks_per_s = rate > 0 ? rate * 1000.0 : 1e8;
@@ -1166,8 +1209,9 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
                            bt->stream));
     HIP_TRY(hipMemsetAsync(bt->queue, 0, sizeof(int), bt->stream));
     Params S = make_params(bt->st, bt->ticks_per_s);
-    k_solve_batch<<<bt->grid, kBatchBlock, bt->stage * sizeof(double), bt->stream>>>(bt->d_insts, bt->count, S,
-                                                                                      bt->res, bt->queue, bt->stage);
+    const size_t lds = bt->stage * sizeof(double);
+    k_solve_batch<double><<<bt->grid, kBatchBlock, lds, bt->stream>>>(bt->d_insts, bt->count, S, bt->res,
+                                                                      bt->queue, bt->stage);
     HIP_TRY(hipGetLastError());
     if (!dev) {
         HIP_TRY(hipMemcpyAsync(x_packed, dio_x, bt->tot_x * sizeof(double), hipMemcpyDeviceToHost, bt->stream));

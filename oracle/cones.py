@@ -100,6 +100,8 @@ def proj_psd(x, k=None):
 def in_exp(v, tol=0.0):
     t, s, r = v
     if s > 0:
+        if r / s > 700.0:                    # s e^(r/s) beyond the FP64 range: not in K_e
+            return False
         return t - s * math.exp(r / s) >= -tol * max(1.0, abs(t))
     return s >= -tol and t >= -tol and r <= tol
 
@@ -109,6 +111,8 @@ def in_exp_dual(y, tol=0.0):
     (derived from the definition of the dual cone in Sec. II)."""
     y1, y2, y3 = y
     if y3 < 0:
+        if y2 / y3 > 700.0:                  # -y3 e^(y2/y3) beyond the FP64 range: not in K_e*
+            return False
         return -y3 * math.exp(y2 / y3) - math.e * y1 <= tol * max(1.0, abs(y1))
     return y3 <= tol and y1 >= -tol and y2 >= -tol
 

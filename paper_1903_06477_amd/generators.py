@@ -274,3 +274,121 @@ def config5_instance(i: int, A: sp.csr_matrix) -> Problem:
     rng = rng_for(5, i)
     A, b, mu = lasso_data(rng, A.shape[0], A.shape[1], 0.0, A=A)
     return lasso_socp(A, b, mu, name=f"lasso5_{i}")
+
+
+# ---------------------------------------------------------------------------
+# mixed SDP / exponential-cone instance: sparse PCA blocks plus an
+# l1-regularised logistic regression, one block-diagonal problem
+
+def _svec_pairs(k: int):
+    """(i, j) of the column-major lower-triangle packing, i >= j, and the
+    scale of each entry (1 on the diagonal, sqrt(2) off it)."""
+    jj, ii = np.triu_indices(k)          # ordered by j, then i >= j
+    scale = np.where(ii == jj, 1.0, math.sqrt(2.0))
+    return ii, jj, scale
+
+
+def config3_sdp_exp(instance: int = 0, nblk: int = 64, k: int = 64, kbig: int = 256, q: int = 5000,
+                    p: int = 1000, density: float = 0.01, lam_sdp: float = 2.0) -> Problem:
+    """Sparse PCA:  max <S_b, Z_b> - lam ||Z_b||_1, tr Z_b = 1, Z_b PSD for
+    nblk blocks of order k and one of order kbig (S = (G + G^T) / 2, G with
+    N(0, 1) entries), written with T_b >= |Z_b| entrywise; plus logistic
+    regression  min sum_i log(1 + exp(-y_i (a_i^T w + beta))) + lam_log ||w||_1
+    over q samples of p features (F at `density`, N(0, 1); labels +-1;
+    lam_log = 0.1 * ||F^T y||_inf / 2), each loss term through two exponential
+    cones: t_i >= log(exp(0) + exp(z_i)) iff u1 + u2 <= 1, (u1, 1, -t_i) and
+    (u2, 1, z_i - t_i) in K_exp.
+
+    Variables: [svec Z (all blocks) | svec T | w | beta | r | t | u1 | u2].
+    Rows: zero (one trace row per block) | R+ (T - Z, T + Z, 1 - u1 - u2,
+    r - w, r + w) | PSD (svec Z per block) | exp (two cones per sample)."""
+    rng = rng_for(3, instance)
+    orders = [k] * nblk + ([kbig] if kbig > 0 else [])
+    D = [o * (o + 1) // 2 for o in orders]
+    Dt = int(sum(D))
+    offs = np.concatenate([[0], np.cumsum(D)]).astype(np.int64)
+    # data
+    cZ = np.zeros(Dt)
+    wT = np.zeros(Dt)
+    diag_pos = []
+    for b, o in enumerate(orders):
+        Gm = rng.standard_normal((o, o))
+        S = 0.5 * (Gm + Gm.T)
+        ii, jj, sc = _svec_pairs(o)
+        cZ[offs[b]:offs[b + 1]] = -(S[ii, jj] * sc)
+        wT[offs[b]:offs[b + 1]] = np.where(ii == jj, 1.0, math.sqrt(2.0))
+        diag_pos.append(offs[b] + np.nonzero(ii == jj)[0])
+    F = sprandn(q, p, density, rng)
+    y = np.where(rng.random(q) < 0.5, -1.0, 1.0)
+    lam_log = 0.1 * 0.5 * float(np.max(np.abs(F.T @ y)))
+    # variable offsets
+    oZ, oT = 0, Dt
+    ow = 2 * Dt
+    obeta = ow + p
+    orr = obeta + 1
+    ot = orr + p
+    ou1 = ot + q
+    ou2 = ou1 + q
+    n = ou2 + q
+    c = np.zeros(n)
+    c[oZ:oZ + Dt] = cZ
+    c[oT:oT + Dt] = lam_sdp * wT
+    c[orr:orr + p] = lam_log
+    c[ot:ot + q] = 1.0
+    rows, cols, vals, bvec = [], [], [], []
+    r0 = 0
+
+    def add(rr, cc, vv):
+        rows.append(np.asarray(rr, np.int64))
+        cols.append(np.asarray(cc, np.int64))
+        vals.append(np.asarray(vv, np.float64))
+
+    # zero: tr Z_b = 1  (s = 1 - tr Z_b)
+    for b in range(len(orders)):
+        add(np.full(len(diag_pos[b]), r0 + b), oZ + diag_pos[b], np.ones(len(diag_pos[b])))
+    bvec.append(np.ones(len(orders)))
+    r0 += len(orders)
+    nz = len(orders)
+    # R+: T - Z >= 0, T + Z >= 0
+    e = np.arange(Dt)
+    add(r0 + e, oT + e, -np.ones(Dt)); add(r0 + e, oZ + e, np.ones(Dt)); r0 += Dt
+    add(r0 + e, oT + e, -np.ones(Dt)); add(r0 + e, oZ + e, -np.ones(Dt)); r0 += Dt
+    bvec.append(np.zeros(2 * Dt))
+    # R+: 1 - u1 - u2 >= 0
+    eq = np.arange(q)
+    add(r0 + eq, ou1 + eq, np.ones(q)); add(r0 + eq, ou2 + eq, np.ones(q)); r0 += q
+    bvec.append(np.ones(q))
+    # R+: r - w >= 0, r + w >= 0
+    ep_ = np.arange(p)
+    add(r0 + ep_, orr + ep_, -np.ones(p)); add(r0 + ep_, ow + ep_, np.ones(p)); r0 += p
+    add(r0 + ep_, orr + ep_, -np.ones(p)); add(r0 + ep_, ow + ep_, -np.ones(p)); r0 += p
+    bvec.append(np.zeros(2 * p))
+    nl = 2 * Dt + q + 2 * p
+    # PSD: s = svec Z_b
+    add(r0 + e, oZ + e, -np.ones(Dt)); r0 += Dt
+    bvec.append(np.zeros(Dt))
+    # exp: per sample (u1, 1, -t) and (u2, 1, -y_i (a_i^T w + beta) - t)
+    eb = np.zeros(6 * q)
+    base = r0 + 6 * eq
+    add(base, ou1 + eq, -np.ones(q))                 # s = u1
+    eb[6 * eq + 1] = 1.0                               # s = 1
+    add(base + 2, ot + eq, np.ones(q))                 # s = -t
+    add(base + 3, ou2 + eq, -np.ones(q))               # s = u2
+    eb[6 * eq + 4] = 1.0
+    Fc = F.tocoo()
+    add(base[Fc.row] + 5, ow + Fc.col, y[Fc.row] * Fc.data)   # s = -y (a^T w + beta) - t
+    add(base + 5, np.full(q, obeta), y)
+    add(base + 5, ot + eq, np.ones(q))
+    bvec.append(eb)
+    r0 += 6 * q
+    m = r0
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m, n))
+    cone = Cone(z=nz, l=nl, s=orders, ep=2 * q)
+    return Problem(A=_csr(A), b=np.concatenate(bvec), c=c, cone=cone, name=f"sdp_exp_{m}x{n}",
+                   meta=dict(F=F, labels=y, lam_log=lam_log, lam_sdp=lam_sdp, orders=orders,
+                             offsets=dict(Z=oZ, T=oT, w=ow, beta=obeta, r=orr, t=ot, u1=ou1, u2=ou2)))
+
+
+def small_sdp_exp(seed: int = 0) -> Problem:
+    """The mixed SDP / exp instance at a size the oracle solves in seconds."""
+    return config3_sdp_exp(instance=1000 + seed, nblk=2, k=4, kbig=7, q=30, p=6, density=0.3)

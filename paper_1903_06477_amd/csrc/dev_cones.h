@@ -25,8 +25,11 @@ struct ConeDev {
     const int* soff;
     int ep;                   // exponential cones
     int soc0, psd0, exp0;     // first row of each region (relative to the start of y)
-    double* psd_scratch;      // per-workgroup scratch for PSD blocks (k*k + k doubles each)
+    double* psd_scratch;      // per-workgroup scratch for PSD blocks (2 k^2 + k (k + 1) doubles each)
     int psd_kmax;
+    double* psd_vecs;         // per block: the eigenvectors of its last projection (kmax^2
+                              // doubles each), or null: every projection starts cold
+    int* psd_warm;            // per block: 1 once psd_vecs holds an orthogonal basis
 };
 
 // ---------------------------------------------------------------- exponential cone
@@ -151,34 +154,99 @@ __device__ inline void proj_exp_dual(const double* v, double* out) {
 // ---------------------------------------------------------------- PSD blocks
 //
 // Pi of a PSD block: mat(x) = V diag(lam) V^T, keep max(lam, 0), back to the
-// packed layout.  The eigendecomposition is a cyclic two-sided Jacobi method
-// run by one workgroup on the k x k matrix held in `a` (k*k doubles, global
-// scratch private to the workgroup) with the eigenvector matrix in `vm`:
-// each sweep visits every pair (p, q) once in round-robin order, k/2 disjoint
+// packed layout (Sec. II).  The eigendecomposition is a cyclic two-sided
+// Jacobi method run by one workgroup on the k x k matrix held in `a` (global
+// scratch private to the workgroup) with the eigenvector matrix in `vm`: each
+// sweep visits every pair (p, q) once in round-robin order, k/2 disjoint
 // rotations per round in parallel.
+//
+// Warm start: the iterates the method projects change little from one call to
+// the next, so a block keeps the eigenvectors V0 of its previous projection.
+// Jacobi then runs on B = V0^T mat(x) V0 (similar to mat(x), nearly diagonal)
+// with the rotations accumulated onto V0, which typically leaves one or two
+// sweeps instead of eight to ten.
+
+// Column j and row i of packed index idx (column-major lower triangle).
+__device__ __forceinline__ void psd_unpack_index(int k, int idx, int& i, int& j) {
+    const double b = 2.0 * k + 1.0;
+    j = (int)((b - sqrt(b * b - 8.0 * idx)) * 0.5);
+    if (j < 0) j = 0;
+    if (j > k - 1) j = k - 1;
+    while (j > 0 && j * k - j * (j - 1) / 2 > idx) --j;               // off(j) = j k - j (j - 1) / 2
+    while (j + 1 < k && (j + 1) * k - (j + 1) * j / 2 <= idx) ++j;
+    i = j + (idx - (j * k - j * (j - 1) / 2));
+}
+
+// C = A B or C = A^T B for k x k row-major matrices, by the whole workgroup.
+// A thread computes rows i0 .. i0+3 of one column j: consecutive threads take
+// consecutive columns, so B and C coalesce, A is a broadcast, and each B load
+// feeds four products.
+template <bool TA>
+__device__ __forceinline__ void psd_gemm(int k, const double* __restrict__ A, const double* __restrict__ B,
+                                         double* __restrict__ C) {
+    const int rb = (k + 3) / 4;
+    for (int idx = threadIdx.x; idx < rb * k; idx += blockDim.x) {
+        const int i0 = (idx / k) * 4, j = idx - (idx / k) * k;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        const int i1 = min(i0 + 1, k - 1), i2 = min(i0 + 2, k - 1), i3 = min(i0 + 3, k - 1);
+        for (int e = 0; e < k; ++e) {
+            const double b = B[e * k + j];
+            s0 += (TA ? A[e * k + i0] : A[i0 * k + e]) * b;
+            s1 += (TA ? A[e * k + i1] : A[i1 * k + e]) * b;
+            s2 += (TA ? A[e * k + i2] : A[i2 * k + e]) * b;
+            s3 += (TA ? A[e * k + i3] : A[i3 * k + e]) * b;
+        }
+        C[i0 * k + j] = s0;
+        if (i0 + 1 < k) C[(i0 + 1) * k + j] = s1;
+        if (i0 + 2 < k) C[(i0 + 2) * k + j] = s2;
+        if (i0 + 3 < k) C[(i0 + 3) * k + j] = s3;
+    }
+}
+
 template <typename Team>
-__device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, double* vm, const double* in, double* outv) {
+__device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, double* vm, double* in, double* outv,
+                                               double* V0, int* warm) {
     const int t = threadIdx.x, nt = blockDim.x;
     const double rs2 = 0.70710678118654752440;
     // unpack: column-major lower triangle, off-diagonals scaled by sqrt(2)
     for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
-        // column j holds k - j entries starting at off(j) = j k - j (j - 1) / 2
-        int j = 0, off = 0;
-        while (off + (k - j) <= idx) { off += k - j; ++j; }
-        const int i = j + (idx - off);
+        int i, j;
+        psd_unpack_index(k, idx, i, j);
         const double v = in[idx];
         if (i == j) a[i * k + i] = v;
         else { a[i * k + j] = v * rs2; a[j * k + i] = v * rs2; }
     }
-    for (int idx = t; idx < k * k; idx += nt) vm[idx] = ((idx / k) == (idx % k)) ? 1.0 : 0.0;
+    __syncthreads();
+    const bool use_warm = V0 != nullptr && *warm != 0;
+    if (use_warm) {
+        psd_gemm<false>(k, a, V0, vm);                 // vm = mat(x) V0
+        __syncthreads();
+        psd_gemm<true>(k, V0, vm, a);                  // a = V0^T mat(x) V0
+        __syncthreads();
+        for (int idx = t; idx < k * k; idx += nt) {     // symmetrise (rounding) and start from V0
+            const int i = idx / k, j = idx - (idx / k) * k;
+            if (i < j) {
+                const double v = 0.5 * (a[i * k + j] + a[j * k + i]);
+                a[i * k + j] = v;
+                a[j * k + i] = v;
+            }
+            vm[idx] = V0[idx];
+        }
+    } else {
+        for (int idx = t; idx < k * k; idx += nt) vm[idx] = ((idx / k) == (idx % k)) ? 1.0 : 0.0;
+    }
     __syncthreads();
     if (k > 1) {
         const int kk = (k & 1) ? k + 1 : k;   // pad to even with a dummy index
         __shared__ double cs[512], sn[512];
         __shared__ int pp[512], qq[512];
         __shared__ double offn;
+        // stop once the off-diagonal part is at the rounding level of a k x k
+        // matrix, or when a sweep no longer gains the quadratic factor
+        const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
+        double prev = 1.0;
         for (int sweep = 0; sweep < 30; ++sweep) {
-            // off-diagonal Frobenius norm relative to the whole matrix
+            // squared off-diagonal Frobenius norm relative to the whole matrix
             {
                 __shared__ double red2[2 * NWMAX];
                 double off = 0.0, tot = 0.0;
@@ -198,7 +266,9 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
                 }
                 __syncthreads();
             }
-            if (offn <= 1e-30) break;
+            const double cur = offn;
+            if (cur <= tol2 || (sweep >= 2 && cur > 0.25 * prev)) break;
+            prev = cur;
             for (int round = 0; round < kk - 1; ++round) {
                 // round-robin pairing: position 0 fixed, others rotate
                 for (int h = t; h < kk / 2; h += nt) {
@@ -208,7 +278,8 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
                     double c = 1.0, s = 0.0;
                     if (q < k) {
                         const double apq = a[p * k + q];
-                        if (apq != 0.0) {
+                        // a rotation smaller than the rounding of the diagonal changes nothing
+                        if (fabs(apq) > 2.2e-16 * sqrt(fabs(a[p * k + p] * a[q * k + q])) && apq != 0.0) {
                             const double app = a[p * k + p], aqq = a[q * k + q];
                             const double tau = (aqq - app) / (2.0 * apq);
                             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -219,45 +290,94 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
                     pp[h] = p; qq[h] = q; cs[h] = c; sn[h] = s;
                 }
                 __syncthreads();
-                // A <- J^T A: rows p, q
-                for (int idx = t; idx < (kk / 2) * k; idx += nt) {
-                    const int h = idx / k, j = idx % k;
-                    const int p = pp[h], q = qq[h];
-                    if (q >= k) continue;
-                    const double c = cs[h], s = sn[h];
-                    const double ap = a[p * k + j], aq = a[q * k + j];
-                    a[p * k + j] = c * ap - s * aq;
-                    a[q * k + j] = s * ap + c * aq;
+                // A <- J^T A: rows p, q.  Four elements per thread per step, all
+                // loads before the stores (independent addresses); skipped pairs
+                // (no rotation) cost nothing.
+                const int tot = (kk / 2) * k;
+                for (int b0 = t; b0 < tot; b0 += 4 * nt) {
+                    double ap[4], aq[4];
+                    int ip[4], iq[4];
+                    double cc[4], ss[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int idx = b0 + u * nt;
+                        ip[u] = -1;
+                        if (idx < tot) {
+                            const int h = idx / k, j = idx - (idx / k) * k;
+                            const int p = pp[h], q = qq[h];
+                            if (q < k && sn[h] != 0.0) {
+                                ip[u] = p * k + j;
+                                iq[u] = q * k + j;
+                                cc[u] = cs[h];
+                                ss[u] = sn[h];
+                            }
+                        }
+                        if (ip[u] >= 0) { ap[u] = a[ip[u]]; aq[u] = a[iq[u]]; }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (ip[u] < 0) continue;
+                        a[ip[u]] = cc[u] * ap[u] - ss[u] * aq[u];
+                        a[iq[u]] = ss[u] * ap[u] + cc[u] * aq[u];
+                    }
                 }
                 __syncthreads();
-                // A <- A J and V <- V J: columns p, q
-                for (int idx = t; idx < (kk / 2) * k; idx += nt) {
-                    const int h = idx / k, i = idx % k;
-                    const int p = pp[h], q = qq[h];
-                    if (q >= k) continue;
-                    const double c = cs[h], s = sn[h];
-                    const double ap = a[i * k + p], aq = a[i * k + q];
-                    a[i * k + p] = c * ap - s * aq;
-                    a[i * k + q] = s * ap + c * aq;
-                    const double vp = vm[i * k + p], vq = vm[i * k + q];
-                    vm[i * k + p] = c * vp - s * vq;
-                    vm[i * k + q] = s * vp + c * vq;
+                // A <- A J and V <- V J: columns p, q (same scheme)
+                for (int b0 = t; b0 < tot; b0 += 4 * nt) {
+                    double ap[4], aq[4], vp[4], vq[4];
+                    int ip[4], iq[4];
+                    double cc[4], ss[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int idx = b0 + u * nt;
+                        ip[u] = -1;
+                        if (idx < tot) {
+                            const int h = idx / k, i = idx - (idx / k) * k;
+                            const int p = pp[h], q = qq[h];
+                            if (q < k && sn[h] != 0.0) {
+                                ip[u] = i * k + p;
+                                iq[u] = i * k + q;
+                                cc[u] = cs[h];
+                                ss[u] = sn[h];
+                            }
+                        }
+                        if (ip[u] >= 0) {
+                            ap[u] = a[ip[u]]; aq[u] = a[iq[u]];
+                            vp[u] = vm[ip[u]]; vq[u] = vm[iq[u]];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (ip[u] < 0) continue;
+                        a[ip[u]] = cc[u] * ap[u] - ss[u] * aq[u];
+                        a[iq[u]] = ss[u] * ap[u] + cc[u] * aq[u];
+                        vm[ip[u]] = cc[u] * vp[u] - ss[u] * vq[u];
+                        vm[iq[u]] = ss[u] * vp[u] + cc[u] * vq[u];
+                    }
                 }
                 __syncthreads();
             }
         }
     }
-    // reconstruct V max(lam, 0) V^T in packed form
+    // reconstruct V max(lam, 0) V^T in packed form: lam into `in` (consumed),
+    // W^T = (V diag(lam+))^T into `a`, then entry (i, j) = sum_e W^T[e][i] V[j][e]
+    for (int e = t; e < k; e += nt) in[e] = fmax(a[e * k + e], 0.0);
+    __syncthreads();
+    for (int idx = t; idx < k * k; idx += nt) {
+        const int e = idx / k, i = idx - (idx / k) * k;
+        a[idx] = vm[i * k + e] * in[e];
+    }
+    __syncthreads();
     for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
-        int j = 0, off = 0;
-        while (off + (k - j) <= idx) { off += k - j; ++j; }
-        const int i = j + (idx - off);
+        int i, j;
+        psd_unpack_index(k, idx, i, j);
         double s = 0.0;
-        for (int e = 0; e < k; ++e) {
-            const double lam = a[e * k + e];
-            if (lam > 0.0) s += vm[i * k + e] * lam * vm[j * k + e];
-        }
+        for (int e = 0; e < k; ++e) s += a[e * k + i] * vm[j * k + e];
         outv[idx] = (i == j) ? s : s * 1.41421356237309504880;
+    }
+    if (V0 != nullptr) {
+        for (int idx = t; idx < k * k; idx += nt) V0[idx] = vm[idx];
+        if (t == 0) *warm = 1;
     }
     __syncthreads();
 }
@@ -318,7 +438,9 @@ __device__ __forceinline__ void project_C(Team& tm, int n, int N, const ConeDev&
             const int len = k * (k + 1) / 2;
             for (int e = threadIdx.x; e < len; e += blockDim.x) pin[e] = in(o + e);
             __syncthreads();
-            psd_project_block(tm, k, a, vm, pin, pout);
+            psd_project_block(tm, k, a, vm, pin, pout,
+                              K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
+                              K.psd_warm ? K.psd_warm + c : nullptr);
             for (int e = threadIdx.x; e < len; e += blockDim.x) emit(o + e, pout[e]);
             __syncthreads();
         }

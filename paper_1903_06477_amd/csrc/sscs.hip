@@ -521,6 +521,8 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
     I.K.soc0 = h.soc0; I.K.psd0 = h.psd0; I.K.exp0 = h.exp0;
     I.K.psd_scratch = nullptr;
     I.K.psd_kmax = h.kmax;
+    I.K.psd_vecs = nullptr;
+    I.K.psd_warm = nullptr;
     return SSCS_OK;
 }
 
@@ -533,6 +535,8 @@ void free_instance(Inst& I) {
     hipFree(I.b); hipFree(I.c); hipFree(I.g);
     hipFree(I.qoff); hipFree(I.sord); hipFree(I.soff);
     hipFree(I.K.psd_scratch);
+    hipFree(I.K.psd_vecs);
+    hipFree(I.K.psd_warm);
     hipFree(I.partA); hipFree(I.partAt);
     I = Inst{};
 }
@@ -718,7 +722,15 @@ int set_partitions(sscs_work* w, bool try_lds) {
     HIP_TRY(hipGetDevice(&dev));
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const long long limit = (long long)lds_max - (long long)sizeof(Shared) - 1024;
+    // dynamic LDS left next to the kernels' static LDS (Shared, descriptors,
+    // the PSD rotation tables)
+    long long stat = 0;
+    for (const void* f : {solve_grid_fn(true, I.mixed), op_grid_fn(true, I.mixed)}) {
+        hipFuncAttributes fa{};
+        HIP_TRY(hipFuncGetAttributes(&fa, f));
+        stat = std::max<long long>(stat, (long long)fa.sharedSizeBytes);
+    }
+    const long long limit = (long long)lds_max - stat - 256;
     std::vector<int> pA, pAt;
     long long need = 0;
     const int vb = I.mixed ? 4 : 8;       // bytes per cached value
@@ -764,6 +776,9 @@ int alloc_work_vectors(sscs_work* w) {
         const size_t per = 2 * k * k + k * (k + 1);
         const size_t nblk = std::min<size_t>(w->grid, w->I.K.ns);
         TRY(dmalloc(&w->I.K.psd_scratch, per * nblk));
+        TRY(dmalloc(&w->I.K.psd_vecs, k * k * (size_t)w->I.K.ns));
+        TRY(dmalloc(&w->I.K.psd_warm, (size_t)w->I.K.ns));
+        HIP_TRY(hipMemsetAsync(w->I.K.psd_warm, 0, w->I.K.ns * sizeof(int), w->stream));
     }
     return SSCS_OK;
 }
@@ -908,6 +923,8 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
     V.tr_res = w->tr_res; V.tr_kind = w->tr_kind; V.tr_ls = w->tr_ls; V.tr_cap = w->tr_cap;
     Prob P = make_prob(w->I);
     Params S = make_params(w->st, w->ticks_per_s);
+    // every solve starts its PSD projections cold (same input, same bits)
+    if (w->I.K.psd_warm) HIP_TRY(hipMemsetAsync(w->I.K.psd_warm, 0, w->I.K.ns * sizeof(int), w->stream));
     if (w->grid == 1) {
         HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
         const int sd = stage_doubles(w->I.n + w->I.m);

@@ -1,0 +1,67 @@
+"""GPU parity on the mixed PSD / exponential-cone instance (sparse PCA blocks
+of orders 4, 4, 7 plus a 30-sample l1 logistic regression): status, pr, dr,
+gap <= eps recomputed on the CPU in FP64 from the returned (x, y, s), the
+returned y in K* and s in K to 1e-6, and the objective within 1e-5 relative
+of the oracle's, in FP64 and mixed precision, on the grid kernel and on the
+one-workgroup kernel."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1903_06477_amd import generators as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sscs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_06477_amd import sscs as S
+    S.lib()
+    return S
+
+
+@pytest.fixture(scope="module")
+def reference():
+    from oracle import superscs as S
+    out = {}
+    for seed in (0, 1):
+        p = G.small_sdp_exp(seed)
+        out[seed] = (p, S.solve(p, S.Settings(direction="aa", mem=5, max_iters=20000)))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("grid", ["auto", "1"])
+def test_sdp_exp_end_to_end(sscs, reference, seed, precision, grid):
+    from oracle.cones import proj_dual_cone
+    prob, ref = reference[seed]
+    assert ref.status == 1
+    old = os.environ.get("SSCS_GRID")
+    try:
+        if grid == "1":
+            os.environ["SSCS_GRID"] = "1"
+        else:
+            os.environ.pop("SSCS_GRID", None)
+        print(f"sdp/exp seed {seed} {precision} grid={grid}", flush=True)
+        with sscs.Solver(prob, sscs.Settings(direction="aa", mem=5, cg_tol=1e-12, cg_max=5000,
+                                             max_iters=20000, precision=precision)) as s:
+            x, y, sv, info = s.solve()
+    finally:
+        if old is None:
+            os.environ.pop("SSCS_GRID", None)
+        else:
+            os.environ["SSCS_GRID"] = old
+    assert info["status"] == sscs.SOLVED
+    nb, nc = np.linalg.norm(prob.b), np.linalg.norm(prob.c)
+    pr = np.linalg.norm(prob.A @ x + sv - prob.b) / (1 + nb)
+    dr = np.linalg.norm(prob.A.T @ y + prob.c) / (1 + nc)
+    cx, by = prob.c @ x, prob.b @ y
+    gap = abs(cx + by) / (1 + abs(cx) + abs(by))
+    assert max(pr, dr, gap) <= 1e-6 * 1.0001
+    assert np.linalg.norm(y - proj_dual_cone(y, prob.cone)) <= 1e-6 * (1 + np.linalg.norm(y))
+    assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))

@@ -205,12 +205,17 @@ struct GridTeam {
 
 // CSR matrix on the device.  `seg` is the number of lanes that cooperate on one
 // row (a power of two <= 64), chosen on the host from the mean row length.
+// Rows longer than `lthr` nonzeros (ascending list `lrows`, `nlong` of them)
+// are summed by a whole workgroup in the team products instead, so one long
+// row (a variable shared by every cone, say) does not serialise a segment.
 template <typename T>
 struct Csr {
     const int* rp;
     const int* ci;
     const T* v;
     int rows, cols, seg;
+    const int* lrows;
+    int nlong, lthr;
 };
 
 // Row-segmented SpMV over the team: for every row r, f(r, sum_k v[k] gx(ci[k]))
@@ -282,17 +287,22 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
     for (int l0 = seg; l0 < mp.rows; l0 += ROWS * nseg) {
         int kb[ROWS], ke[ROWS];
         double acc[ROWS];
+        bool own[ROWS];
 #pragma unroll
         for (int q = 0; q < ROWS; ++q) {
             const int l = l0 + q * nseg;
             const bool in = l < mp.rows;
+            int b = 0, e = 0;
             if (LDS) {
-                kb[q] = in ? lrp[l] + ls : 0;
-                ke[q] = in ? lrp[l + 1] : 0;
+                b = in ? lrp[l] : 0;
+                e = in ? lrp[l + 1] : 0;
             } else {
-                kb[q] = in ? M.rp[mp.r0 + l] + ls : 0;
-                ke[q] = in ? M.rp[mp.r0 + l + 1] : 0;
+                b = in ? M.rp[mp.r0 + l] : 0;
+                e = in ? M.rp[mp.r0 + l + 1] : 0;
             }
+            own[q] = in && (e - b) <= M.lthr;          // long rows are summed below
+            kb[q] = own[q] ? b + ls : 0;
+            ke[q] = own[q] ? e : 0;
             acc[q] = 0.0;
         }
         bool more = true;
@@ -314,7 +324,36 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
             double a = acc[q];
             for (int off = S >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, WAVE);
             const int l = l0 + q * nseg;
-            if (ls == 0 && l < mp.rows) f(mp.r0 + l, a);
+            if (ls == 0 && own[q]) f(mp.r0 + l, a);
+        }
+    }
+    if (M.nlong > 0) {
+        // long rows of this part: the whole workgroup per row, summed in a
+        // fixed order (lanes, then waves); the first thread reports the row
+        __shared__ double lred[NWMAX];
+        int lo = 0, hi = M.nlong;
+        while (lo < hi) {                              // first long row >= mp.r0
+            const int mid = (lo + hi) >> 1;
+            if (M.lrows[mid] < mp.r0) lo = mid + 1; else hi = mid;
+        }
+        for (int li = lo; li < M.nlong && M.lrows[li] < mp.r0 + mp.rows; ++li) {
+            const int r = M.lrows[li], l = r - mp.r0;
+            const int b = LDS ? lrp[l] : M.rp[r], e = LDS ? lrp[l + 1] : M.rp[r + 1];
+            double a = 0.0;
+            for (int kk = b + (int)threadIdx.x; kk < e; kk += blockDim.x) {
+                const double v = LDS ? (double)lv[kk] : (double)M.v[kk];
+                const int c = LDS ? lci[kk] : M.ci[kk];
+                a += v * (double)gx(c);
+            }
+            a = wave_sum(a);
+            if ((threadIdx.x & (WAVE - 1)) == 0) lred[threadIdx.x / WAVE] = a;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) t += lred[w];
+                f(r, t);
+            }
+            __syncthreads();
         }
     }
 }

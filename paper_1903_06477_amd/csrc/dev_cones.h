@@ -25,7 +25,7 @@ struct ConeDev {
     const int* soff;
     int ep;                   // exponential cones
     int soc0, psd0, exp0;     // first row of each region (relative to the start of y)
-    double* psd_scratch;      // per-workgroup scratch for PSD blocks (2 k^2 + k (k + 1) doubles each)
+    double* psd_scratch;      // per-workgroup scratch for PSD blocks (psd_scratch_doubles(kmax) each)
     int psd_kmax;
     double* psd_vecs;         // per block: the eigenvectors of its last projection (kmax^2
                               // doubles each), or null: every projection starts cold
@@ -155,16 +155,26 @@ __device__ inline void proj_exp_dual(const double* v, double* out) {
 //
 // Pi of a PSD block: mat(x) = V diag(lam) V^T, keep max(lam, 0), back to the
 // packed layout (Sec. II).  The eigendecomposition is a cyclic two-sided
-// Jacobi method run by one workgroup on the k x k matrix held in `a` (global
-// scratch private to the workgroup) with the eigenvector matrix in `vm`: each
-// sweep visits every pair (p, q) once in round-robin order, k/2 disjoint
-// rotations per round in parallel.
+// Jacobi method run by one workgroup on the k x k matrix (global scratch
+// private to the workgroup): each sweep visits every pair (p, q) once in
+// round-robin order, k/2 disjoint rotations J per round in parallel.
+//
+// A round writes C = J^T A J to a second buffer in one pass over the 2 x 2
+// blocks the disjoint rotations cut A into, so a round costs one barrier; the
+// eigenvectors are kept as the rows of Vt = V^T (Vt <- J^T Vt), which makes
+// their updates and the reconstruction walk rows.
 //
 // Warm start: the iterates the method projects change little from one call to
-// the next, so a block keeps the eigenvectors V0 of its previous projection.
-// Jacobi then runs on B = V0^T mat(x) V0 (similar to mat(x), nearly diagonal)
-// with the rotations accumulated onto V0, which typically leaves one or two
-// sweeps instead of eight to ten.
+// the next, so a block keeps the eigenvectors of its previous projection
+// (Vt0).  Jacobi then starts from B = Vt0 mat(x) Vt0^T (similar to mat(x),
+// nearly diagonal) with Vt = Vt0, which leaves one to three sweeps instead
+// of eight to ten.
+
+// Scratch of one workgroup for blocks of order <= kmax: a, vm, tmp (k x k
+// each), the packed input and output.
+__host__ __device__ inline size_t psd_scratch_doubles(int kmax) {
+    return 3 * (size_t)kmax * kmax + (size_t)kmax * (kmax + 1);
+}
 
 // Column j and row i of packed index idx (column-major lower triangle).
 __device__ __forceinline__ void psd_unpack_index(int k, int idx, int& i, int& j) {
@@ -177,11 +187,10 @@ __device__ __forceinline__ void psd_unpack_index(int k, int idx, int& i, int& j)
     i = j + (idx - (j * k - j * (j - 1) / 2));
 }
 
-// C = A B or C = A^T B for k x k row-major matrices, by the whole workgroup.
-// A thread computes rows i0 .. i0+3 of one column j: consecutive threads take
+// C = A B for k x k row-major matrices, by the whole workgroup.  A thread
+// computes rows i0 .. i0+3 of one column j: consecutive threads take
 // consecutive columns, so B and C coalesce, A is a broadcast, and each B load
 // feeds four products.
-template <bool TA>
 __device__ __forceinline__ void psd_gemm(int k, const double* __restrict__ A, const double* __restrict__ B,
                                          double* __restrict__ C) {
     const int rb = (k + 3) / 4;
@@ -191,10 +200,10 @@ __device__ __forceinline__ void psd_gemm(int k, const double* __restrict__ A, co
         const int i1 = min(i0 + 1, k - 1), i2 = min(i0 + 2, k - 1), i3 = min(i0 + 3, k - 1);
         for (int e = 0; e < k; ++e) {
             const double b = B[e * k + j];
-            s0 += (TA ? A[e * k + i0] : A[i0 * k + e]) * b;
-            s1 += (TA ? A[e * k + i1] : A[i1 * k + e]) * b;
-            s2 += (TA ? A[e * k + i2] : A[i2 * k + e]) * b;
-            s3 += (TA ? A[e * k + i3] : A[i3 * k + e]) * b;
+            s0 += A[i0 * k + e] * b;
+            s1 += A[i1 * k + e] * b;
+            s2 += A[i2 * k + e] * b;
+            s3 += A[i3 * k + e] * b;
         }
         C[i0 * k + j] = s0;
         if (i0 + 1 < k) C[(i0 + 1) * k + j] = s1;
@@ -203,12 +212,103 @@ __device__ __forceinline__ void psd_gemm(int k, const double* __restrict__ A, co
     }
 }
 
+// dst = src^T (k x k) by the workgroup (consecutive threads write
+// consecutive entries of dst); ends with a barrier.
+__device__ __forceinline__ void psd_transpose(int k, const double* __restrict__ src, double* __restrict__ dst) {
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int i = idx / k, j = idx - (idx / k) * k;
+        dst[idx] = src[j * k + i];
+    }
+    __syncthreads();
+}
+
+// Rotation tables of one Jacobi round (LDS, shared by both PSD routines).
+struct PsdRound {
+    double cs[512], sn[512];
+    int pp[512], qq[512];
+    double offn;
+    int nact;
+};
+
+__device__ __forceinline__ PsdRound& psd_round_lds() {
+    __shared__ PsdRound r;
+    return r;
+}
+
+// Pairs of round `round` of the round-robin ordering over kk (even) indices:
+// position 0 stays, the others rotate; pair h is (pp[h], qq[h]) with p < q.
+// Fills rotation (cs, sn) from `mat` for pairs with q < k; counts active ones.
+// Called by the threads of one workgroup; ends with a workgroup barrier.
+__device__ __forceinline__ void psd_round_params(int k, int kk, int round, const double* mat, PsdRound& R) {
+    if (threadIdx.x == 0) R.nact = 0;
+    __syncthreads();
+    int act = 0;
+    for (int h = threadIdx.x; h < kk / 2; h += blockDim.x) {
+        const int x = (h == 0) ? 0 : 1 + ((h - 1 + round) % (kk - 1));
+        const int y = 1 + ((kk - 2 - h + round) % (kk - 1));
+        const int p = x < y ? x : y, q = x < y ? y : x;
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+            const double apq = mat[p * k + q];
+            // a rotation smaller than the rounding of the diagonal changes nothing
+            if (apq != 0.0 && fabs(apq) > 2.2e-16 * sqrt(fabs(mat[p * k + p] * mat[q * k + q]))) {
+                const double app = mat[p * k + p], aqq = mat[q * k + q];
+                const double tau = (aqq - app) / (2.0 * apq);
+                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                c = 1.0 / sqrt(1.0 + tt * tt);
+                s = tt * c;
+                act = 1;
+            }
+        }
+        R.pp[h] = p; R.qq[h] = q; R.cs[h] = c; R.sn[h] = s;
+    }
+    if (act) atomicAdd(&R.nact, 1);
+    __syncthreads();
+}
+
+// One Jacobi round as C = J^T A J written to dst (dst != src): the rotations
+// are disjoint 2 x 2 blocks, so entry block (p1, q1) x (p2, q2) of C depends
+// only on the same block of A and on the two rotations; thread `r` of `nr`
+// takes blocks r, r + nr, ...  Rows p, q of Vt turn with J^T in place.
+__device__ __forceinline__ void psd_round_apply(int k, int np, const PsdRound& R, const double* __restrict__ src,
+                                                double* __restrict__ dst, double* __restrict__ vt, int r, int nr) {
+    for (int idx = r; idx < np * np; idx += nr) {
+        const int h1 = idx / np, h2 = idx - (idx / np) * np;
+        const int p1 = R.pp[h1], q1 = R.qq[h1], p2 = R.pp[h2], q2 = R.qq[h2];
+        const bool e1 = q1 < k, e2 = q2 < k;          // the dummy index has no row / column
+        const double c1 = R.cs[h1], s1 = R.sn[h1], c2 = R.cs[h2], s2 = R.sn[h2];
+        const double app = src[p1 * k + p2];
+        const double apq = e2 ? src[p1 * k + q2] : 0.0;
+        const double aqp = e1 ? src[q1 * k + p2] : 0.0;
+        const double aqq = (e1 && e2) ? src[q1 * k + q2] : 0.0;
+        // B = J^T A (rows), then C = B J (columns)
+        const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
+        const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
+        dst[p1 * k + p2] = c2 * bpp - s2 * bpq;
+        if (e2) dst[p1 * k + q2] = s2 * bpp + c2 * bpq;
+        if (e1) dst[q1 * k + p2] = c2 * bqp - s2 * bqq;
+        if (e1 && e2) dst[q1 * k + q2] = s2 * bqp + c2 * bqq;
+    }
+    for (int idx = r; idx < np * k; idx += nr) {
+        const int h = idx / k, j = idx - (idx / k) * k;
+        const int p = R.pp[h], q = R.qq[h];
+        if (q >= k || R.sn[h] == 0.0) continue;
+        const double c = R.cs[h], s_ = R.sn[h];
+        const double vp = vt[p * k + j], vq = vt[q * k + j];
+        vt[p * k + j] = c * vp - s_ * vq;
+        vt[q * k + j] = s_ * vp + c * vq;
+    }
+}
+
+// `a`, `vm` and `tmp` hold k*k doubles each, `in` and `outv` the packed
+// block (in is consumed); V0 (k*k, rows are eigenvectors) and *warm persist
+// between calls, or V0 is null.
 template <typename Team>
-__device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, double* vm, double* in, double* outv,
-                                               double* V0, int* warm) {
+__device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, double* vm, double* tmp, double* in,
+                                               double* outv, double* V0, int* warm) {
     const int t = threadIdx.x, nt = blockDim.x;
     const double rs2 = 0.70710678118654752440;
-    // unpack: column-major lower triangle, off-diagonals scaled by sqrt(2)
+    // unpack into a: column-major lower triangle, off-diagonals scaled by sqrt(2)
     for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
         int i, j;
         psd_unpack_index(k, idx, i, j);
@@ -217,18 +317,20 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
         else { a[i * k + j] = v * rs2; a[j * k + i] = v * rs2; }
     }
     __syncthreads();
+    double* mat = a;        // the matrix being diagonalised; tmp is the transpose buffer
     const bool use_warm = V0 != nullptr && *warm != 0;
     if (use_warm) {
-        psd_gemm<false>(k, a, V0, vm);                 // vm = mat(x) V0
+        psd_gemm(k, V0, a, tmp);                       // tmp = Vt0 A
         __syncthreads();
-        psd_gemm<true>(k, V0, vm, a);                  // a = V0^T mat(x) V0
+        psd_transpose(k, tmp, vm);                     // vm = A Vt0^T (A symmetric)
+        psd_gemm(k, V0, vm, a);                        // a = Vt0 A Vt0^T
         __syncthreads();
-        for (int idx = t; idx < k * k; idx += nt) {     // symmetrise (rounding) and start from V0
+        for (int idx = t; idx < k * k; idx += nt) {     // symmetrise (rounding) and start from Vt0
             const int i = idx / k, j = idx - (idx / k) * k;
             if (i < j) {
-                const double v = 0.5 * (a[i * k + j] + a[j * k + i]);
-                a[i * k + j] = v;
-                a[j * k + i] = v;
+                const double v = 0.5 * (mat[i * k + j] + mat[j * k + i]);
+                mat[i * k + j] = v;
+                mat[j * k + i] = v;
             }
             vm[idx] = V0[idx];
         }
@@ -238,9 +340,7 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
     __syncthreads();
     if (k > 1) {
         const int kk = (k & 1) ? k + 1 : k;   // pad to even with a dummy index
-        __shared__ double cs[512], sn[512];
-        __shared__ int pp[512], qq[512];
-        __shared__ double offn;
+        PsdRound& R = psd_round_lds();
         // stop once the off-diagonal part is at the rounding level of a k x k
         // matrix, or when a sweep no longer gains the quadratic factor
         const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
@@ -251,7 +351,7 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
                 __shared__ double red2[2 * NWMAX];
                 double off = 0.0, tot = 0.0;
                 for (int idx = t; idx < k * k; idx += nt) {
-                    const double v = a[idx] * a[idx];
+                    const double v = mat[idx] * mat[idx];
                     tot += v;
                     if ((idx / k) != (idx % k)) off += v;
                 }
@@ -262,117 +362,36 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
                 if (t == 0) {
                     double so = 0.0, st = 0.0;
                     for (int w = 0; w < nt / WAVE; ++w) { so += red2[w]; st += red2[NWMAX + w]; }
-                    offn = (st > 0.0) ? so / st : 0.0;
+                    R.offn = (st > 0.0) ? so / st : 0.0;
                 }
                 __syncthreads();
             }
-            const double cur = offn;
+            const double cur = R.offn;
             if (cur <= tol2 || (sweep >= 2 && cur > 0.25 * prev)) break;
             prev = cur;
             for (int round = 0; round < kk - 1; ++round) {
-                // round-robin pairing: position 0 fixed, others rotate
-                for (int h = t; h < kk / 2; h += nt) {
-                    int x = (h == 0) ? 0 : 1 + ((h - 1 + round) % (kk - 1));
-                    int y = 1 + ((kk - 2 - h + round) % (kk - 1));
-                    int p = x < y ? x : y, q = x < y ? y : x;
-                    double c = 1.0, s = 0.0;
-                    if (q < k) {
-                        const double apq = a[p * k + q];
-                        // a rotation smaller than the rounding of the diagonal changes nothing
-                        if (fabs(apq) > 2.2e-16 * sqrt(fabs(a[p * k + p] * a[q * k + q])) && apq != 0.0) {
-                            const double app = a[p * k + p], aqq = a[q * k + q];
-                            const double tau = (aqq - app) / (2.0 * apq);
-                            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                            c = 1.0 / sqrt(1.0 + tt * tt);
-                            s = tt * c;
-                        }
-                    }
-                    pp[h] = p; qq[h] = q; cs[h] = c; sn[h] = s;
-                }
+                psd_round_params(k, kk, round, mat, R);
+                if (R.nact == 0) continue;                  // uniform: nothing to rotate this round
+                psd_round_apply(k, kk / 2, R, mat, tmp, vm, t, nt);
                 __syncthreads();
-                // A <- J^T A: rows p, q.  Four elements per thread per step, all
-                // loads before the stores (independent addresses); skipped pairs
-                // (no rotation) cost nothing.
-                const int tot = (kk / 2) * k;
-                for (int b0 = t; b0 < tot; b0 += 4 * nt) {
-                    double ap[4], aq[4];
-                    int ip[4], iq[4];
-                    double cc[4], ss[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int idx = b0 + u * nt;
-                        ip[u] = -1;
-                        if (idx < tot) {
-                            const int h = idx / k, j = idx - (idx / k) * k;
-                            const int p = pp[h], q = qq[h];
-                            if (q < k && sn[h] != 0.0) {
-                                ip[u] = p * k + j;
-                                iq[u] = q * k + j;
-                                cc[u] = cs[h];
-                                ss[u] = sn[h];
-                            }
-                        }
-                        if (ip[u] >= 0) { ap[u] = a[ip[u]]; aq[u] = a[iq[u]]; }
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (ip[u] < 0) continue;
-                        a[ip[u]] = cc[u] * ap[u] - ss[u] * aq[u];
-                        a[iq[u]] = ss[u] * ap[u] + cc[u] * aq[u];
-                    }
-                }
-                __syncthreads();
-                // A <- A J and V <- V J: columns p, q (same scheme)
-                for (int b0 = t; b0 < tot; b0 += 4 * nt) {
-                    double ap[4], aq[4], vp[4], vq[4];
-                    int ip[4], iq[4];
-                    double cc[4], ss[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int idx = b0 + u * nt;
-                        ip[u] = -1;
-                        if (idx < tot) {
-                            const int h = idx / k, i = idx - (idx / k) * k;
-                            const int p = pp[h], q = qq[h];
-                            if (q < k && sn[h] != 0.0) {
-                                ip[u] = i * k + p;
-                                iq[u] = i * k + q;
-                                cc[u] = cs[h];
-                                ss[u] = sn[h];
-                            }
-                        }
-                        if (ip[u] >= 0) {
-                            ap[u] = a[ip[u]]; aq[u] = a[iq[u]];
-                            vp[u] = vm[ip[u]]; vq[u] = vm[iq[u]];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (ip[u] < 0) continue;
-                        a[ip[u]] = cc[u] * ap[u] - ss[u] * aq[u];
-                        a[iq[u]] = ss[u] * ap[u] + cc[u] * aq[u];
-                        vm[ip[u]] = cc[u] * vp[u] - ss[u] * vq[u];
-                        vm[iq[u]] = ss[u] * vp[u] + cc[u] * vq[u];
-                    }
-                }
-                __syncthreads();
+                double* sw = mat;
+                mat = tmp;
+                tmp = sw;
             }
         }
     }
-    // reconstruct V max(lam, 0) V^T in packed form: lam into `in` (consumed),
-    // W^T = (V diag(lam+))^T into `a`, then entry (i, j) = sum_e W^T[e][i] V[j][e]
-    for (int e = t; e < k; e += nt) in[e] = fmax(a[e * k + e], 0.0);
+    // reconstruct V max(lam, 0) V^T in packed form with Vt = V^T: lam into
+    // `in` (consumed), Wt = diag(lam+) Vt into tmp, entry (i, j) =
+    // sum_e Wt[e][i] Vt[e][j] (Wt coalesced, Vt a broadcast)
+    for (int e = t; e < k; e += nt) in[e] = fmax(mat[e * k + e], 0.0);
     __syncthreads();
-    for (int idx = t; idx < k * k; idx += nt) {
-        const int e = idx / k, i = idx - (idx / k) * k;
-        a[idx] = vm[i * k + e] * in[e];
-    }
+    for (int idx = t; idx < k * k; idx += nt) tmp[idx] = vm[idx] * in[idx / k];
     __syncthreads();
     for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
         int i, j;
         psd_unpack_index(k, idx, i, j);
         double s = 0.0;
-        for (int e = 0; e < k; ++e) s += a[e * k + i] * vm[j * k + e];
+        for (int e = 0; e < k; ++e) s += tmp[e * k + i] * vm[e * k + j];
         outv[idx] = (i == j) ? s : s * 1.41421356237309504880;
     }
     if (V0 != nullptr) {
@@ -382,11 +401,114 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
     __syncthreads();
 }
 
+// The same projection computed by a whole grid team, for blocks too large for
+// one workgroup to turn over quickly (the order-256 block of the sparse-PCA
+// instance).  Every pass is spread over all threads of the team; each
+// workgroup derives the round's rotations itself from the shared matrix, so a
+// round costs one team barrier.  Same arithmetic per entry as
+// psd_project_block.  `in` (packed input, filled by the caller) and the
+// buffers are global scratch visible to the whole team.
+template <typename Team>
+__device__ void psd_project_team(Team& tm, Shared& sh, int k, double* a, double* vm, double* tmp, double* in,
+                                 double* outv, double* V0, int* warm) {
+    const int r0 = tm.rank(), R_ = tm.size();
+    const double rs2 = 0.70710678118654752440;
+    for (int idx = r0; idx < k * (k + 1) / 2; idx += R_) {
+        int i, j;
+        psd_unpack_index(k, idx, i, j);
+        const double v = in[idx];
+        if (i == j) a[i * k + i] = v;
+        else { a[i * k + j] = v * rs2; a[j * k + i] = v * rs2; }
+    }
+    tm.sync();
+    double* mat = a;
+    const bool use_warm = V0 != nullptr && *warm != 0;
+    if (use_warm) {
+        for (int idx = r0; idx < k * k; idx += R_) {    // tmp = Vt0 A
+            const int i = idx / k, j = idx - (idx / k) * k;
+            double s_ = 0.0;
+            for (int e = 0; e < k; ++e) s_ += V0[i * k + e] * a[e * k + j];
+            tmp[idx] = s_;
+        }
+        tm.sync();
+        for (int idx = r0; idx < k * k; idx += R_) {    // a = (Vt0 A) Vt0^T
+            const int i = idx / k, j = idx - (idx / k) * k;
+            double s_ = 0.0;
+            for (int e = 0; e < k; ++e) s_ += tmp[i * k + e] * V0[j * k + e];
+            a[idx] = s_;
+        }
+        tm.sync();
+        for (int idx = r0; idx < k * k; idx += R_) {
+            const int i = idx / k, j = idx - (idx / k) * k;
+            if (i < j) {
+                const double v = 0.5 * (a[i * k + j] + a[j * k + i]);
+                a[i * k + j] = v;
+                a[j * k + i] = v;
+            }
+            vm[idx] = V0[idx];
+        }
+    } else {
+        for (int idx = r0; idx < k * k; idx += R_) vm[idx] = ((idx / k) == (idx % k)) ? 1.0 : 0.0;
+    }
+    tm.sync();
+    if (k > 1) {
+        const int kk = (k & 1) ? k + 1 : k;
+        PsdRound& R = psd_round_lds();
+        const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
+        double prev = 1.0;
+        for (int sweep = 0; sweep < 30; ++sweep) {
+            double off = 0.0, tot = 0.0;
+            for (int idx = r0; idx < k * k; idx += R_) {
+                const double v = mat[idx] * mat[idx];
+                tot += v;
+                if ((idx / k) != (idx % k)) off += v;
+            }
+            put(sh, 0, off);
+            put(sh, 1, tot);
+            tm.reduce(sh, 2);
+            const double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
+            if (cur <= tol2 || (sweep >= 2 && cur > 0.25 * prev)) break;
+            prev = cur;
+            for (int round = 0; round < kk - 1; ++round) {
+                psd_round_params(k, kk, round, mat, R);
+                if (R.nact == 0) continue;                  // uniform across the team
+                // C = J^T A J into tmp: mat is only read, since other
+                // workgroups may still be deriving this round's rotations from it
+                psd_round_apply(k, kk / 2, R, mat, tmp, vm, r0, R_);
+                tm.sync();
+                double* sw = mat;
+                mat = tmp;
+                tmp = sw;
+            }
+        }
+    }
+    // reconstruct from Vt: lam into `in`, Wt = diag(lam+) Vt into tmp
+    for (int e = r0; e < k; e += R_) in[e] = fmax(mat[e * k + e], 0.0);
+    tm.sync();
+    for (int idx = r0; idx < k * k; idx += R_) tmp[idx] = vm[idx] * in[idx / k];
+    tm.sync();
+    for (int idx = r0; idx < k * (k + 1) / 2; idx += R_) {
+        int i, j;
+        psd_unpack_index(k, idx, i, j);
+        double s_ = 0.0;
+        for (int e = 0; e < k; ++e) s_ += tmp[e * k + i] * vm[e * k + j];
+        outv[idx] = (i == j) ? s_ : s_ * 1.41421356237309504880;
+    }
+    if (V0 != nullptr) {
+        for (int idx = r0; idx < k * k; idx += R_) V0[idx] = vm[idx];
+        if (r0 == 0) *warm = 1;
+    }
+    tm.sync();
+}
+
+// Blocks of order above this go to the whole grid team.
+constexpr int kPsdTeamOrder = 64;
+
 // ---------------------------------------------------------------- Pi_C pass
 
 template <typename Team, typename In, typename Emit>
-__device__ __forceinline__ void project_C(Team& tm, int n, int N, const ConeDev& K, double* psd_in,
-                                          double* psd_out, In&& in, Emit&& emit) {
+__device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, const ConeDev& K, In&& in,
+                                          Emit&& emit) {
     // elementwise part: x, zero rows, R+ rows, tau
     const int nel = n + K.z + K.l;
     for (int i = tm.rank(); i <= nel; i += tm.size()) {
@@ -425,28 +547,51 @@ __device__ __forceinline__ void project_C(Team& tm, int n, int N, const ConeDev&
         emit(o + 2, p[2]);
     }
     // PSD blocks: one workgroup per block (the whole workgroup takes the loop
-    // together, so the barriers inside are uniform)
+    // together, so the barriers inside are uniform); in a grid team, blocks of
+    // order above kPsdTeamOrder are then projected by the whole team
     if (K.ns > 0) {
-        double* a = K.psd_scratch + (size_t)tm.blk() * (2 * (size_t)K.psd_kmax * K.psd_kmax +
-                                                        (size_t)K.psd_kmax * (K.psd_kmax + 1));
+        constexpr bool kGrid = !Team::kBlock;
+        double* a = K.psd_scratch + (size_t)tm.blk() * psd_scratch_doubles(K.psd_kmax);
         double* vm = a + (size_t)K.psd_kmax * K.psd_kmax;
-        double* pin = vm + (size_t)K.psd_kmax * K.psd_kmax;
+        double* tmpm = vm + (size_t)K.psd_kmax * K.psd_kmax;
+        double* pin = tmpm + (size_t)K.psd_kmax * K.psd_kmax;
         double* pout = pin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
         for (int c = tm.blk(); c < K.ns; c += tm.nblk()) {
             const int k = K.sord[c];
+            if (kGrid && k > kPsdTeamOrder) continue;
             const int o = n + K.psd0 + K.soff[c];
             const int len = k * (k + 1) / 2;
             for (int e = threadIdx.x; e < len; e += blockDim.x) pin[e] = in(o + e);
             __syncthreads();
-            psd_project_block(tm, k, a, vm, pin, pout,
+            psd_project_block(tm, k, a, vm, tmpm, pin, pout,
                               K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
                               K.psd_warm ? K.psd_warm + c : nullptr);
             for (int e = threadIdx.x; e < len; e += blockDim.x) emit(o + e, pout[e]);
             __syncthreads();
         }
+        if constexpr (kGrid) {
+            if (K.psd_kmax > kPsdTeamOrder) {
+                double* ta = K.psd_scratch;                  // workgroup 0's scratch, after a team barrier
+                double* tv = ta + (size_t)K.psd_kmax * K.psd_kmax;
+                double* tt = tv + (size_t)K.psd_kmax * K.psd_kmax;
+                double* tin = tt + (size_t)K.psd_kmax * K.psd_kmax;
+                double* tout = tin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
+                for (int c = 0; c < K.ns; ++c) {
+                    const int k = K.sord[c];
+                    if (k <= kPsdTeamOrder) continue;
+                    const int o = n + K.psd0 + K.soff[c];
+                    const int len = k * (k + 1) / 2;
+                    tm.sync();
+                    for (int e = tm.rank(); e < len; e += tm.size()) tin[e] = in(o + e);
+                    tm.sync();
+                    psd_project_team(tm, sh, k, ta, tv, tt, tin, tout,
+                                     K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
+                                     K.psd_warm ? K.psd_warm + c : nullptr);
+                    for (int e = tm.rank(); e < len; e += tm.size()) emit(o + e, tout[e]);
+                }
+            }
+        }
     }
-    (void)psd_in;
-    (void)psd_out;
 }
 
 }  // namespace sscs

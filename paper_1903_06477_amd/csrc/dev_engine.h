@@ -396,7 +396,7 @@ __device__ int setup_gdelta(Team& tm, Shared& sh, Prob& P, const Vecs& V, double
 template <typename Team>
 __device__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, double tau) {
     double acc = 0.0, au = 0.0;
-    project_C(tm, P.n, P.N, P.K, nullptr, nullptr,
+    project_C(tm, sh, P.n, P.N, P.K,
               [&](int i) { return 2.0 * corrected(P, V.ut, tau, i) - V.u[i]; },
               [&](int i, double v) {
                   const double ut = corrected(P, V.ut, tau, i);
@@ -797,7 +797,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         for (ls = 0; ls < S.ls_max; ++ls) {
             const double a = alpha;
             double acc_w = 0.0, acc_d = 0.0;
-            project_C(tm, n, N, P.K, nullptr, nullptr,
+            project_C(tm, sh, n, N, P.K,
                       [&](int i) {
                           return 2.0 * (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - (V.u[i] + a * V.d[i]);
                       },

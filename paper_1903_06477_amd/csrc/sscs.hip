@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, un
         }
         if (tm.rank() == 0 && a.scal) a.scal[0] = r2;
     } else if (a.op == OP_PROJECT) {
-        project_C(tm, n, N, P.K, nullptr, nullptr,
+        project_C(tm, sh, n, N, P.K,
                   [&](int i) { return (i >= n && i < n + m) ? a.in[i - n] : 0.0; },
                   [&](int i, double v) { if (i >= n && i < n + m) a.out1[i - n] = v; });
     } else if (a.op == OP_SETUP) {
@@ -326,6 +326,8 @@ struct Inst {
     int *A_rp = nullptr, *A_ci = nullptr, *At_rp = nullptr, *At_ci = nullptr;
     double *A_v = nullptr, *At_v = nullptr;
     float *A_vf = nullptr, *At_vf = nullptr;   // FP32 copies (mixed precision)
+    int *A_long = nullptr, *At_long = nullptr;   // rows summed by a whole workgroup
+    int nlongA = 0, nlongAt = 0, lthrA = 1 << 30, lthrAt = 1 << 30;
     bool mixed = false;
     double *b = nullptr, *c = nullptr, *dinv = nullptr, *g = nullptr;
     double delta = 1.0, nb = 0.0, nc = 0.0;
@@ -462,6 +464,10 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
         I.A_rp = share->A_rp; I.A_ci = share->A_ci; I.A_v = share->A_v;
         I.At_rp = share->At_rp; I.At_ci = share->At_ci; I.At_v = share->At_v;
         I.A_vf = share->A_vf; I.At_vf = share->At_vf;
+        I.A_long = share->A_long; I.At_long = share->At_long;
+        I.nlongA = share->nlongA; I.nlongAt = share->nlongAt;
+        I.lthrA = share->lthrA; I.lthrAt = share->lthrAt;
+        I.h_rpA = share->h_rpA; I.h_rpAt = share->h_rpAt;
         I.dinv = share->dinv;
         I.owns_A = false;
     } else {
@@ -502,6 +508,22 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
     }
     I.segA = pow2_seg((double)d->nnz / std::max(1, I.m));
     I.segAt = pow2_seg((double)d->nnz / std::max(1, I.n));
+    if (!share) {
+        // rows longer than 64 strides of their segment go to a whole workgroup
+        auto longs = [&](const std::vector<int>& rp, int rows, int seg, int** dst, int* cnt, int* thr) -> int {
+            *thr = 64 * seg;
+            std::vector<int> lr;
+            for (int r = 0; r < rows; ++r)
+                if (rp[r + 1] - rp[r] > *thr) lr.push_back(r);
+            *cnt = (int)lr.size();
+            if (lr.empty()) return SSCS_OK;
+            TRY(dmalloc(dst, lr.size()));
+            HIP_TRY(hipMemcpy(*dst, lr.data(), lr.size() * sizeof(int), hipMemcpyHostToDevice));
+            return SSCS_OK;
+        };
+        TRY(longs(I.h_rpA, I.m, I.segA, &I.A_long, &I.nlongA, &I.lthrA));
+        TRY(longs(I.h_rpAt, I.n, I.segAt, &I.At_long, &I.nlongAt, &I.lthrAt));
+    }
     TRY(dmalloc(&I.b, I.m));
     TRY(dmalloc(&I.c, I.n));
     TRY(dmalloc(&I.g, I.n + I.m));
@@ -531,6 +553,7 @@ void free_instance(Inst& I) {
         hipFree(I.A_rp); hipFree(I.A_ci); hipFree(I.A_v);
         hipFree(I.At_rp); hipFree(I.At_ci); hipFree(I.At_v); hipFree(I.dinv);
         hipFree(I.A_vf); hipFree(I.At_vf);
+        hipFree(I.A_long); hipFree(I.At_long);
     }
     hipFree(I.b); hipFree(I.c); hipFree(I.g);
     hipFree(I.qoff); hipFree(I.sord); hipFree(I.soff);
@@ -544,10 +567,10 @@ void free_instance(Inst& I) {
 Prob make_prob(const Inst& I) {
     Prob P{};
     P.n = I.n; P.m = I.m; P.N = I.N;
-    P.A = Csr<double>{I.A_rp, I.A_ci, I.A_v, I.m, I.n, I.segA};
-    P.At = Csr<double>{I.At_rp, I.At_ci, I.At_v, I.n, I.m, I.segAt};
-    P.Af = Csr<float>{I.A_rp, I.A_ci, I.A_vf, I.m, I.n, I.segA};
-    P.Atf = Csr<float>{I.At_rp, I.At_ci, I.At_vf, I.n, I.m, I.segAt};
+    P.A = Csr<double>{I.A_rp, I.A_ci, I.A_v, I.m, I.n, I.segA, I.A_long, I.nlongA, I.lthrA};
+    P.At = Csr<double>{I.At_rp, I.At_ci, I.At_v, I.n, I.m, I.segAt, I.At_long, I.nlongAt, I.lthrAt};
+    P.Af = Csr<float>{I.A_rp, I.A_ci, I.A_vf, I.m, I.n, I.segA, I.A_long, I.nlongA, I.lthrA};
+    P.Atf = Csr<float>{I.At_rp, I.At_ci, I.At_vf, I.n, I.m, I.segAt, I.At_long, I.nlongAt, I.lthrAt};
     P.b = I.b; P.c = I.c; P.dinv = I.dinv; P.g = I.g;
     P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.lds_bytes > 0 ? 1 : 0;
     P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
@@ -773,7 +796,7 @@ int alloc_work_vectors(sscs_work* w) {
     TRY(dmalloc(&w->part, 2 * (size_t)KMAX * w->max_grid));
     if (w->I.K.ns > 0) {
         const size_t k = w->I.K.psd_kmax;
-        const size_t per = 2 * k * k + k * (k + 1);
+        const size_t per = psd_scratch_doubles((int)k);
         const size_t nblk = std::min<size_t>(w->grid, w->I.K.ns);
         TRY(dmalloc(&w->I.K.psd_scratch, per * nblk));
         TRY(dmalloc(&w->I.K.psd_vecs, k * k * (size_t)w->I.K.ns));
@@ -1139,7 +1162,7 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
             Inst& I = bt->inst[i];
             if (I.K.ns > 0) {
                 const size_t k = I.K.psd_kmax;
-                r = dmalloc(&I.K.psd_scratch, 2 * k * k + k * (k + 1));
+                r = dmalloc(&I.K.psd_scratch, psd_scratch_doubles((int)k));
             }
         }
         if (r == SSCS_OK) {

@@ -342,7 +342,7 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
         const int kk = (k & 1) ? k + 1 : k;   // pad to even with a dummy index
         PsdRound& R = psd_round_lds();
         // stop once the off-diagonal part is at the rounding level of a k x k
-        // matrix, or when a sweep no longer gains the quadratic factor
+        // matrix, or when a sweep near that level no longer gains the quadratic factor
         const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
         double prev = 1.0;
         for (int sweep = 0; sweep < 30; ++sweep) {
@@ -367,7 +367,7 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
                 __syncthreads();
             }
             const double cur = R.offn;
-            if (cur <= tol2 || (sweep >= 2 && cur > 0.25 * prev)) break;
+            if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
             prev = cur;
             for (int round = 0; round < kk - 1; ++round) {
                 psd_round_params(k, kk, round, mat, R);
@@ -467,7 +467,7 @@ __device__ void psd_project_team(Team& tm, Shared& sh, int k, double* a, double*
             put(sh, 1, tot);
             tm.reduce(sh, 2);
             const double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
-            if (cur <= tol2 || (sweep >= 2 && cur > 0.25 * prev)) break;
+            if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
             prev = cur;
             for (int round = 0; round < kk - 1; ++round) {
                 psd_round_params(k, kk, round, mat, R);

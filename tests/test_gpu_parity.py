@@ -94,6 +94,25 @@ def test_project_dual_cone_matches_oracle(sscs, seed):
             np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10 * (1 + np.abs(y).max()))
 
 
+@pytest.mark.parametrize("orders", [[5, 80], [3, 130, 66, 65]])
+def test_project_large_psd_blocks(sscs, orders):
+    """Blocks above order 64 take the grid-team Jacobi path; repeated calls on
+    nearby points take its warm-started form."""
+    from oracle.cones import proj_dual_cone
+    cone = G.Cone(z=2, l=3, s=orders)
+    m = cone.rows()
+    prob = G.Problem(A=sp.csr_matrix(np.ones((m, 1))), b=np.zeros(m), c=np.ones(1), cone=cone)
+    r = np.random.default_rng(sum(orders))
+    with sscs.Solver(prob) as s:
+        y = r.standard_normal(m)
+        for step in range(4):
+            yy = y * (10.0 ** (step - 1)) if step < 3 else y + 1e-6 * r.standard_normal(m)
+            print(f"psd orders {orders} call {step}", flush=True)
+            got = s.project_dual_cone(yy)
+            ref = proj_dual_cone(yy, cone)
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10 * (1 + np.abs(yy).max()))
+
+
 def test_project_exp_hard_points(sscs):
     """Exponential cones near the boundary, the face and the polar."""
     from oracle.cones import proj_dual_cone

@@ -1,5 +1,7 @@
 """GPU parity on the mixed PSD / exponential-cone instance (sparse PCA blocks
-of orders 4, 4, 7 plus a 30-sample l1 logistic regression): status, pr, dr,
+of orders 4, 4, 7 plus a 30-sample l1 logistic regression, and a variant with
+blocks of orders 4 and 66, whose larger block takes the grid-team projection
+path on the grid kernel): status, pr, dr,
 gap <= eps recomputed on the CPU in FP64 from the returned (x, y, s), the
 returned y in K* and s in K to 1e-6, and the objective within 1e-5 relative
 of the oracle's, in FP64 and mixed precision, on the grid kernel and on the
@@ -31,10 +33,13 @@ def reference():
     for seed in (0, 1):
         p = G.small_sdp_exp(seed)
         out[seed] = (p, S.solve(p, S.Settings(direction="aa", mem=5, max_iters=20000)))
+    # one PSD block of order 66: the grid-team projection path
+    p = G.config3_sdp_exp(instance=2001, nblk=1, k=4, kbig=66, q=20, p=4, density=0.3)
+    out[2] = (p, S.solve(p, S.Settings(direction="aa", mem=5, max_iters=20000)))
     return out
 
 
-@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("grid", ["auto", "1"])
 def test_sdp_exp_end_to_end(sscs, reference, seed, precision, grid):

@@ -8,6 +8,11 @@ is resident in HBM before timing; outputs go to device buffers.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (the persistent solve kernel) and the CPU oracle timed on a bounded sample.
+Further fields measure the other workloads on the same GPU: the same SOCP
+with the mixed-precision linear step, the stand-alone SpMV of the CG, 4096
+batched LASSO instances in one launch, the learned warm start against the
+cold-started method on the shared-A LASSO family, and iterations per second
+on the mixed PSD / exponential-cone instance.
 """
 from __future__ import annotations
 
@@ -133,6 +138,32 @@ def learned_leg(ntrain=2048, ntest=1024, epochs=60):
             "warm_worst_residual": r["warm_worst_residual"]}
 
 
+def sdp_exp_leg(sscs, G, iters=150):
+    """The mixed PSD / exponential-cone instance (64 sparse-PCA blocks of
+    order 64 and one of order 256, l1 logistic regression with 5000 samples x
+    1000 features; n = 349033, m = 535113): `iters` iterations of Algorithm 1
+    timed (a complete solve to 1e-6 takes about 4300), reported as iterations
+    per second, FP64, AA memory 5."""
+    import torch
+    p = G.config3_sdp_exp()
+    st = bench_settings(sscs, iters)
+    s = sscs.Solver(p, st)
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty(p.m, dtype=torch.float64, device="cuda:0")
+    sv = torch.empty(p.m, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.solve(out=(x, y, sv))[3]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.close()
+    return {"workload": "sparse PCA (64 x order 64 + order 256, lambda 2) + l1 logistic regression "
+                        "(5000 x 1000 at 1%), PSD rows 166016, 10000 exp cones",
+            "n": p.n, "m": p.m, "nnz": int(p.A.nnz), "iters": info["iters"], "wall_s": wall,
+            "iterations_per_s": info["iters"] / wall, "cg_iters": info["cg_iters"], "res_fp": info["res_fp"],
+            "dtype": "f64"}
+
+
 def source_digest():
     """SHA-256 of the HIP sources the solve kernel is built from."""
     import hashlib
@@ -185,6 +216,8 @@ def main():
     ap.add_argument("--max-iters", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched LASSO leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-sdp", action="store_true", help="skip the PSD / exponential-cone leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -276,19 +309,22 @@ def main():
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }
     solver.close()
-    # the same workload with the mixed-precision linear step
-    stm = bench_settings(sscs, args.max_iters)
-    stm.precision = "mixed"
-    with sscs.Solver(prob, stm, stream=stream.cuda_stream) as sm:
-        sm.solve(out=(x, y, s))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        im = sm.solve(out=(x, y, s))[3]
-        torch.cuda.synchronize()
-        wm = time.perf_counter() - t0
-    out["mixed"] = {"solves_per_s": 1.0 / wm if im["status"] == sscs.SOLVED else 0.0, "iters": im["iters"],
-                    "cg_iters": im["cg_iters"], "pr": im["pr"], "dr": im["dr"], "gap": im["gap"],
-                    "dtype": "f32 operator in CG / f64 residuals, refinement, scalars"}
+    if not args.no_mixed:
+        # the same workload with the mixed-precision linear step
+        stm = bench_settings(sscs, args.max_iters)
+        stm.precision = "mixed"
+        with sscs.Solver(prob, stm, stream=stream.cuda_stream) as sm:
+            sm.solve(out=(x, y, s))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            im = sm.solve(out=(x, y, s))[3]
+            torch.cuda.synchronize()
+            wm = time.perf_counter() - t0
+        out["mixed"] = {"solves_per_s": 1.0 / wm if im["status"] == sscs.SOLVED else 0.0, "iters": im["iters"],
+                        "cg_iters": im["cg_iters"], "pr": im["pr"], "dr": im["dr"], "gap": im["gap"],
+                        "dtype": "f32 operator in CG / f64 residuals, refinement, scalars"}
+    if not args.no_sdp:
+        out["sdp_exp"] = sdp_exp_leg(sscs, G)
     if not args.no_batched:
         probs4 = [G.config4_instance(i) for i in range(4096)]
         out["batched"] = batched_leg(sscs, G, probs=probs4)

@@ -161,7 +161,7 @@ def sdp_exp_leg(sscs, G, iters=150):
                         "(5000 x 1000 at 1%), PSD rows 166016, 10000 exp cones",
             "n": p.n, "m": p.m, "nnz": int(p.A.nnz), "iters": info["iters"], "wall_s": wall,
             "iterations_per_s": info["iters"] / wall, "cg_iters": info["cg_iters"], "res_fp": info["res_fp"],
-            "dtype": "f64"}
+            "status": info["status_name"], "pr": info["pr"], "dr": info["dr"], "gap": info["gap"], "dtype": "f64"}
 
 
 def source_digest():
@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-sdp", action="store_true", help="skip the PSD / exponential-cone leg")
+    ap.add_argument("--sdp-iters", type=int, default=150,
+                    help="iteration cap of the PSD / exponential-cone leg (a large cap times a complete solve)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -324,7 +326,7 @@ def main():
                         "cg_iters": im["cg_iters"], "pr": im["pr"], "dr": im["dr"], "gap": im["gap"],
                         "dtype": "f32 operator in CG / f64 residuals, refinement, scalars"}
     if not args.no_sdp:
-        out["sdp_exp"] = sdp_exp_leg(sscs, G)
+        out["sdp_exp"] = sdp_exp_leg(sscs, G, args.sdp_iters)
     if not args.no_batched:
         probs4 = [G.config4_instance(i) for i in range(4096)]
         out["batched"] = batched_leg(sscs, G, probs=probs4)

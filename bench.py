@@ -135,7 +135,8 @@ def learned_leg(ntrain=2048, ntest=1024, epochs=60):
             "iters_warm_mean": r["iters_warm_mean"], "cold_solves_per_s": ntest / r["t_cold"],
             "warm_solves_per_s": ntest / r["t_warm_total"], "train_loss": [r["loss_first"], r["loss_last"]],
             "training_data_s": r["t_generate"], "training_s": r["t_train"],
-            "warm_worst_residual": r["warm_worst_residual"]}
+            "warm_worst_residual": r["warm_worst_residual"], "test_loss": r["test_loss"],
+            "ablation_training_mean_start": {"solve_s": r["t_mean_start"], "iters_mean": r["iters_mean_start"]}}
 
 
 def sdp_exp_leg(sscs, G, iters=150):

@@ -33,8 +33,8 @@ extern "C" {
 typedef struct sscs_mlp sscs_mlp;
 
 /* widths has nlayers + 1 entries (each >= 1); max_batch bounds every batch.
- * Weights are initialised with He-uniform values from a counter-based hash of
- * (seed, layer, index); biases are zero. */
+ * Weights and biases of layer l are initialised uniform in +-1/sqrt(w_l) from a
+ * counter-based hash (splitmix64) of (seed, stream, index). */
 int sscs_mlp_create(int32_t nlayers, const int32_t *widths, int32_t max_batch, uint64_t seed,
                     void *hip_stream, sscs_mlp **out);
 int sscs_mlp_destroy(sscs_mlp *net);

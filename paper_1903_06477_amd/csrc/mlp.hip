@@ -183,16 +183,18 @@ __global__ void k_adam(float* __restrict__ W, const float* __restrict__ g, float
     }
 }
 
-// Counter-based initialisation: splitmix64 of (seed, layer, index) -> uniform
-// in [-a, a) with a = sqrt(6 / fan_in).
-__global__ void k_init(float* __restrict__ W, size_t n, int fan_in, unsigned long long seed, int layer) {
+// Counter-based initialisation: splitmix64 of (seed, stream, index) ->
+// uniform in [-a, a) with a = 1 / sqrt(fan_in), for weights (stream 2 l) and
+// biases (stream 2 l + 1) of layer l.  (A wider range with zero biases leaves
+// most ReLU units of this network dead after a few Adam steps.)
+__global__ void k_init(float* __restrict__ W, size_t n, int fan_in, unsigned long long seed, int stream) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        unsigned long long z = seed + 0x9e3779b97f4a7c15ull * ((unsigned long long)layer * 0x100000000ull + i + 1);
+        unsigned long long z = seed + 0x9e3779b97f4a7c15ull * ((unsigned long long)stream * 0x100000000ull + i + 1);
         z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
         z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
         z = z ^ (z >> 31);
         const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
-        W[i] = (float)((2.0 * u - 1.0) * sqrt(6.0 / fan_in));
+        W[i] = (float)((2.0 * u - 1.0) / sqrt((double)fan_in));
     }
 }
 
@@ -384,7 +386,9 @@ int sscs_mlp_create(int32_t nlayers, const int32_t* widths, int32_t max_batch, u
     if (r == SSCS_OK) r = dalloc(&n->lossd, 1);
     for (int l = 0; l < nlayers && r == SSCS_OK; ++l) {
         const size_t nw = (size_t)widths[l + 1] * widths[l];
-        k_init<<<grid_for(nw), 256, 0, n->stream>>>(n->W[l], nw, widths[l], (unsigned long long)seed, l);
+        k_init<<<grid_for(nw), 256, 0, n->stream>>>(n->W[l], nw, widths[l], (unsigned long long)seed, 2 * l);
+        k_init<<<grid_for(widths[l + 1]), 256, 0, n->stream>>>(n->b[l], widths[l + 1], widths[l],
+                                                              (unsigned long long)seed, 2 * l + 1);
         if (hipGetLastError() != hipSuccess) r = SSCS_E_HIP;
         if (r == SSCS_OK) r = refresh_bf16(n, l);
     }

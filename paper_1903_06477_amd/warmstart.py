@@ -83,6 +83,7 @@ class WarmStarter:
         import torch
         xm, xs = X.mean(0), X.std(0) + 1e-6
         tm, ts = T.mean(0), T.std(0) + 1e-6
+        self.t_mean, self.t_std = tm, ts
         Xd = torch.from_numpy(((X - xm) / xs).astype(np.float32)).cuda()
         Td = torch.from_numpy(((T - tm) / ts).astype(np.float32)).cuda()
         rng = np.random.default_rng(seed)
@@ -132,7 +133,7 @@ def residuals(prob, x, y, s):
 
 
 def experiment(ntrain: int, ntest: int, epochs: int = 60, seed: int = 0, check_every: int = 1,
-               settings: Optional[S.Settings] = None, log=print) -> Dict:
+               settings: Optional[S.Settings] = None, log=print, lr: float = 1e-3) -> Dict:
     """Train on ntrain cold-solved instances; test on ntest instances warm
     (network inference + warm batched solve + cold fallbacks) vs cold."""
     import torch
@@ -158,13 +159,13 @@ def experiment(ntrain: int, ntest: int, epochs: int = 60, seed: int = 0, check_e
     # 2. train
     ws = WarmStarter(X.shape[1], T.shape[1], seed=seed)
     t1 = time.perf_counter()
-    losses = ws.fit(X, T, epochs=epochs, seed=seed)
+    losses = ws.fit(X, T, epochs=epochs, seed=seed, lr=lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     log(f"training: {epochs} epochs in {t_train:.2f}s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     # 3. test: cold vs warm
     Xt = torch.from_numpy(features(test)).cuda()
-    _, _, _, info_cold, t_cold = batched_solve(test, st)
+    xc, yc, sc, info_cold, t_cold = batched_solve(test, st)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     pred = ws.predict(Xt)
@@ -176,7 +177,15 @@ def experiment(ntrain: int, ntest: int, epochs: int = 60, seed: int = 0, check_e
     t_fb = 0.0
     if fail:
         _, _, _, info_fb, t_fb = batched_solve([test[i] for i in fail], st)
+    # ablation: the same warm start built from the training targets' mean (no network)
+    Tm = torch.from_numpy(np.tile(T.mean(0), (ntest, 1)).astype(np.float32)).cuda()
+    u0m = M.assemble_u0(Tm, n, m).reshape(-1)
+    _, _, _, info_mean, t_mean = batched_solve(test, st, u0=u0m)
+    it_mean = np.array([i["iters"] for i in info_mean])
     it_cold = np.array([i["iters"] for i in info_cold])
+    # held-out loss in the training standardisation (1.0 = no better than the mean)
+    Tt = targets(xc.cpu().numpy(), yc.cpu().numpy(), sc.cpu().numpy(), ntest, n, m)
+    test_loss = float(np.mean(((pred.cpu().numpy() - Tt) / ws.t_std) ** 2))
     it_warm = np.array([i["iters"] for i in info_warm])
     cold_ok = np.mean([i["status"] == S.SOLVED for i in info_cold])
     # host check of the warm solutions
@@ -192,10 +201,11 @@ def experiment(ntrain: int, ntest: int, epochs: int = 60, seed: int = 0, check_e
                t_inference=t_inf, t_warm_solve=t_warm, t_fallback=t_fb, n_fallback=len(fail),
                t_warm_total=t_inf + t_warm + t_fb, iters_cold_mean=float(it_cold.mean()),
                iters_warm_mean=float(it_warm.mean()), warm_worst_residual=wworst,
+               t_mean_start=t_mean, iters_mean_start=float(it_mean.mean()), test_loss=test_loss,
                speedup=t_cold / (t_inf + t_warm + t_fb))
     log(f"test: cold {t_cold:.2f}s ({it_cold.mean():.0f} it), warm {t_inf + t_warm + t_fb:.2f}s = inference "
         f"{t_inf:.3f}s + solve {t_warm:.2f}s ({it_warm.mean():.0f} it) + fallback {t_fb:.2f}s ({len(fail)}); "
-        f"speedup {res['speedup']:.2f}x")
+        f"speedup {res['speedup']:.2f}x; training-mean start {t_mean:.2f}s ({it_mean.mean():.0f} it)")
     return res
 
 
@@ -206,5 +216,6 @@ if __name__ == "__main__":
     ap.add_argument("--ntrain", type=int, default=2048)
     ap.add_argument("--ntest", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=1e-3)
     a = ap.parse_args()
-    print(json.dumps(experiment(a.ntrain, a.ntest, a.epochs, log=lambda s: print(s, flush=True))))
+    print(json.dumps(experiment(a.ntrain, a.ntest, a.epochs, lr=a.lr, log=lambda s: print(s, flush=True))))

@@ -121,7 +121,7 @@ def test_create_is_deterministic_and_rejects_bad_batches(M):
     Wc, _ = c.get_params()
     assert all(np.array_equal(x, y) for x, y in zip(Wa, Wb))
     assert not np.array_equal(Wa[0], Wc[0])
-    lim = np.sqrt(6.0 / 10)
+    lim = np.sqrt(1.0 / 10)
     assert np.abs(Wa[0]).max() <= lim and np.abs(Wa[0]).max() > 0.5 * lim
     X = _dev(np.zeros((9, 10)))
     with pytest.raises(S.SSCSError):

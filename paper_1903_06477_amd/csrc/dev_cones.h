@@ -26,6 +26,7 @@ struct ConeDev {
     int ep;                   // exponential cones
     int soc0, psd0, exp0;     // first row of each region (relative to the start of y)
     double* psd_scratch;      // per-workgroup scratch for PSD blocks (psd_scratch_doubles(kmax) each)
+    double* psd_team;         // grid-team scratch for blocks above kPsdTeamOrder (psd_team_doubles(kmax))
     int psd_kmax;
     double* psd_vecs;         // per block: the eigenvectors of its last projection (kmax^2
                               // doubles each), or null: every projection starts cold
@@ -174,6 +175,12 @@ __device__ inline void proj_exp_dual(const double* v, double* out) {
 // each), the packed input and output.
 __host__ __device__ inline size_t psd_scratch_doubles(int kmax) {
     return 3 * (size_t)kmax * kmax + (size_t)kmax * (kmax + 1);
+}
+
+// Scratch of the grid-team projection: four k x k matrices, the packed input
+// and output.
+__host__ __device__ inline size_t psd_team_doubles(int kmax) {
+    return 4 * (size_t)kmax * kmax + (size_t)kmax * (kmax + 1);
 }
 
 // Column j and row i of packed index idx (column-major lower triangle).
@@ -403,83 +410,247 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
 
 // The same projection computed by a whole grid team, for blocks too large for
 // one workgroup to turn over quickly (the order-256 block of the sparse-PCA
-// instance).  Every pass is spread over all threads of the team; each
-// workgroup derives the round's rotations itself from the shared matrix, so a
-// round costs one team barrier.  Same arithmetic per entry as
-// psd_project_block.  `in` (packed input, filled by the caller) and the
-// buffers are global scratch visible to the whole team.
+// instance): a two-sided *block* Jacobi method.  The indices are cut into
+// tiles of kPsdTile; each round pairs the tiles round-robin, and workgroup w
+// diagonalises pair w's 2-tile principal submatrix in LDS (cyclic Jacobi to
+// the rounding level), producing an orthogonal Q_w.  Then, spread over the
+// whole team, the rows of A and of Vt are turned by Q^T (A' = Q^T A,
+// Vt' = Q^T Vt) and the columns of A' by Q (A'' = A' Q) -- dense products of
+// 2-tile panels.  Three team barriers per round and k/kPsdTile - 1 rounds per
+// sweep, instead of one barrier per round over k - 1 rounds.  Warm start and
+// stopping rule as in psd_project_block.
+constexpr int kPsdTile = 8;
+constexpr int kPsdSub = 2 * kPsdTile;
+
+struct PsdSub {
+    double S[kPsdSub][kPsdSub + 1];
+    double Q[kPsdSub][kPsdSub + 1];
+};
+
+__device__ __forceinline__ PsdSub& psd_sub_lds() {
+    __shared__ PsdSub r;
+    return r;
+}
+
+// Global index of slot `a` (0 .. kPsdSub-1) of tile pair (t1, t2), or -1 when
+// the slot lies past k or in the dummy tile.
+__device__ __forceinline__ int psd_slot_index(int k, int nt, int t1, int t2, int a) {
+    const int t = a < kPsdTile ? t1 : t2;
+    if (t >= nt) return -1;
+    const int g = t * kPsdTile + (a % kPsdTile);
+    return g < k ? g : -1;
+}
+
+// Tile pair h of round `round` over ntt (even) tile positions.
+__device__ __forceinline__ void psd_tile_pair(int ntt, int round, int h, int& t1, int& t2) {
+    const int x = (h == 0) ? 0 : 1 + ((h - 1 + round) % (ntt - 1));
+    const int y = 1 + ((ntt - 2 - h + round) % (ntt - 1));
+    t1 = x < y ? x : y;
+    t2 = x < y ? y : x;
+}
+
+// Tile pair containing tile t in round `round`, and t's side (0: first tile).
+__device__ __forceinline__ int psd_tile_owner(int ntt, int round, int t, int& side) {
+    for (int h = 0; h < ntt / 2; ++h) {
+        int t1, t2;
+        psd_tile_pair(ntt, round, h, t1, t2);
+        if (t1 == t) { side = 0; return h; }
+        if (t2 == t) { side = 1; return h; }
+    }
+    side = 0;
+    return 0;
+}
+
+// Diagonalises the 2-tile submatrix of `mat` for tile pair (t1, t2) in LDS
+// and writes Q (slot x slot, row-major) to q.  One workgroup.
+__device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, const double* mat, double* q, PsdRound& R) {
+    PsdSub& L = psd_sub_lds();
+    const int t = threadIdx.x, n = blockDim.x;
+    for (int e = t; e < kPsdSub * kPsdSub; e += n) {
+        const int a = e / kPsdSub, b = e % kPsdSub;
+        const int ga = psd_slot_index(k, nt, t1, t2, a), gb = psd_slot_index(k, nt, t1, t2, b);
+        L.S[a][b] = (ga >= 0 && gb >= 0) ? mat[(size_t)ga * k + gb] : 0.0;
+        L.Q[a][b] = a == b ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double tol2 = (1e-16 * kPsdSub) * (1e-16 * kPsdSub);
+    double prev = 1.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        if (t == 0) {
+            double off = 0.0, tot = 0.0;
+            for (int a = 0; a < kPsdSub; ++a)
+                for (int b = 0; b < kPsdSub; ++b) {
+                    const double v = L.S[a][b] * L.S[a][b];
+                    tot += v;
+                    if (a != b) off += v;
+                }
+            R.offn = tot > 0.0 ? off / tot : 0.0;
+        }
+        __syncthreads();
+        const double cur = R.offn;
+        if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
+        prev = cur;
+        for (int round = 0; round < kPsdSub - 1; ++round) {
+            for (int h = t; h < kPsdSub / 2; h += n) {
+                int p, qq;
+                psd_tile_pair(kPsdSub, round, h, p, qq);
+                double c = 1.0, s_ = 0.0;
+                const double apq = L.S[p][qq];
+                if (apq != 0.0 && fabs(apq) > 2.2e-16 * sqrt(fabs(L.S[p][p] * L.S[qq][qq]))) {
+                    const double tau = (L.S[qq][qq] - L.S[p][p]) / (2.0 * apq);
+                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s_ = tt * c;
+                }
+                R.pp[h] = p; R.qq[h] = qq; R.cs[h] = c; R.sn[h] = s_;
+            }
+            __syncthreads();
+            // rows p, q of S <- J^T S
+            for (int e = t; e < (kPsdSub / 2) * kPsdSub; e += n) {
+                const int h = e / kPsdSub, j = e % kPsdSub;
+                const double c = R.cs[h], s_ = R.sn[h];
+                if (s_ == 0.0) continue;
+                const int p = R.pp[h], qq = R.qq[h];
+                const double xp = L.S[p][j], xq = L.S[qq][j];
+                L.S[p][j] = c * xp - s_ * xq;
+                L.S[qq][j] = s_ * xp + c * xq;
+            }
+            __syncthreads();
+            // columns p, q of S and of Q <- (.) J
+            for (int e = t; e < (kPsdSub / 2) * kPsdSub; e += n) {
+                const int h = e / kPsdSub, i = e % kPsdSub;
+                const double c = R.cs[h], s_ = R.sn[h];
+                if (s_ == 0.0) continue;
+                const int p = R.pp[h], qq = R.qq[h];
+                const double xp = L.S[i][p], xq = L.S[i][qq];
+                L.S[i][p] = c * xp - s_ * xq;
+                L.S[i][qq] = s_ * xp + c * xq;
+                const double vp = L.Q[i][p], vq = L.Q[i][qq];
+                L.Q[i][p] = c * vp - s_ * vq;
+                L.Q[i][qq] = s_ * vp + c * vq;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = t; e < kPsdSub * kPsdSub; e += n) q[e] = L.Q[e / kPsdSub][e % kPsdSub];
+    __syncthreads();
+}
+
+// `buf` holds 4 k*k doubles (matrix, its turned copy, Vt and its turned copy);
+// `in` (packed input, filled by the caller) and `outv` are contiguous, with
+// room for the rounds' Q matrices (k (k + 1) doubles in all, k > 2 kPsdTile).
 template <typename Team>
-__device__ void psd_project_team(Team& tm, Shared& sh, int k, double* a, double* vm, double* tmp, double* in,
-                                 double* outv, double* V0, int* warm) {
+__device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, double* buf, double* in, double* outv, double* V0,
+                                 int* warm) {
     const int r0 = tm.rank(), R_ = tm.size();
     const double rs2 = 0.70710678118654752440;
+    double* mat = buf;
+    double* tmp = buf + (size_t)k * k;
+    double* vm = tmp + (size_t)k * k;
+    double* vm2 = vm + (size_t)k * k;
+    double* qb = in;                                   // Q of every pair of a round (after the unpack)
     for (int idx = r0; idx < k * (k + 1) / 2; idx += R_) {
         int i, j;
         psd_unpack_index(k, idx, i, j);
         const double v = in[idx];
-        if (i == j) a[i * k + i] = v;
-        else { a[i * k + j] = v * rs2; a[j * k + i] = v * rs2; }
+        if (i == j) mat[i * k + i] = v;
+        else { mat[i * k + j] = v * rs2; mat[j * k + i] = v * rs2; }
     }
     tm.sync();
-    double* mat = a;
     const bool use_warm = V0 != nullptr && *warm != 0;
     if (use_warm) {
         for (int idx = r0; idx < k * k; idx += R_) {    // tmp = Vt0 A
             const int i = idx / k, j = idx - (idx / k) * k;
             double s_ = 0.0;
-            for (int e = 0; e < k; ++e) s_ += V0[i * k + e] * a[e * k + j];
+            for (int e = 0; e < k; ++e) s_ += V0[i * k + e] * mat[e * k + j];
             tmp[idx] = s_;
         }
         tm.sync();
-        for (int idx = r0; idx < k * k; idx += R_) {    // a = (Vt0 A) Vt0^T
+        for (int idx = r0; idx < k * k; idx += R_) {    // vm2 = (Vt0 A) Vt0^T
             const int i = idx / k, j = idx - (idx / k) * k;
             double s_ = 0.0;
             for (int e = 0; e < k; ++e) s_ += tmp[i * k + e] * V0[j * k + e];
-            a[idx] = s_;
+            vm2[idx] = s_;
         }
         tm.sync();
         for (int idx = r0; idx < k * k; idx += R_) {
             const int i = idx / k, j = idx - (idx / k) * k;
-            if (i < j) {
-                const double v = 0.5 * (a[i * k + j] + a[j * k + i]);
-                a[i * k + j] = v;
-                a[j * k + i] = v;
-            }
+            mat[idx] = 0.5 * (vm2[i * k + j] + vm2[j * k + i]);   // symmetrise (rounding)
             vm[idx] = V0[idx];
         }
     } else {
         for (int idx = r0; idx < k * k; idx += R_) vm[idx] = ((idx / k) == (idx % k)) ? 1.0 : 0.0;
     }
     tm.sync();
-    if (k > 1) {
-        const int kk = (k & 1) ? k + 1 : k;
-        PsdRound& R = psd_round_lds();
-        const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
-        double prev = 1.0;
-        for (int sweep = 0; sweep < 30; ++sweep) {
-            double off = 0.0, tot = 0.0;
+    const int nt = (k + kPsdTile - 1) / kPsdTile;        // tiles
+    const int ntt = nt + (nt & 1);                        // even, with a dummy tile
+    const int np = ntt / 2;
+    PsdRound& R = psd_round_lds();
+    const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
+    double prev = 1.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int idx = r0; idx < k * k; idx += R_) {
+            const double v = mat[idx] * mat[idx];
+            tot += v;
+            if ((idx / k) != (idx % k)) off += v;
+        }
+        put(sh, 0, off);
+        put(sh, 1, tot);
+        tm.reduce(sh, 2);
+        const double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
+        if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
+        prev = cur;
+        for (int round = 0; round < ntt - 1; ++round) {
+            // 1. each pair's submatrix diagonalised by one workgroup
+            for (int h = tm.blk(); h < np; h += tm.nblk()) {
+                int t1, t2;
+                psd_tile_pair(ntt, round, h, t1, t2);
+                psd_sub_diag(k, nt, t1, t2, mat, qb + (size_t)h * kPsdSub * kPsdSub, R);
+            }
+            tm.sync();
+            // 2. tmp = Q^T A and vm2 = Q^T Vt on the rows of each pair
             for (int idx = r0; idx < k * k; idx += R_) {
-                const double v = mat[idx] * mat[idx];
-                tot += v;
-                if ((idx / k) != (idx % k)) off += v;
+                const int r = idx / k, j = idx - (idx / k) * k;
+                int side;
+                const int h = psd_tile_owner(ntt, round, r / kPsdTile, side);
+                int t1, t2;
+                psd_tile_pair(ntt, round, h, t1, t2);
+                const double* q = qb + (size_t)h * kPsdSub * kPsdSub;
+                const int ip = side * kPsdTile + r % kPsdTile;
+                double sa = 0.0, sv = 0.0;
+                for (int a = 0; a < kPsdSub; ++a) {
+                    const int ga = psd_slot_index(k, nt, t1, t2, a);
+                    if (ga < 0) continue;
+                    const double qa = q[a * kPsdSub + ip];
+                    sa += qa * mat[(size_t)ga * k + j];
+                    sv += qa * vm[(size_t)ga * k + j];
+                }
+                tmp[idx] = sa;
+                vm2[idx] = sv;
             }
-            put(sh, 0, off);
-            put(sh, 1, tot);
-            tm.reduce(sh, 2);
-            const double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
-            if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
-            prev = cur;
-            for (int round = 0; round < kk - 1; ++round) {
-                psd_round_params(k, kk, round, mat, R);
-                if (R.nact == 0) continue;                  // uniform across the team
-                // C = J^T A J into tmp: mat is only read, since other
-                // workgroups may still be deriving this round's rotations from it
-                psd_round_apply(k, kk / 2, R, mat, tmp, vm, r0, R_);
-                tm.sync();
-                double* sw = mat;
-                mat = tmp;
-                tmp = sw;
+            tm.sync();
+            // 3. mat = tmp Q on the columns of each pair
+            for (int idx = r0; idx < k * k; idx += R_) {
+                const int i = idx / k, c = idx - (idx / k) * k;
+                int side;
+                const int h = psd_tile_owner(ntt, round, c / kPsdTile, side);
+                int t1, t2;
+                psd_tile_pair(ntt, round, h, t1, t2);
+                const double* q = qb + (size_t)h * kPsdSub * kPsdSub;
+                const int cp = side * kPsdTile + c % kPsdTile;
+                double s_ = 0.0;
+                for (int b = 0; b < kPsdSub; ++b) {
+                    const int gb = psd_slot_index(k, nt, t1, t2, b);
+                    if (gb < 0) continue;
+                    s_ += tmp[(size_t)i * k + gb] * q[b * kPsdSub + cp];
+                }
+                mat[idx] = s_;
             }
+            double* sw = vm;
+            vm = vm2;
+            vm2 = sw;
+            tm.sync();
         }
     }
     // reconstruct from Vt: lam into `in`, Wt = diag(lam+) Vt into tmp
@@ -571,10 +742,8 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
         }
         if constexpr (kGrid) {
             if (K.psd_kmax > kPsdTeamOrder) {
-                double* ta = K.psd_scratch;                  // workgroup 0's scratch, after a team barrier
-                double* tv = ta + (size_t)K.psd_kmax * K.psd_kmax;
-                double* tt = tv + (size_t)K.psd_kmax * K.psd_kmax;
-                double* tin = tt + (size_t)K.psd_kmax * K.psd_kmax;
+                double* tb = K.psd_team;                     // 4 kmax^2 matrices, then input / output
+                double* tin = tb + 4 * (size_t)K.psd_kmax * K.psd_kmax;
                 double* tout = tin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
                 for (int c = 0; c < K.ns; ++c) {
                     const int k = K.sord[c];
@@ -584,7 +753,7 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
                     tm.sync();
                     for (int e = tm.rank(); e < len; e += tm.size()) tin[e] = in(o + e);
                     tm.sync();
-                    psd_project_team(tm, sh, k, ta, tv, tt, tin, tout,
+                    psd_project_team(tm, sh, k, tb, tin, tout,
                                      K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
                                      K.psd_warm ? K.psd_warm + c : nullptr);
                     for (int e = tm.rank(); e < len; e += tm.size()) emit(o + e, tout[e]);

@@ -226,8 +226,10 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
     return it;
 }
 
+// Out of line: the CG loop then gets a register allocation of its own,
+// independent of the rest of the solve kernel it is called from.
 template <typename TV, typename Team>
-__device__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
+__device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit) {
     if constexpr (Team::kBlock) {
         if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit);

@@ -545,6 +545,7 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
     I.K.psd_kmax = h.kmax;
     I.K.psd_vecs = nullptr;
     I.K.psd_warm = nullptr;
+    I.K.psd_team = nullptr;
     return SSCS_OK;
 }
 
@@ -559,6 +560,7 @@ void free_instance(Inst& I) {
     hipFree(I.qoff); hipFree(I.sord); hipFree(I.soff);
     hipFree(I.K.psd_scratch);
     hipFree(I.K.psd_vecs);
+    hipFree(I.K.psd_team);
     hipFree(I.K.psd_warm);
     hipFree(I.partA); hipFree(I.partAt);
     I = Inst{};
@@ -800,6 +802,7 @@ int alloc_work_vectors(sscs_work* w) {
         const size_t nblk = std::min<size_t>(w->grid, w->I.K.ns);
         TRY(dmalloc(&w->I.K.psd_scratch, per * nblk));
         TRY(dmalloc(&w->I.K.psd_vecs, k * k * (size_t)w->I.K.ns));
+        if ((int)k > kPsdTeamOrder) TRY(dmalloc(&w->I.K.psd_team, psd_team_doubles((int)k)));
         TRY(dmalloc(&w->I.K.psd_warm, (size_t)w->I.K.ns));
         HIP_TRY(hipMemsetAsync(w->I.K.psd_warm, 0, w->I.K.ns * sizeof(int), w->stream));
     }

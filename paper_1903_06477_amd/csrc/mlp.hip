@@ -162,12 +162,23 @@ __global__ void k_relu_back(const float* __restrict__ dH, int rows, int cols, co
 }
 
 // out[j] = sum_r G[r][j] (bias gradients), rows summed in order.
-__global__ void k_colsum(const float* __restrict__ G, int rows, int cols, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+// 256 threads = 16 columns x 16 row groups; row group g sums rows g, g + 16, ...
+// of its column, then the 16 partial sums are added in group order.
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ G, int rows, int cols,
+                                                float* __restrict__ out) {
+    __shared__ double part[16][17];
+    const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int j = blockIdx.x * 16 + c;
     double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += G[(size_t)r * cols + j];
-    out[j] = (float)s;
+    if (j < cols)
+        for (int r = g; r < rows; r += 16) s += G[(size_t)r * cols + j];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < cols) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += part[q][c];
+        out[j] = (float)t;
+    }
 }
 
 __global__ void k_adam(float* __restrict__ W, const float* __restrict__ g, float* __restrict__ m,
@@ -301,7 +312,7 @@ int backward(sscs_mlp* n, int batch, const float* X, const float* T, float* Y) {
         HTRY(hipGetLastError());
         r = launch_gemm(n->stream, n->GT, ldB, n->HT, ldB, out, in, ldB, nullptr, 0, n->gW[l], in, nullptr, 0);
         if (r != SSCS_OK) return r;
-        k_colsum<<<(out + 255) / 256, 256, 0, n->stream>>>(G, batch, out, n->gb[l]);
+        k_colsum<<<(out + 15) / 16, 256, 0, n->stream>>>(G, batch, out, n->gb[l]);
         HTRY(hipGetLastError());
         if (l == 0) break;
         // dH = G W_l : operands G (batch x out) and W_l^T (in x out), K = out; then ReLU mask of H_l

@@ -151,11 +151,13 @@ struct BatchInst {
     Vecs V;
 };
 
-// Two workgroups per CU (waves_per_eu 2): the one-workgroup engine is bound by
-// memory latency, and a second resident instance hides more of it than the
-// few registers spilled by the tighter budget cost.
+// Up to four workgroups per CU (waves_per_eu 4, as LDS allows): the
+// one-workgroup engine is bound by memory latency, and more resident
+// instances hide more of it than the registers spilled by the tighter budget
+// cost (the CG routine, where the time goes, is out of line and keeps its own
+// allocation).
 template <typename TV>
-__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_batch(
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) k_solve_batch(
     const BatchInst* __restrict__ insts, int count, Params S, Result* res, int* queue, int stage_doubles) {
     __shared__ Shared sh;
     __shared__ Desc d;

@@ -9,7 +9,8 @@ is resident in HBM before timing; outputs go to device buffers.
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (the persistent solve kernel) and the CPU oracle timed on a bounded sample.
 Further fields measure the other workloads on the same GPU: the same SOCP
-with the mixed-precision linear step, the stand-alone SpMV of the CG, 4096
+with the mixed-precision linear step and by plain relaxed DRS (no SuperMann
+steps), the stand-alone SpMV of the CG, 4096
 batched LASSO instances in one launch, the learned warm start against the
 cold-started method on the shared-A LASSO family, and iterations per second
 on the mixed PSD / exponential-cone instance.
@@ -219,6 +220,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-sdp", action="store_true", help="skip the PSD / exponential-cone leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain DRS leg")
     ap.add_argument("--sdp-iters", type=int, default=150,
                     help="iteration cap of the PSD / exponential-cone leg (a large cap times a complete solve)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -326,6 +328,19 @@ def main():
         out["mixed"] = {"solves_per_s": 1.0 / wm if im["status"] == sscs.SOLVED else 0.0, "iters": im["iters"],
                         "cg_iters": im["cg_iters"], "pr": im["pr"], "dr": im["dr"], "gap": im["gap"],
                         "dtype": "f32 operator in CG / f64 residuals, refinement, scalars"}
+    if not args.no_plain:
+        # the same workload by plain relaxed DRS (d = 0, K0 off: u <- u - 1.5 R u)
+        stp = bench_settings(sscs, 100000)
+        stp.direction, stp.c0 = "zero", 0.0
+        with sscs.Solver(prob, stp, stream=stream.cuda_stream) as sp_:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ip = sp_.solve(out=(x, y, s))[3]
+            torch.cuda.synchronize()
+            wp = time.perf_counter() - t0
+        out["plain_drs"] = {"solves_per_s": 1.0 / wp if ip["status"] == sscs.SOLVED else 0.0, "iters": ip["iters"],
+                            "cg_iters": ip["cg_iters"], "pr": ip["pr"], "dr": ip["dr"], "gap": ip["gap"],
+                            "method": "relaxed Douglas-Rachford (lambda 1.5) without SuperMann steps"}
     if not args.no_sdp:
         out["sdp_exp"] = sdp_exp_leg(sscs, G, args.sdp_iters)
     if not args.no_batched:

@@ -792,6 +792,22 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             write_trace(tm, V, nu, nRu, 0, 0);
             continue;
         }
+        if (S.direction == DIR_ZERO) {
+            // d = 0: the linear step of d is 0, every trial point is w = u with
+            // Rw = Ru and rho = ||Ru||^2, so the first trial is the K2 step
+            // u - lambda R u (the relaxed DRS / KM iteration of Sec. IV-A);
+            // taken directly, without the redundant linear step and projection
+            for (int e = tm.rank(); e < N; e += tm.size()) {
+                V.pz[e] = 0.0;
+                V.pxi[e] = 0.0;
+                V.u[e] -= S.lam * V.Ru[e];
+            }
+            ds.pend = 1;
+            ++k2c;
+            tm.sync();
+            write_trace(tm, V, nu, nRu, 2, 0);
+            continue;
+        }
         const double tau_d = linear_step<TV>(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc);
         double alpha = 1.0;
         int kind = 3, ls = 0;
@@ -836,6 +852,10 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
                 V.pz[e] = z;
                 V.pxi[e] = V.Rw[e] - V.Ru[e];
             }
+            // the next linear step solves for u + a d: by linearity (the same
+            // property the line search uses, Sec. IV-B) its CG starts from the
+            // sum of the two solutions already at hand
+            for (int j = tm.rank(); j < n; j += tm.size()) V.xw_u[j] += a * V.xw_d[j];
             ds.pend = 1;
             ++k1c;
         } else if (kind == 2) {

@@ -249,6 +249,17 @@ def test_small_socp_directions(sscs, direction, mem):
                                  cg_max=5000, record_trace=True))
 
 
+def test_plain_relaxed_drs(sscs):
+    """d = 0 with K0 off: every step is u - lambda R u (Sec. IV-A, equation
+    (drs) with relaxation), taken by the engine's direct path."""
+    prob = G.small_socp(2)
+    _, S = _oracle()
+    info, ref, _ = _compare_solve(sscs, prob, S.Settings(direction="zero", c0=0.0, lam=1.5, max_iters=30000),
+                                  sscs.Settings(direction="zero", c0=0.0, lam=1.5, max_iters=30000, cg_tol=1e-13,
+                                                cg_max=5000, record_trace=True))
+    assert info["k2"] == info["iters"] and info["k0"] == 0
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_certificates(sscs, seed):
     _, S = _oracle()

@@ -84,10 +84,10 @@ def cpu_baseline(prob, gpu_iters, budget_iters=60):
 def bench_settings(sscs, max_iters):
     """Anderson memory 5 (the workload's direction); relaxation 1.5, K1 factor
     0.9999 and safeguard decay 0.999 (Algorithm 1 inputs lambda, c1, q; the
-    paper leaves their values open); inexact CG with tolerance 0.1 ||Ru||/||u||
+    paper leaves their values open); inexact CG with tolerance 0.2 ||Ru||/||u||
     clamped to [1e-12, 1e-3]."""
     return sscs.Settings(direction="aa", mem=5, eps=1e-6, lam=1.5, c1=0.9999, q=0.999,
-                         cg_tol=1e-12, cg_adapt=0.1, cg_max=500, max_iters=max_iters,
+                         cg_tol=1e-12, cg_adapt=0.2, cg_max=500, max_iters=max_iters,
                          data_on_device=True)
 
 
@@ -300,7 +300,7 @@ def main():
         "config": {"workload": "sparse SOCP n=20000 m=50000 density 1e-3, zero 1000 + R+ 20000 + "
                                f"{len(prob.cone.q)} SOC (sizes 3..50), planted optimum, AA mem 5, eps 1e-6",
                    "settings": {"lambda": 1.5, "c1": 0.9999, "q": 0.999, "sigma": 0.01, "c0": 0.99,
-                                "cg_adapt": 0.1, "cg_tol": 1e-12},
+                                "cg_adapt": 0.2, "cg_tol": 1e-12},
                    "n": n, "m": m, "nnz": int(nnz), "parallelism": "single GPU"},
         "iterations_per_s": last["iters"] * value,
         "solve": {"iters": last["iters"], "cg_iters": last["cg_iters"], "k0": last["k0"], "k1": last["k1"],

@@ -185,7 +185,10 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
             tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
             const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
             if (round == 0 && pass == 0) thr = tol * tol * sh.out[3];
-            if (!(rr > thr)) {
+            // at least one step per solve: a warm start that already meets the
+            // tolerance would otherwise be returned as is, and its error would
+            // stay at the tolerance from one outer iteration to the next
+            if (!(rr > thr) && (it > 0 || round > 0)) {
                 done = pass == 0;            // the FP64 residual itself meets the tolerance
                 break;
             }
@@ -311,7 +314,7 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
             tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
             const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
             if (round == 0 && pass == 0) thr = tol * tol * sh.out[3];
-            if (!(rr > thr)) {
+            if (!(rr > thr) && (it > 0 || round > 0)) {   // at least one step, as in solve_M_staged
                 done = pass == 0;            // the FP64 residual itself meets the tolerance
                 break;
             }

@@ -39,7 +39,7 @@ def features(probs) -> np.ndarray:
 
 
 def solver_settings(**kw) -> S.Settings:
-    base = dict(direction="aa", mem=5, eps=1e-6, lam=1.5, c1=0.9999, q=0.999, cg_tol=1e-12, cg_adapt=0.1,
+    base = dict(direction="aa", mem=5, eps=1e-6, lam=1.5, c1=0.9999, q=0.999, cg_tol=1e-12, cg_adapt=0.2,
                 cg_max=500, max_iters=20000)
     base.update(kw)
     return S.Settings(**base)

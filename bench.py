@@ -54,6 +54,16 @@ def op_units(info):
     return info["cg_iters"] + 2 * linear_steps + iters
 
 
+def outer_vector_bytes(info, N, mem=5):
+    """N-vector passes of the outer iterations beyond the CG operator: the
+    projection / residual pass (5 N-vectors), the Anderson update (13 for
+    memory 5) at every iteration, and 5 per line-search trial (one trial per
+    iteration that is not K0, plus one per backtrack)."""
+    iters = info["iters"] + 1
+    trials = (info["iters"] - info["k0"]) + info["backtracks"]
+    return 8.0 * N * ((5 + 13 * mem / 5) * iters + 5 * trials)
+
+
 def cpu_baseline(prob, gpu_iters, budget_iters=60):
     """The oracle (FP64 direct factorisation) on a bounded sample: the
     factorisation plus `budget_iters` iterations of Algorithm 1, extrapolated
@@ -266,9 +276,11 @@ def main():
     solved = all(i["status"] == sscs.SOLVED for i in infos)
     ms_per_step = wall * 1e3 / args.steps
     value = args.steps / wall if solved else 0.0
-    # roofline of the solve kernel: CG-operator equivalents x bytes per operator
+    # roofline of the solve kernel: CG-operator equivalents x bytes per operator,
+    # plus the vector passes of the outer iterations
     units = np.mean([op_units(i) for i in infos])
-    bytes_per_launch = units * cg_op_bytes(nnz, m, n)
+    vec_bytes = float(np.mean([outer_vector_bytes(i, n + m + 1) for i in infos]))
+    bytes_per_launch = units * cg_op_bytes(nnz, m, n) + vec_bytes
     kernel_ms = ev_ms / args.steps
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     # stand-alone SpMV of the CG (same kernel code), device-resident, event-timed
@@ -309,7 +321,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_solve_grid", "kernel_ms": kernel_ms,
-                     "bytes_per_launch": bytes_per_launch, "cg_op_units": units},
+                     "bytes_per_launch": bytes_per_launch, "cg_op_units": units,
+                     "cg_op_bytes": cg_op_bytes(nnz, m, n), "outer_vector_bytes": vec_bytes},
         "spmv": {"A_us": ms_a * 1e3, "A_GBs": gbs_a, "At_us": ms_t * 1e3, "At_GBs": gbs_t,
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }

@@ -114,6 +114,12 @@ typedef struct {
     double  cg_adapt;             /* 0: every CG solve to cg_tol; > 0: inexact linear steps,
                                      CG tolerance cg_adapt * ||R u|| / ||u|| clamped to
                                      [cg_tol, 1e-3] (the first solve uses 1e-6) */
+    int32_t cg_d_match;           /* with cg_adapt > 0: 1 = the CG for the direction's
+                                     linear step (d~ of Sec. IV-B) stops at the same absolute
+                                     residual as that iteration's u~ solve, so the trial
+                                     points u~ + alpha d~ carry the error of u~ alone;
+                                     0 = at the relative tolerance of its own right-hand
+                                     side (a much tighter absolute accuracy) */
 } sscs_settings;
 
 /* Result of a solve. */
@@ -137,7 +143,7 @@ typedef struct sscs_batch sscs_batch;
 /* Fills *st with defaults: eps 1e-6, AA mem 5, c0 0.99 (0.1 is the paper's
  * advice for RB, Sec. IV-D-1), c1 0.99, q 0.99, sigma 0.01, lambda 1,
  * thetabar 0.1, ls_max 10, FP64, cg_tol 1e-10, cg_max 500, aa_reg 1e-12,
- * cg_adapt 0. */
+ * cg_adapt 0, cg_d_match 1. */
 int sscs_default_settings(sscs_settings *st);
 
 /* Validates and uploads (A, b, c, K), builds A^T and the per-instance

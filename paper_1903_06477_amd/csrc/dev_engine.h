@@ -59,6 +59,7 @@ struct Params {
     double eps, c0, c1, q, sigma, lam, thetabar, aa_reg;
     double cg_tol;
     double cg_adapt;        // > 0: CG tolerance cg_adapt ||R u|| / ||u||, within [cg_tol, 1e-3]
+    int cg_d_match;         // with cg_adapt > 0: d~'s CG stops at the absolute threshold of u~'s
     int direction, mem, ls_max, cg_max;
     long long max_iters;
     long long max_ticks;    // time limit in wall-clock ticks, <= 0: none
@@ -75,7 +76,10 @@ struct Result {
 // ------------------------------------------------------------------ linear step
 
 // out[0 .. n+m) = M^{-1} r[0 .. n+m), warm-starting CG from xw (updated in place).
-// Leaves h^T M^{-1} r in sh.out[0]; returns the CG iteration count.
+// Leaves h^T M^{-1} r in sh.out[0]; returns the CG iteration count.  CG stops
+// once ||K x - rhs||^2 <= thr, where thr = thr_abs if thr_abs > 0, else
+// tol^2 ||rhs||^2 (rhs = r_x - A^T r_y); the threshold used is stored to
+// *thr_used when given.
 //
 // The CG on K = I + A^T A (Jacobi preconditioner D) is the single-reduction
 // (Chronopoulos-Gear) recurrence: with u = D r and w = K u,
@@ -117,7 +121,7 @@ __device__ __forceinline__ int cg_rounds() {
 // solve_M.
 template <typename TV, typename Team>
 __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
-                              double* xw, double tol, int maxit) {
+                              double* xw, double tol, int maxit, double thr_abs, double* thr_used) {
     const int n = P.n, m = P.m;
     double* __restrict__ ul = tm.lu;
     double* __restrict__ tl = tm.lt;
@@ -184,7 +188,10 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
             if (round == 0 && pass == 0) put(sh, 3, a_bb);
             tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
             const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
-            if (round == 0 && pass == 0) thr = tol * tol * sh.out[3];
+            if (round == 0 && pass == 0) {
+                thr = thr_abs > 0.0 ? thr_abs : tol * tol * sh.out[3];
+                if (thr_used) *thr_used = thr;
+            }
             // at least one step per solve: a warm start that already meets the
             // tolerance would otherwise be returned as is, and its error would
             // stay at the tolerance from one outer iteration to the next
@@ -233,9 +240,9 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
 // independent of the rest of the solve kernel it is called from.
 template <typename TV, typename Team>
 __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
-                       double* xw, double tol, int maxit) {
+                       double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr) {
     if constexpr (Team::kBlock) {
-        if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit);
+        if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used);
     }
     const int n = P.n;
     const Csr<TV>& KA = op_mat<TV>(P, 0);
@@ -313,7 +320,10 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
             if (round == 0 && pass == 0) put(sh, 3, a_bb);
             tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
             const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
-            if (round == 0 && pass == 0) thr = tol * tol * sh.out[3];
+            if (round == 0 && pass == 0) {
+                thr = thr_abs > 0.0 ? thr_abs : tol * tol * sh.out[3];
+                if (thr_used) *thr_used = thr;
+            }
             if (!(rr > thr) && (it > 0 || round > 0)) {   // at least one step, as in solve_M_staged
                 done = pass == 0;            // the FP64 residual itself meets the tolerance
                 break;
@@ -359,8 +369,9 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
 // on the fly in its own pass, saving a barrier.  r and out must not alias.
 template <typename TV, typename Team>
 __device__ double linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
-                              double* xw, double tol, int maxit, long long* cg_iters) {
-    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit);
+                              double* xw, double tol, int maxit, long long* cg_iters, double thr_abs = 0.0,
+                              double* thr_used = nullptr) {
+    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used);
     return (r[P.N - 1] + sh.out[0]) / P.delta;
 }
 
@@ -757,8 +768,9 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     int status = 0;
     long long nu = 0;
     double tol = S.cg_adapt > 0.0 ? 1e-6 : S.cg_tol;
+    double thr_u = 0.0;                                // the u step's CG threshold (absolute)
     for (nu = 0;; ++nu) {
-        const double tau_u = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc);
+        const double tau_u = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc, 0.0, &thr_u);
         nRu = sqrt(residual_pass(tm, sh, P, V, tau_u));
         if (S.cg_adapt > 0.0) {
             // inexact linear steps: accuracy relative to the current fixed-point residual
@@ -811,7 +823,12 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             write_trace(tm, V, nu, nRu, 2, 0);
             continue;
         }
-        const double tau_d = linear_step<TV>(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc);
+        // inexact steps (cg_d_match): d~ to the same absolute accuracy as u~,
+        // since trial points combine them as u~ + alpha d~ (Sec. IV-B); a
+        // tolerance relative to d's own, much smaller, right-hand side solves
+        // d~ far more accurately than u~ is known
+        const double tau_d = linear_step<TV>(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc,
+                                             S.cg_adapt > 0.0 && S.cg_d_match ? thr_u : 0.0);
         double alpha = 1.0;
         int kind = 3, ls = 0;
         double coef = 0.0;

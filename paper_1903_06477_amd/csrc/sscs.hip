@@ -158,13 +158,17 @@ struct BatchInst {
 // allocation).
 template <typename TV>
 __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) k_solve_batch(
-    const BatchInst* __restrict__ insts, int count, Params S, Result* res, int* queue, int stage_doubles) {
+    const BatchInst* __restrict__ insts, const int* __restrict__ order, int count, Params S, Result* res, int* queue,
+    int stage_doubles) {
     __shared__ Shared sh;
     __shared__ Desc d;
     BlockTeam tm;
     if (threadIdx.x == 0) d.S = S;
     for (;;) {
-        if (threadIdx.x == 0) sh.qhead = atomicAdd(queue, 1);
+        if (threadIdx.x == 0) {
+            const int q = atomicAdd(queue, 1);
+            sh.qhead = q < count ? order[q] : count;
+        }
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(sh.qhead);
         __syncthreads();
@@ -383,6 +387,7 @@ int validate_settings(const sscs_settings* st) {
     if (st->c0 < 0 || st->c1 < 0 || st->q < 0 || st->q >= 1) return SSCS_E_INVALID;
     if (!(st->thetabar > 0 && st->thetabar < 1)) return SSCS_E_INVALID;
     if (!(st->cg_tol > 0) || !(st->cg_adapt >= 0)) return SSCS_E_INVALID;
+    if (st->cg_d_match != 0 && st->cg_d_match != 1) return SSCS_E_INVALID;
     if (st->precision != SSCS_PREC_FP64 && st->precision != SSCS_PREC_MIXED) return SSCS_E_INVALID;
     return SSCS_OK;
 }
@@ -399,6 +404,7 @@ Params make_params(const sscs_settings& st, double ticks_per_s) {
     p.aa_reg = st.aa_reg;
     p.cg_tol = st.cg_tol;
     p.cg_adapt = st.cg_adapt;
+    p.cg_d_match = st.cg_d_match;
     p.direction = st.direction;
     p.mem = st.mem;
     p.ls_max = st.ls_max;
@@ -878,6 +884,7 @@ int sscs_default_settings(sscs_settings* st) {
     st->record_trace = 0;
     st->aa_reg = 1e-12;
     st->cg_adapt = 0.0;
+    st->cg_d_match = 1;
     return SSCS_OK;
 }
 
@@ -1098,6 +1105,7 @@ struct sscs_batch {
     double* io = nullptr;        // staging: u0 (tot_u), x, y, s
     Result* res = nullptr;
     int* queue = nullptr;
+    int* order = nullptr;        // queue position -> instance, most work per iteration first
     int grid = 1;
     int stage = 0;               // dynamic LDS of k_solve_batch, in doubles
     double ticks_per_s = 1e8;
@@ -1115,7 +1123,7 @@ int sscs_batch_destroy(sscs_batch* bt) {
     if (bt->stream) hipStreamSynchronize(bt->stream);
     else hipDeviceSynchronize();
     for (auto& I : bt->inst) free_instance(I);
-    hipFree(bt->vecbuf); hipFree(bt->d_insts); hipFree(bt->io); hipFree(bt->res); hipFree(bt->queue);
+    hipFree(bt->vecbuf); hipFree(bt->d_insts); hipFree(bt->io); hipFree(bt->res); hipFree(bt->queue); hipFree(bt->order);
     delete bt;
     return SSCS_OK;
 }
@@ -1160,6 +1168,7 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
         if (r == SSCS_OK) r = dmalloc(&bt->io, bt->tot_u + bt->tot_x + 2 * bt->tot_y);
         if (r == SSCS_OK) r = dmalloc(&bt->res, count);
         if (r == SSCS_OK) r = dmalloc(&bt->queue, 1);
+        if (r == SSCS_OK) r = dmalloc(&bt->order, count);
         if (r == SSCS_OK) r = dmalloc(&bt->d_insts, count);
         // PSD scratch: one workgroup owns an instance at a time, so each instance
         // with PSD blocks gets its own (the batched engine allows orders <= 64)
@@ -1181,6 +1190,17 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
             }
             hipError_t e = hipMemcpyAsync(bt->d_insts, bt->h_insts.data(), count * sizeof(BatchInst),
                                           hipMemcpyHostToDevice, bt->stream);
+            if (e != hipSuccess) { g_last_hip = hipGetErrorString(e); r = SSCS_E_HIP; }
+        }
+        if (r == SSCS_OK) {
+            // workgroups take instances in decreasing work per iteration (nonzeros
+            // of A plus n + m; ties in index order), so the large instances start
+            // first and the end of the launch is not held up by one of them
+            std::vector<int> ord(count);
+            for (int i = 0; i < count; ++i) ord[i] = i;
+            auto cost = [&](int i) { return (long long)bt->inst[i].nnz + bt->inst[i].n + bt->inst[i].m; };
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost(a) > cost(b); });
+            hipError_t e = hipMemcpy(bt->order, ord.data(), count * sizeof(int), hipMemcpyHostToDevice);
             if (e != hipSuccess) { g_last_hip = hipGetErrorString(e); r = SSCS_E_HIP; }
         }
         if (r == SSCS_OK) {
@@ -1255,8 +1275,8 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
     HIP_TRY(hipMemsetAsync(bt->queue, 0, sizeof(int), bt->stream));
     Params S = make_params(bt->st, bt->ticks_per_s);
     const size_t lds = bt->stage * sizeof(double);
-    k_solve_batch<double><<<bt->grid, kBatchBlock, lds, bt->stream>>>(bt->d_insts, bt->count, S, bt->res,
-                                                                      bt->queue, bt->stage);
+    k_solve_batch<double><<<bt->grid, kBatchBlock, lds, bt->stream>>>(bt->d_insts, bt->order, bt->count, S,
+                                                                      bt->res, bt->queue, bt->stage);
     HIP_TRY(hipGetLastError());
     if (!dev) {
         HIP_TRY(hipMemcpyAsync(x_packed, dio_x, bt->tot_x * sizeof(double), hipMemcpyDeviceToHost, bt->stream));

@@ -44,7 +44,7 @@ class _Settings(ctypes.Structure):
                 ("ls_max", ctypes.c_int32), ("max_iters", ctypes.c_int64), ("max_time_s", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double), ("cg_max", ctypes.c_int32),
                 ("data_on_device", ctypes.c_int32), ("record_trace", ctypes.c_int32),
-                ("aa_reg", ctypes.c_double), ("cg_adapt", ctypes.c_double)]
+                ("aa_reg", ctypes.c_double), ("cg_adapt", ctypes.c_double), ("cg_d_match", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -130,6 +130,7 @@ class Settings:
     record_trace: bool = False
     aa_reg: float = 1e-12
     cg_adapt: float = 0.0
+    cg_d_match: bool = True
 
     def to_c(self) -> _Settings:
         st = _Settings()
@@ -148,6 +149,7 @@ class Settings:
         st.record_trace = int(self.record_trace)
         st.aa_reg = self.aa_reg
         st.cg_adapt = self.cg_adapt
+        st.cg_d_match = int(self.cg_d_match)
         return st
 
 

@@ -44,6 +44,7 @@ struct Prob {
 struct Vecs {
     double *u, *ut, *ub, *Ru, *d, *dt, *Rw, *pz, *pxi;   // length N
     double *xw_u, *xw_d;                                 // CG warm starts, length n
+    double *q_u, *q_d;                                   // K xw_u, K xw_d as the CG left them, length n
     double *cg_b, *cg_u, *cg_w, *cg_p, *cg_r, *cg_s;     // length n
     double *cg_g[2];                                     // 4 n each: gathered (D r, D s, D w, -) per column
     double *cg_t;                                        // length m
@@ -240,39 +241,53 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
 // independent of the rest of the solve kernel it is called from.
 template <typename TV, typename Team>
 __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
-                       double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr) {
+                       double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr,
+                       double* q = nullptr, bool refresh = true) {
     if constexpr (Team::kBlock) {
         if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used);
     }
     const int n = P.n;
     const Csr<TV>& KA = op_mat<TV>(P, 0);
     const Csr<TV>& KAt = op_mat<TV>(P, 1);
+    // q (optional, FP64 operator only) holds K xw as the previous solve's
+    // recurrence left it (K x = rhs - r): then r0 = rhs - q needs no product,
+    // which saves two products and a barrier per solve.  The recurrence
+    // residual drifts from the true one by rounding only; refresh recomputes
+    // r0 from scratch.
+    constexpr bool kQ = std::is_same<TV, double>::value;
+    if constexpr (!kQ) q = nullptr;
+    const bool use_q = q != nullptr && !refresh;
+    int cur = 0;
+    auto start = [&](int j, double rj) {          // r0 = rj; u = w = p = s = 0; record (D r0, 0, 0)
+        V.cg_r[j] = rj;
+        V.cg_s[j] = 0.0;
+        V.cg_u[j] = 0.0;
+        V.cg_w[j] = 0.0;
+        V.cg_p[j] = 0.0;
+        double* g = V.cg_g[cur] + 4 * (size_t)j;
+        g[0] = P.dinv[j] * rj;
+        g[1] = 0.0;
+        g[2] = 0.0;
+    };
     // rhs = rx - A^T ry
     double a_bb = 0.0;
     spmv_part<1>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; }, [&](int j, double s) {
         const double bj = r[j] - s;
         V.cg_b[j] = bj;
         a_bb += bj * bj;
+        if (use_q) start(j, bj - q[j]);
     });
     double thr = 0.0;
-    int it = 0, cur = 0;
+    int it = 0;
     const int rounds = cg_rounds<TV>();
     for (int round = 0; round < rounds; ++round) {
-        // t = A xw ; r0 = rhs - (xw + A^T t) in FP64; u = w = p = s = 0; record (D r0, 0, 0)
-        spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
-        tm.sync();
-        spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; }, [&](int j, double s) {
-            const double rj = V.cg_b[j] - (xw[j] + s);
-            V.cg_r[j] = rj;
-            V.cg_s[j] = 0.0;
-            V.cg_u[j] = 0.0;
-            V.cg_w[j] = 0.0;
-            V.cg_p[j] = 0.0;
-            double* g = V.cg_g[cur] + 4 * (size_t)j;
-            g[0] = P.dinv[j] * rj;
-            g[1] = 0.0;
-            g[2] = 0.0;
-        });
+        if (!(use_q && round == 0)) {
+            // t = A xw ; r0 = rhs - (xw + A^T t) in FP64
+            spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
+            tm.sync();
+            spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; },
+                         [&](int j, double s) { start(j, V.cg_b[j] - (xw[j] + s)); });
+        }
         tm.sync();
         double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0;
         bool done = false;
@@ -357,6 +372,7 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
     for (int j = tm.rank(); j < n; j += tm.size()) {
         out[j] = xw[j];
         a_hp += P.c[j] * xw[j];
+        if (q) q[j] = V.cg_b[j] - V.cg_r[j];
     }
     put(sh, 0, a_hp);
     tm.reduce(sh, 1);
@@ -370,8 +386,8 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
 template <typename TV, typename Team>
 __device__ double linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                               double* xw, double tol, int maxit, long long* cg_iters, double thr_abs = 0.0,
-                              double* thr_used = nullptr) {
-    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used);
+                              double* thr_used = nullptr, double* q = nullptr, bool refresh = true) {
+    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used, q, refresh);
     return (r[P.N - 1] + sh.out[0]) / P.delta;
 }
 
@@ -758,7 +774,17 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     const long long t_start = wall_clock64();
     for (int i = tm.rank(); i < N; i += tm.size())
         V.u[i] = V.u0 ? V.u0[i] : (i == N - 1 ? 1.0 : 0.0);
-    for (int j = tm.rank(); j < n; j += tm.size()) { V.xw_u[j] = 0.0; V.xw_d[j] = 0.0; }
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        V.xw_u[j] = 0.0;
+        V.xw_d[j] = 0.0;
+        V.q_u[j] = 0.0;
+        V.q_d[j] = 0.0;
+    }
+    // grid teams start CG from the stored K xw (saving two products and a
+    // barrier per linear step), recomputing the true residual every 64th
+    // iteration and always when the solves are exact
+    double* const qu = Team::kBlock ? nullptr : V.q_u;
+    double* const qd = Team::kBlock ? nullptr : V.q_d;
     tm.sync();
     DirState ds = {0, 0, 0, 0};
     double eta0 = 0.0, eta = 0.0, r_safe = 0.0;
@@ -770,7 +796,9 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     double tol = S.cg_adapt > 0.0 ? 1e-6 : S.cg_tol;
     double thr_u = 0.0;                                // the u step's CG threshold (absolute)
     for (nu = 0;; ++nu) {
-        const double tau_u = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc, 0.0, &thr_u);
+        const bool refresh = !(S.cg_adapt > 0.0) || nu % 64 == 0;
+        const double tau_u = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc, 0.0, &thr_u, qu,
+                                             refresh);
         nRu = sqrt(residual_pass(tm, sh, P, V, tau_u));
         if (S.cg_adapt > 0.0) {
             // inexact linear steps: accuracy relative to the current fixed-point residual
@@ -828,7 +856,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         // tolerance relative to d's own, much smaller, right-hand side solves
         // d~ far more accurately than u~ is known
         const double tau_d = linear_step<TV>(tm, sh, P, V, V.d, V.dt, V.xw_d, tol, S.cg_max, &cgc,
-                                             S.cg_adapt > 0.0 && S.cg_d_match ? thr_u : 0.0);
+                                             S.cg_adapt > 0.0 && S.cg_d_match ? thr_u : 0.0, nullptr, qd, refresh);
         double alpha = 1.0;
         int kind = 3, ls = 0;
         double coef = 0.0;
@@ -875,7 +903,10 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             // the next linear step solves for u + a d: by linearity (the same
             // property the line search uses, Sec. IV-B) its CG starts from the
             // sum of the two solutions already at hand
-            for (int j = tm.rank(); j < n; j += tm.size()) V.xw_u[j] += a * V.xw_d[j];
+            for (int j = tm.rank(); j < n; j += tm.size()) {
+                V.xw_u[j] += a * V.xw_d[j];
+                if (qu) qu[j] += a * qd[j];
+            }
             ds.pend = 1;
             ++k1c;
         } else if (kind == 2) {

@@ -590,7 +590,7 @@ Prob make_prob(const Inst& I) {
 
 size_t vec_doubles(int n, int m, int mem) {
     const size_t N = (size_t)n + m + 1;
-    return 9 * N + 16 * (size_t)n + (size_t)m + 2 * (size_t)mem * N + 8;
+    return 9 * N + 18 * (size_t)n + (size_t)m + 2 * (size_t)mem * N + 8;
 }
 
 // Carves the Vecs of one instance from a contiguous device buffer.
@@ -602,6 +602,7 @@ Vecs carve(double* base, int n, int m, int mem) {
     V.u = take(N); V.ut = take(N); V.ub = take(N); V.Ru = take(N); V.d = take(N);
     V.dt = take(N); V.Rw = take(N); V.pz = take(N); V.pxi = take(N);
     V.xw_u = take(n); V.xw_d = take(n);
+    V.q_u = take(n); V.q_d = take(n);
     V.cg_b = take(n); V.cg_u = take(n); V.cg_w = take(n); V.cg_p = take(n);
     V.cg_r = take(n); V.cg_s = take(n);
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 31) & ~uintptr_t(31));   // 32-byte records

@@ -118,16 +118,30 @@ __device__ __forceinline__ int cg_rounds() {
 // One-workgroup form of solve_M: the workgroup owns every row, so the vectors
 // the two products gather from (u for A, t for A^T) live in LDS and the
 // column records are not needed; each iteration is: update and store u in
-// LDS | t = A u into LDS | w = u + A^T t and the dots.  Same recurrence as
-// solve_M.
+// LDS, reduce ||r||^2 | t = A u into LDS | w = u + A^T t and the dots.  Same
+// recurrence as solve_M; since a workgroup barrier is cheap, the stopping
+// test runs right after the update, before the product the next step would
+// need (solve_M folds it into the dots' reduction to save a grid barrier, at
+// the price of one product more per solve).  q and refresh as in solve_M.
 template <typename TV, typename Team>
 __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
-                              double* xw, double tol, int maxit, double thr_abs, double* thr_used) {
+                              double* xw, double tol, int maxit, double thr_abs, double* thr_used, double* q,
+                              bool refresh) {
     const int n = P.n, m = P.m;
     double* __restrict__ ul = tm.lu;
     double* __restrict__ tl = tm.lt;
     const Csr<TV>& KA = op_mat<TV>(P, 0);
     const Csr<TV>& KAt = op_mat<TV>(P, 1);
+    constexpr bool kQ = std::is_same<TV, double>::value;
+    if constexpr (!kQ) q = nullptr;
+    const bool use_q = q != nullptr && !refresh;
+    auto start = [&](int j, double rj) {          // r0 = rj; p = s = w = 0
+        V.cg_r[j] = rj;
+        V.cg_s[j] = 0.0;
+        V.cg_u[j] = 0.0;
+        V.cg_w[j] = 0.0;
+        V.cg_p[j] = 0.0;
+    };
     for (int i = tm.rank(); i < m; i += tm.size()) tl[i] = r[n + i];
     tm.sync();
     // rhs = rx - A^T ry
@@ -136,28 +150,26 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
         const double bj = r[j] - s;
         V.cg_b[j] = bj;
         a_bb += bj * bj;
+        if (use_q) start(j, bj - q[j]);
     });
     double thr = 0.0;
     int it = 0;
     const int rounds = cg_rounds<TV>();
     for (int round = 0; round < rounds; ++round) {
-        // r0 = rhs - (xw + A^T A xw) in FP64; p = s = w = 0
-        for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
-        tm.sync();
-        spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) { tl[i] = s; });
-        tm.sync();
-        spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
-            const double rj = V.cg_b[j] - (xw[j] + s);
-            V.cg_r[j] = rj;
-            V.cg_s[j] = 0.0;
-            V.cg_u[j] = 0.0;
-            V.cg_w[j] = 0.0;
-            V.cg_p[j] = 0.0;
-        });
+        if (!(use_q && round == 0)) {
+            // r0 = rhs - (xw + A^T A xw) in FP64
+            for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
+            tm.sync();
+            spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) { tl[i] = s; });
+            tm.sync();
+            spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; },
+                         [&](int j, double s) { start(j, V.cg_b[j] - (xw[j] + s)); });
+        }
         tm.sync();
         double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0;
         bool done = false;
         for (int pass = 0;; ++pass) {
+            double a_rr = 0.0;
             for (int j = tm.rank(); j < n; j += tm.size()) {
                 const double pj = V.cg_u[j] + beta * V.cg_p[j];
                 const double sj = V.cg_w[j] + beta * V.cg_s[j];
@@ -169,28 +181,14 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
                 V.cg_r[j] = rj;
                 V.cg_u[j] = uj;
                 ul[j] = uj;
-            }
-            tm.sync();
-            spmv_part<4>(tm, KA, 0, [&](int c) { return ul[c]; }, [&](int i, double acc) { tl[i] = acc; });
-            tm.sync();
-            double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
-            spmv_part<4>(tm, KAt, 1, [&](int c) { return tl[c]; }, [&](int j, double s) {
-                const double uj = V.cg_u[j];
-                const double rj = V.cg_r[j];
-                const double wj = uj + s;
-                V.cg_w[j] = wj;
-                a_g += rj * uj;
-                a_d += wj * uj;
                 a_rr += rj * rj;
-            });
-            put(sh, 0, a_g);
-            put(sh, 1, a_d);
-            put(sh, 2, a_rr);
-            if (round == 0 && pass == 0) put(sh, 3, a_bb);
-            tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
-            const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
+            }
+            put(sh, 0, a_rr);
+            if (round == 0 && pass == 0) put(sh, 1, a_bb);
+            tm.reduce(sh, (round == 0 && pass == 0) ? 2 : 1);
+            const double rr = sh.out[0];
             if (round == 0 && pass == 0) {
-                thr = thr_abs > 0.0 ? thr_abs : tol * tol * sh.out[3];
+                thr = thr_abs > 0.0 ? thr_abs : tol * tol * sh.out[1];
                 if (thr_used) *thr_used = thr;
             }
             // at least one step per solve: a warm start that already meets the
@@ -204,6 +202,21 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
                 done = true;
                 break;
             }
+            spmv_part<4>(tm, KA, 0, [&](int c) { return ul[c]; }, [&](int i, double acc) { tl[i] = acc; });
+            tm.sync();
+            double a_g = 0.0, a_d = 0.0;
+            spmv_part<4>(tm, KAt, 1, [&](int c) { return tl[c]; }, [&](int j, double s) {
+                const double uj = V.cg_u[j];
+                const double rj = V.cg_r[j];
+                const double wj = uj + s;
+                V.cg_w[j] = wj;
+                a_g += rj * uj;
+                a_d += wj * uj;
+            });
+            put(sh, 0, a_g);
+            put(sh, 1, a_d);
+            tm.reduce(sh, 2);
+            const double gamma = sh.out[0], delta = sh.out[1];
             double den = delta;
             if (pass == 0) {
                 beta = 0.0;
@@ -231,6 +244,7 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
     for (int j = tm.rank(); j < n; j += tm.size()) {
         out[j] = xw[j];
         a_hp += P.c[j] * xw[j];
+        if (q) q[j] = V.cg_b[j] - V.cg_r[j];
     }
     put(sh, 0, a_hp);
     tm.reduce(sh, 1);
@@ -244,7 +258,7 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
                        double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr,
                        double* q = nullptr, bool refresh = true) {
     if constexpr (Team::kBlock) {
-        if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used);
+        if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used, q, refresh);
     }
     const int n = P.n;
     const Csr<TV>& KA = op_mat<TV>(P, 0);
@@ -780,11 +794,11 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         V.q_u[j] = 0.0;
         V.q_d[j] = 0.0;
     }
-    // grid teams start CG from the stored K xw (saving two products and a
-    // barrier per linear step), recomputing the true residual every 64th
-    // iteration and always when the solves are exact
-    double* const qu = Team::kBlock ? nullptr : V.q_u;
-    double* const qd = Team::kBlock ? nullptr : V.q_d;
+    // CG starts from the stored K xw (saving two products per linear step),
+    // recomputing the true residual every 64th iteration and always when the
+    // solves are exact
+    double* const qu = V.q_u;
+    double* const qd = V.q_d;
     tm.sync();
     DirState ds = {0, 0, 0, 0};
     double eta0 = 0.0, eta = 0.0, r_safe = 0.0;
@@ -905,7 +919,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             // sum of the two solutions already at hand
             for (int j = tm.rank(); j < n; j += tm.size()) {
                 V.xw_u[j] += a * V.xw_d[j];
-                if (qu) qu[j] += a * qd[j];
+                qu[j] += a * qd[j];
             }
             ds.pend = 1;
             ++k1c;

@@ -338,3 +338,67 @@ def test_lasso_batch_matches_oracle_and_single(sscs):
     xa, ya, sa, ia = alone.solve()
     assert ia[0]["iters"] == infos[2]["iters"]
     np.testing.assert_array_equal(xa, parts[2][0])
+
+
+# The inexact-mode tests solve to eps = 1e-8 on both sides: their trajectories
+# differ from the oracle's, and two solutions that each just meet eps = 1e-6
+# may differ in objective by more than 1e-5 relative.
+EPS_INEXACT = 1e-8
+
+
+def _inexact_settings(sscs, match=True):
+    return sscs.Settings(direction="aa", mem=5, eps=EPS_INEXACT, lam=1.5, c1=0.9999, q=0.999, cg_tol=1e-12,
+                         cg_adapt=0.2, cg_d_match=match, cg_max=2000, max_iters=20000)
+
+
+@pytest.mark.parametrize("engine", ["grid", "block"])
+@pytest.mark.parametrize("match", [True, False])
+def test_inexact_linear_steps(sscs, engine, match):
+    """Inexact CG (tolerance 0.2 ||Ru||/||u||, d~ to u~'s absolute accuracy or
+    to its own relative one), started from the carried K xw with periodic
+    recomputation: the same solution as the oracle's exact solve, checked on
+    the host (pr/dr/gap <= eps = 1e-8, objective within 1e-5)."""
+    import os
+    _, S = _oracle()
+    old = os.environ.get("SSCS_GRID")
+    try:
+        if engine == "block":
+            os.environ["SSCS_GRID"] = "1"
+        else:
+            os.environ.pop("SSCS_GRID", None)
+        for prob in [G.config1_lp(), G.small_socp(2), G.small_socp(5)]:
+            print(f"inexact {engine} match={match} {prob.name or 'socp'} n={prob.n} m={prob.m}", flush=True)
+            ref = S.solve(prob, S.Settings(direction="aa", mem=5, eps=EPS_INEXACT, max_iters=20000))
+            with sscs.Solver(prob, _inexact_settings(sscs, match)) as s:
+                x, y, sv, info = s.solve()
+            assert info["status"] == sscs.SOLVED == ref.status
+            assert max(kkt_measures(prob, x, y, sv)) <= EPS_INEXACT * 1.0001
+            assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
+    finally:
+        if old is None:
+            os.environ.pop("SSCS_GRID", None)
+        else:
+            os.environ["SSCS_GRID"] = old
+
+
+def test_inexact_linear_steps_batch(sscs):
+    """The batched engine's one-workgroup CG in inexact mode (carried K xw,
+    stopping test before the next product) against the oracle, and batch
+    invariance in that mode."""
+    _, S = _oracle()
+    probs = [G.config4_instance(i) for i in range(8)]
+    st = _inexact_settings(sscs)
+    bs = sscs.BatchSolver(probs, st)
+    x, y, sv, infos = bs.solve()
+    parts = bs.split(x, y, sv)
+    for i, p in enumerate(probs):
+        ref = S.solve(p, S.Settings(direction="aa", mem=5, eps=EPS_INEXACT, max_iters=20000))
+        assert infos[i]["status"] == ref.status == S.SOLVED
+        assert max(kkt_measures(p, *parts[i])) <= EPS_INEXACT * 1.0001
+        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
+    bs.close()
+    alone = sscs.BatchSolver([probs[3]], st)
+    xa, _, _, ia = alone.solve()
+    alone.close()
+    assert ia[0]["iters"] == infos[3]["iters"]
+    np.testing.assert_array_equal(xa, parts[3][0])

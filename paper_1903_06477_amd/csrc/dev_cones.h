@@ -461,15 +461,17 @@ __device__ __forceinline__ int psd_tile_owner(int ntt, int round, int t, int& si
     return 0;
 }
 
-// Diagonalises the 2-tile submatrix of `mat` for tile pair (t1, t2) in LDS
-// and writes Q (slot x slot, row-major) to q.  One workgroup.
-__device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, const double* mat, double* q, PsdRound& R) {
+// Diagonalises the 2-tile submatrix for tile pair (t1, t2) in LDS and writes
+// Q (slot x slot, row-major) to q; entry (i, j) of the matrix is at(i, j).
+// One workgroup.
+template <typename At>
+__device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q, PsdRound& R) {
     PsdSub& L = psd_sub_lds();
     const int t = threadIdx.x, n = blockDim.x;
     for (int e = t; e < kPsdSub * kPsdSub; e += n) {
         const int a = e / kPsdSub, b = e % kPsdSub;
         const int ga = psd_slot_index(k, nt, t1, t2, a), gb = psd_slot_index(k, nt, t1, t2, b);
-        L.S[a][b] = (ga >= 0 && gb >= 0) ? mat[(size_t)ga * k + gb] : 0.0;
+        L.S[a][b] = (ga >= 0 && gb >= 0) ? at(ga, gb) : 0.0;
         L.Q[a][b] = a == b ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -538,7 +540,12 @@ __device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, const d
 
 // `buf` holds 4 k*k doubles (matrix, its turned copy, Vt and its turned copy);
 // `in` (packed input, filled by the caller) and `outv` are contiguous, with
-// room for the rounds' Q matrices (k (k + 1) doubles in all, k > 2 kPsdTile).
+// room for two rounds' Q matrices (k (k + 1) doubles in all, k > 2 kPsdTile).
+// A round is: (1) each tile pair's submatrix diagonalised by one workgroup,
+// (2) the pairs' block rows of the matrix and of Vt turned, (3) the block
+// columns turned.  Step (1) of the next round builds its submatrices from the
+// output of (2) and this round's Q directly, so it runs alongside (3): two
+// grid barriers per round.
 template <typename Team>
 __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, double* buf, double* in, double* outv, double* V0,
                                  int* warm) {
@@ -548,7 +555,7 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     double* tmp = buf + (size_t)k * k;
     double* vm = tmp + (size_t)k * k;
     double* vm2 = vm + (size_t)k * k;
-    double* qb = in;                                   // Q of every pair of a round (after the unpack)
+    double* qbuf[2] = {in, in + (size_t)((k / kPsdTile + 2) / 2) * kPsdSub * kPsdSub};   // Q of two rounds
     for (int idx = r0; idx < k * (k + 1) / 2; idx += R_) {
         int i, j;
         psd_unpack_index(k, idx, i, j);
@@ -601,22 +608,40 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
         const double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
         if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
         prev = cur;
+        // (1) for round 0, from the matrix itself
+        for (int h = tm.blk(); h < np; h += tm.nblk()) {
+            int t1, t2;
+            psd_tile_pair(ntt, 0, h, t1, t2);
+            psd_sub_diag(k, nt, t1, t2, [&](int i, int j) { return mat[(size_t)i * k + j]; },
+                         qbuf[0] + (size_t)h * kPsdSub * kPsdSub, R);
+        }
+        tm.sync();
         for (int round = 0; round < ntt - 1; ++round) {
-            // 1. each pair's submatrix diagonalised by one workgroup
-            for (int h = tm.blk(); h < np; h += tm.nblk()) {
+            const double* qr = qbuf[round & 1];
+            // entry (i, c) of tmp Q for this round's pairs
+            auto turned = [&](int i, int c) {
+                int side;
+                const int h = psd_tile_owner(ntt, round, c / kPsdTile, side);
                 int t1, t2;
                 psd_tile_pair(ntt, round, h, t1, t2);
-                psd_sub_diag(k, nt, t1, t2, mat, qb + (size_t)h * kPsdSub * kPsdSub, R);
-            }
-            tm.sync();
-            // 2. tmp = Q^T A and vm2 = Q^T Vt on the rows of each pair
+                const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
+                const int cp = side * kPsdTile + c % kPsdTile;
+                double s_ = 0.0;
+                for (int b = 0; b < kPsdSub; ++b) {
+                    const int gb = psd_slot_index(k, nt, t1, t2, b);
+                    if (gb < 0) continue;
+                    s_ += tmp[(size_t)i * k + gb] * q[b * kPsdSub + cp];
+                }
+                return s_;
+            };
+            // (2) tmp = Q^T A and vm2 = Q^T Vt on the rows of each pair
             for (int idx = r0; idx < k * k; idx += R_) {
                 const int r = idx / k, j = idx - (idx / k) * k;
                 int side;
                 const int h = psd_tile_owner(ntt, round, r / kPsdTile, side);
                 int t1, t2;
                 psd_tile_pair(ntt, round, h, t1, t2);
-                const double* q = qb + (size_t)h * kPsdSub * kPsdSub;
+                const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
                 const int ip = side * kPsdTile + r % kPsdTile;
                 double sa = 0.0, sv = 0.0;
                 for (int a = 0; a < kPsdSub; ++a) {
@@ -630,22 +655,15 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
                 vm2[idx] = sv;
             }
             tm.sync();
-            // 3. mat = tmp Q on the columns of each pair
-            for (int idx = r0; idx < k * k; idx += R_) {
-                const int i = idx / k, c = idx - (idx / k) * k;
-                int side;
-                const int h = psd_tile_owner(ntt, round, c / kPsdTile, side);
-                int t1, t2;
-                psd_tile_pair(ntt, round, h, t1, t2);
-                const double* q = qb + (size_t)h * kPsdSub * kPsdSub;
-                const int cp = side * kPsdTile + c % kPsdTile;
-                double s_ = 0.0;
-                for (int b = 0; b < kPsdSub; ++b) {
-                    const int gb = psd_slot_index(k, nt, t1, t2, b);
-                    if (gb < 0) continue;
-                    s_ += tmp[(size_t)i * k + gb] * q[b * kPsdSub + cp];
+            // (3) mat = tmp Q on the columns of each pair, and (1) of the next
+            // round from the same products (reads tmp and this round's Q only)
+            for (int idx = r0; idx < k * k; idx += R_) mat[idx] = turned(idx / k, idx - (idx / k) * k);
+            if (round + 1 < ntt - 1) {
+                for (int h = tm.blk(); h < np; h += tm.nblk()) {
+                    int t1, t2;
+                    psd_tile_pair(ntt, round + 1, h, t1, t2);
+                    psd_sub_diag(k, nt, t1, t2, turned, qbuf[(round + 1) & 1] + (size_t)h * kPsdSub * kPsdSub, R);
                 }
-                mat[idx] = s_;
             }
             double* sw = vm;
             vm = vm2;

@@ -461,11 +461,22 @@ __device__ __forceinline__ int psd_tile_owner(int ntt, int round, int t, int& si
     return 0;
 }
 
+// Orders LDS accesses between the lanes of one wavefront (a wavefront runs in
+// lockstep and its LDS operations complete in issue order; the fences keep
+// the compiler from moving accesses across this point).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Diagonalises the 2-tile submatrix for tile pair (t1, t2) in LDS and writes
 // Q (slot x slot, row-major) to q; entry (i, j) of the matrix is at(i, j).
-// One workgroup.
+// Called by a whole workgroup: all threads load, the cyclic Jacobi sweeps run
+// on the first wavefront alone (eight rotations of a round, parameters passed
+// by lane shuffles, wavefront-level ordering instead of workgroup barriers).
 template <typename At>
-__device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q, PsdRound& R) {
+__device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
     PsdSub& L = psd_sub_lds();
     const int t = threadIdx.x, n = blockDim.x;
     for (int e = t; e < kPsdSub * kPsdSub; e += n) {
@@ -475,65 +486,75 @@ __device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, 
         L.Q[a][b] = a == b ? 1.0 : 0.0;
     }
     __syncthreads();
-    const double tol2 = (1e-16 * kPsdSub) * (1e-16 * kPsdSub);
-    double prev = 1.0;
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        if (t == 0) {
+    if (t < WAVE) {
+        constexpr int kHalf = kPsdSub / 2;
+        constexpr int kPer = kHalf * kPsdSub / WAVE;            // (pair, index) items per lane
+        const double tol2 = (1e-16 * kPsdSub) * (1e-16 * kPsdSub);
+        double prev = 1.0;
+        for (int sweep = 0; sweep < 30; ++sweep) {
             double off = 0.0, tot = 0.0;
-            for (int a = 0; a < kPsdSub; ++a)
-                for (int b = 0; b < kPsdSub; ++b) {
-                    const double v = L.S[a][b] * L.S[a][b];
-                    tot += v;
-                    if (a != b) off += v;
-                }
-            R.offn = tot > 0.0 ? off / tot : 0.0;
-        }
-        __syncthreads();
-        const double cur = R.offn;
-        if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
-        prev = cur;
-        for (int round = 0; round < kPsdSub - 1; ++round) {
-            for (int h = t; h < kPsdSub / 2; h += n) {
-                int p, qq;
-                psd_tile_pair(kPsdSub, round, h, p, qq);
+            for (int e = t; e < kPsdSub * kPsdSub; e += WAVE) {
+                const double v = L.S[e / kPsdSub][e % kPsdSub] * L.S[e / kPsdSub][e % kPsdSub];
+                tot += v;
+                if (e / kPsdSub != e % kPsdSub) off += v;
+            }
+            off = wave_sum(off);
+            tot = wave_sum(tot);
+            const double cur = tot > 0.0 ? off / tot : 0.0;
+            if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
+            prev = cur;
+            for (int round = 0; round < kPsdSub - 1; ++round) {
+                // lane h < kHalf: rotation of pair h
+                int p = 0, qq = 0;
                 double c = 1.0, s_ = 0.0;
-                const double apq = L.S[p][qq];
-                if (apq != 0.0 && fabs(apq) > 2.2e-16 * sqrt(fabs(L.S[p][p] * L.S[qq][qq]))) {
-                    const double tau = (L.S[qq][qq] - L.S[p][p]) / (2.0 * apq);
-                    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    s_ = tt * c;
+                if (t < kHalf) {
+                    psd_tile_pair(kPsdSub, round, t, p, qq);
+                    const double apq = L.S[p][qq];
+                    if (apq != 0.0 && fabs(apq) > 2.2e-16 * sqrt(fabs(L.S[p][p] * L.S[qq][qq]))) {
+                        const double tau = (L.S[qq][qq] - L.S[p][p]) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        s_ = tt * c;
+                    }
                 }
-                R.pp[h] = p; R.qq[h] = qq; R.cs[h] = c; R.sn[h] = s_;
+                int ph[kPer], qh[kPer];
+                double ch[kPer], sh_[kPer];
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    const int h = (t + r * WAVE) / kPsdSub;
+                    ph[r] = __shfl(p, h, WAVE);
+                    qh[r] = __shfl(qq, h, WAVE);
+                    ch[r] = __shfl(c, h, WAVE);
+                    sh_[r] = __shfl(s_, h, WAVE);
+                }
+                wave_lds_sync();
+                // rows p, q of S <- J^T S
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    if (sh_[r] == 0.0) continue;
+                    const int j = (t + r * WAVE) % kPsdSub;
+                    const double xp = L.S[ph[r]][j], xq = L.S[qh[r]][j];
+                    L.S[ph[r]][j] = ch[r] * xp - sh_[r] * xq;
+                    L.S[qh[r]][j] = sh_[r] * xp + ch[r] * xq;
+                }
+                wave_lds_sync();
+                // columns p, q of S and of Q <- (.) J
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    if (sh_[r] == 0.0) continue;
+                    const int i = (t + r * WAVE) % kPsdSub;
+                    const double xp = L.S[i][ph[r]], xq = L.S[i][qh[r]];
+                    L.S[i][ph[r]] = ch[r] * xp - sh_[r] * xq;
+                    L.S[i][qh[r]] = sh_[r] * xp + ch[r] * xq;
+                    const double vp = L.Q[i][ph[r]], vq = L.Q[i][qh[r]];
+                    L.Q[i][ph[r]] = ch[r] * vp - sh_[r] * vq;
+                    L.Q[i][qh[r]] = sh_[r] * vp + ch[r] * vq;
+                }
+                wave_lds_sync();
             }
-            __syncthreads();
-            // rows p, q of S <- J^T S
-            for (int e = t; e < (kPsdSub / 2) * kPsdSub; e += n) {
-                const int h = e / kPsdSub, j = e % kPsdSub;
-                const double c = R.cs[h], s_ = R.sn[h];
-                if (s_ == 0.0) continue;
-                const int p = R.pp[h], qq = R.qq[h];
-                const double xp = L.S[p][j], xq = L.S[qq][j];
-                L.S[p][j] = c * xp - s_ * xq;
-                L.S[qq][j] = s_ * xp + c * xq;
-            }
-            __syncthreads();
-            // columns p, q of S and of Q <- (.) J
-            for (int e = t; e < (kPsdSub / 2) * kPsdSub; e += n) {
-                const int h = e / kPsdSub, i = e % kPsdSub;
-                const double c = R.cs[h], s_ = R.sn[h];
-                if (s_ == 0.0) continue;
-                const int p = R.pp[h], qq = R.qq[h];
-                const double xp = L.S[i][p], xq = L.S[i][qq];
-                L.S[i][p] = c * xp - s_ * xq;
-                L.S[i][qq] = s_ * xp + c * xq;
-                const double vp = L.Q[i][p], vq = L.Q[i][qq];
-                L.Q[i][p] = c * vp - s_ * vq;
-                L.Q[i][qq] = s_ * vp + c * vq;
-            }
-            __syncthreads();
         }
     }
+    __syncthreads();
     for (int e = t; e < kPsdSub * kPsdSub; e += n) q[e] = L.Q[e / kPsdSub][e % kPsdSub];
     __syncthreads();
 }
@@ -592,7 +613,6 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     const int nt = (k + kPsdTile - 1) / kPsdTile;        // tiles
     const int ntt = nt + (nt & 1);                        // even, with a dummy tile
     const int np = ntt / 2;
-    PsdRound& R = psd_round_lds();
     const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
     double prev = 1.0;
     for (int sweep = 0; sweep < 30; ++sweep) {
@@ -613,7 +633,7 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
             int t1, t2;
             psd_tile_pair(ntt, 0, h, t1, t2);
             psd_sub_diag(k, nt, t1, t2, [&](int i, int j) { return mat[(size_t)i * k + j]; },
-                         qbuf[0] + (size_t)h * kPsdSub * kPsdSub, R);
+                         qbuf[0] + (size_t)h * kPsdSub * kPsdSub);
         }
         tm.sync();
         for (int round = 0; round < ntt - 1; ++round) {
@@ -662,7 +682,7 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
                 for (int h = tm.blk(); h < np; h += tm.nblk()) {
                     int t1, t2;
                     psd_tile_pair(ntt, round + 1, h, t1, t2);
-                    psd_sub_diag(k, nt, t1, t2, turned, qbuf[(round + 1) & 1] + (size_t)h * kPsdSub * kPsdSub, R);
+                    psd_sub_diag(k, nt, t1, t2, turned, qbuf[(round + 1) & 1] + (size_t)h * kPsdSub * kPsdSub);
                 }
             }
             double* sw = vm;

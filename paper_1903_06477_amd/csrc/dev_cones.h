@@ -470,21 +470,16 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Diagonalises the 2-tile submatrix for tile pair (t1, t2) in LDS and writes
-// Q (slot x slot, row-major) to q; entry (i, j) of the matrix is at(i, j).
-// Called by a whole workgroup: all threads load, the cyclic Jacobi sweeps run
-// on the first wavefront alone (eight rotations of a round, parameters passed
-// by lane shuffles, wavefront-level ordering instead of workgroup barriers).
-template <typename At>
-__device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
+// Cyclic Jacobi on the symmetric kPsdSub x kPsdSub matrix in L.S (filled and
+// visible to the workgroup); writes its eigenvectors Q (slot x slot,
+// row-major, new column b = sum_a Q[a][b] old column a) to q.  Called by a
+// whole workgroup: the sweeps run on the first wavefront alone (eight
+// rotations of a round, parameters passed by lane shuffles, wavefront
+// ordering instead of workgroup barriers).
+__device__ __noinline__ void psd_sub_jacobi(double* q) {
     PsdSub& L = psd_sub_lds();
     const int t = threadIdx.x, n = blockDim.x;
-    for (int e = t; e < kPsdSub * kPsdSub; e += n) {
-        const int a = e / kPsdSub, b = e % kPsdSub;
-        const int ga = psd_slot_index(k, nt, t1, t2, a), gb = psd_slot_index(k, nt, t1, t2, b);
-        L.S[a][b] = (ga >= 0 && gb >= 0) ? at(ga, gb) : 0.0;
-        L.Q[a][b] = a == b ? 1.0 : 0.0;
-    }
+    for (int e = t; e < kPsdSub * kPsdSub; e += n) L.Q[e / kPsdSub][e % kPsdSub] = (e / kPsdSub == e % kPsdSub) ? 1.0 : 0.0;
     __syncthreads();
     if (t < WAVE) {
         constexpr int kHalf = kPsdSub / 2;
@@ -559,6 +554,78 @@ __device__ __noinline__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, 
     __syncthreads();
 }
 
+
+// Diagonalises the 2-tile submatrix for tile pair (t1, t2), entry (i, j) of
+// the matrix being at(i, j); Q to q.  Whole workgroup.
+template <typename At>
+__device__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
+    PsdSub& L = psd_sub_lds();
+    for (int e = threadIdx.x; e < kPsdSub * kPsdSub; e += blockDim.x) {
+        const int a = e / kPsdSub, b = e % kPsdSub;
+        const int ga = psd_slot_index(k, nt, t1, t2, a), gb = psd_slot_index(k, nt, t1, t2, b);
+        L.S[a][b] = (ga >= 0 && gb >= 0) ? at(ga, gb) : 0.0;
+    }
+    __syncthreads();
+    psd_sub_jacobi(q);
+}
+
+// Subproblem of tile pair h of round `nr`, taken from the matrix after round
+// r (B = Q_r^T A Q_r, A = mat, Q_r of every round-r pair at qr), computed from
+// A and Q_r directly: rows of the subproblem come from two round-r pairs, so
+// T = A[rows of those pairs, pair of column b] Q_r[:, b] (2 x 16 x 16, in the
+// LDS of L), then S[a][b] = sum_x Q_r[x][a'] T[x][b].  Then diagonalised; Q
+// to q.  Whole workgroup.
+__device__ __noinline__ void psd_next_sub(int k, int nt, int ntt, int r, int nr, int h, const double* mat,
+                                          const double* qr, double* q) {
+    PsdSub& L = psd_sub_lds();
+    double* T = &L.S[0][0];                        // 2 * kPsdSub * kPsdSub doubles over S and Q
+    const int t = threadIdx.x, n = blockDim.x;
+    int u1, u2;
+    psd_tile_pair(ntt, nr, h, u1, u2);
+    for (int e = t; e < 2 * kPsdSub * kPsdSub; e += n) {
+        const int sr = e / (kPsdSub * kPsdSub), x = (e / kPsdSub) % kPsdSub, b = e % kPsdSub;
+        const int u = sr ? u2 : u1;
+        const int gb = psd_slot_index(k, nt, u1, u2, b);
+        double v = 0.0;
+        if (u < nt && gb >= 0) {
+            int srow, scol;
+            const int hr = psd_tile_owner(ntt, r, u, srow);
+            const int hc = psd_tile_owner(ntt, r, gb / kPsdTile, scol);
+            int r1, r2, c1, c2;
+            psd_tile_pair(ntt, r, hr, r1, r2);
+            psd_tile_pair(ntt, r, hc, c1, c2);
+            const int gx = psd_slot_index(k, nt, r1, r2, x);
+            if (gx >= 0) {
+                const double* qc = qr + (size_t)hc * kPsdSub * kPsdSub;
+                const int cb = scol * kPsdTile + gb % kPsdTile;
+                for (int y = 0; y < kPsdSub; ++y) {
+                    const int gy = psd_slot_index(k, nt, c1, c2, y);
+                    if (gy >= 0) v += mat[(size_t)gx * k + gy] * qc[y * kPsdSub + cb];
+                }
+            }
+        }
+        T[e] = v;
+    }
+    __syncthreads();
+    double s_ = 0.0;
+    if (t < kPsdSub * kPsdSub) {
+        const int a = t / kPsdSub, b = t % kPsdSub;
+        const int ga = psd_slot_index(k, nt, u1, u2, a), gb = psd_slot_index(k, nt, u1, u2, b);
+        if (ga >= 0 && gb >= 0) {
+            int sa;
+            const int hr = psd_tile_owner(ntt, r, ga / kPsdTile, sa);
+            const double* qa = qr + (size_t)hr * kPsdSub * kPsdSub;
+            const int ca = sa * kPsdTile + ga % kPsdTile;
+            const double* tr = T + (size_t)(a / kPsdTile) * kPsdSub * kPsdSub;
+            for (int x = 0; x < kPsdSub; ++x) s_ += qa[x * kPsdSub + ca] * tr[x * kPsdSub + b];
+        }
+    }
+    __syncthreads();
+    if (t < kPsdSub * kPsdSub) L.S[t / kPsdSub][t % kPsdSub] = s_;
+    __syncthreads();
+    psd_sub_jacobi(q);
+}
+
 // `buf` holds 4 k*k doubles (matrix, its turned copy, Vt and its turned copy);
 // `in` (packed input, filled by the caller) and `outv` are contiguous, with
 // room for two rounds' Q matrices (k (k + 1) doubles in all, k > 2 kPsdTile).
@@ -614,8 +681,9 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     const int ntt = nt + (nt & 1);                        // even, with a dummy tile
     const int np = ntt / 2;
     const double tol2 = fmax(1e-30, (1e-16 * k) * (1e-16 * k));
-    double prev = 1.0;
-    for (int sweep = 0; sweep < 30; ++sweep) {
+    PsdSub& L = psd_sub_lds();
+    // off-diagonal mass of the starting matrix
+    {
         double off = 0.0, tot = 0.0;
         for (int idx = r0; idx < k * k; idx += R_) {
             const double v = mat[idx] * mat[idx];
@@ -625,10 +693,10 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
         put(sh, 0, off);
         put(sh, 1, tot);
         tm.reduce(sh, 2);
-        const double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
-        if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
-        prev = cur;
-        // (1) for round 0, from the matrix itself
+    }
+    double cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
+    if (cur > tol2) {
+        // Q of round 0 from the matrix itself
         for (int h = tm.blk(); h < np; h += tm.nblk()) {
             int t1, t2;
             psd_tile_pair(ntt, 0, h, t1, t2);
@@ -636,59 +704,88 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
                          qbuf[0] + (size_t)h * kPsdSub * kPsdSub);
         }
         tm.sync();
-        for (int round = 0; round < ntt - 1; ++round) {
-            const double* qr = qbuf[round & 1];
-            // entry (i, c) of tmp Q for this round's pairs
-            auto turned = [&](int i, int c) {
-                int side;
-                const int h = psd_tile_owner(ntt, round, c / kPsdTile, side);
-                int t1, t2;
-                psd_tile_pair(ntt, round, h, t1, t2);
-                const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
-                const int cp = side * kPsdTile + c % kPsdTile;
-                double s_ = 0.0;
-                for (int b = 0; b < kPsdSub; ++b) {
-                    const int gb = psd_slot_index(k, nt, t1, t2, b);
-                    if (gb < 0) continue;
-                    s_ += tmp[(size_t)i * k + gb] * q[b * kPsdSub + cp];
+        double prev = 1.0;
+        long long g = 0;                                  // rounds done; Q of round g is in qbuf[g & 1]
+        for (int sweep = 0; sweep < 30; ++sweep) {
+            double off = 0.0, tot = 0.0;
+            for (int round = 0; round < ntt - 1; ++round, ++g) {
+                const double* qr = qbuf[g & 1];
+                const bool last = round == ntt - 2;
+                // (a) mat2 = Q^T mat Q, block by block: output block (pair hi, pair hc)
+                // needs input block (hi, hc) and the two pairs' Q only
+                for (int bid = tm.blk(); bid < np * np; bid += tm.nblk()) {
+                    const int hi = bid / np, hc = bid - (bid / np) * np;
+                    int i1, i2, c1, c2;
+                    psd_tile_pair(ntt, round, hi, i1, i2);
+                    psd_tile_pair(ntt, round, hc, c1, c2);
+                    const double* qi = qr + (size_t)hi * kPsdSub * kPsdSub;
+                    const double* qc = qr + (size_t)hc * kPsdSub * kPsdSub;
+                    const int e = threadIdx.x;
+                    if (e < kPsdSub * kPsdSub) {               // L.S = mat[block] Q_c
+                        const int x = e / kPsdSub, cb = e % kPsdSub;
+                        const int gx = psd_slot_index(k, nt, i1, i2, x);
+                        double v = 0.0;
+                        if (gx >= 0)
+                            for (int y = 0; y < kPsdSub; ++y) {
+                                const int gy = psd_slot_index(k, nt, c1, c2, y);
+                                if (gy >= 0) v += mat[(size_t)gx * k + gy] * qc[y * kPsdSub + cb];
+                            }
+                        L.S[x][cb] = v;
+                    }
+                    __syncthreads();
+                    if (e < kPsdSub * kPsdSub) {               // block of mat2 = Q_i^T L.S
+                        const int ia = e / kPsdSub, cb = e % kPsdSub;
+                        const int gi = psd_slot_index(k, nt, i1, i2, ia), gc = psd_slot_index(k, nt, c1, c2, cb);
+                        if (gi >= 0 && gc >= 0) {
+                            double v = 0.0;
+                            for (int x = 0; x < kPsdSub; ++x) v += qi[x * kPsdSub + ia] * L.S[x][cb];
+                            tmp[(size_t)gi * k + gc] = v;
+                            if (last) {
+                                tot += v * v;
+                                if (gi != gc) off += v * v;
+                            }
+                        }
+                    }
+                    __syncthreads();
                 }
-                return s_;
-            };
-            // (2) tmp = Q^T A and vm2 = Q^T Vt on the rows of each pair
-            for (int idx = r0; idx < k * k; idx += R_) {
-                const int r = idx / k, j = idx - (idx / k) * k;
-                int side;
-                const int h = psd_tile_owner(ntt, round, r / kPsdTile, side);
-                int t1, t2;
-                psd_tile_pair(ntt, round, h, t1, t2);
-                const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
-                const int ip = side * kPsdTile + r % kPsdTile;
-                double sa = 0.0, sv = 0.0;
-                for (int a = 0; a < kPsdSub; ++a) {
-                    const int ga = psd_slot_index(k, nt, t1, t2, a);
-                    if (ga < 0) continue;
-                    const double qa = q[a * kPsdSub + ip];
-                    sa += qa * mat[(size_t)ga * k + j];
-                    sv += qa * vm[(size_t)ga * k + j];
-                }
-                tmp[idx] = sa;
-                vm2[idx] = sv;
-            }
-            tm.sync();
-            // (3) mat = tmp Q on the columns of each pair, and (1) of the next
-            // round from the same products (reads tmp and this round's Q only)
-            for (int idx = r0; idx < k * k; idx += R_) mat[idx] = turned(idx / k, idx - (idx / k) * k);
-            if (round + 1 < ntt - 1) {
-                for (int h = tm.blk(); h < np; h += tm.nblk()) {
+                // (b) vm2 = Q^T Vt on the rows of each pair
+                for (int idx = r0; idx < k * k; idx += R_) {
+                    const int rw = idx / k, j = idx - (idx / k) * k;
+                    int side;
+                    const int h = psd_tile_owner(ntt, round, rw / kPsdTile, side);
                     int t1, t2;
-                    psd_tile_pair(ntt, round + 1, h, t1, t2);
-                    psd_sub_diag(k, nt, t1, t2, turned, qbuf[(round + 1) & 1] + (size_t)h * kPsdSub * kPsdSub);
+                    psd_tile_pair(ntt, round, h, t1, t2);
+                    const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
+                    const int ip = side * kPsdTile + rw % kPsdTile;
+                    double sv = 0.0;
+                    for (int x = 0; x < kPsdSub; ++x) {
+                        const int gx = psd_slot_index(k, nt, t1, t2, x);
+                        if (gx >= 0) sv += q[x * kPsdSub + ip] * vm[(size_t)gx * k + j];
+                    }
+                    vm2[idx] = sv;
+                }
+                // (c) Q of the next round (the next sweep's first after the last)
+                // from mat and this round's Q; unused if the sweeps stop here
+                for (int h = tm.blk(); h < np; h += tm.nblk())
+                    psd_next_sub(k, nt, ntt, round, last ? 0 : round + 1, h, mat, qr,
+                                 qbuf[(g + 1) & 1] + (size_t)h * kPsdSub * kPsdSub);
+                double* sw = mat;
+                mat = tmp;
+                tmp = sw;
+                sw = vm;
+                vm = vm2;
+                vm2 = sw;
+                if (last) {
+                    put(sh, 0, off);
+                    put(sh, 1, tot);
+                    tm.reduce(sh, 2);
+                } else {
+                    tm.sync();
                 }
             }
-            double* sw = vm;
-            vm = vm2;
-            vm2 = sw;
-            tm.sync();
+            cur = sh.out[1] > 0.0 ? sh.out[0] / sh.out[1] : 0.0;
+            if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
+            prev = cur;
         }
     }
     // reconstruct from Vt: lam into `in`, Wt = diag(lam+) Vt into tmp

@@ -470,13 +470,19 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inner sweeps per tile subproblem of the team block Jacobi.  The outer
+// method converges with approximate subproblem solutions (each inner sweep
+// is a block of the scalar method's rotations); the outer stopping test
+// alone decides the accuracy.
+constexpr int kPsdInnerSweeps = 1;
+
 // Cyclic Jacobi on the symmetric kPsdSub x kPsdSub matrix in L.S (filled and
 // visible to the workgroup); writes its eigenvectors Q (slot x slot,
 // row-major, new column b = sum_a Q[a][b] old column a) to q.  Called by a
 // whole workgroup: the sweeps run on the first wavefront alone (eight
 // rotations of a round, parameters passed by lane shuffles, wavefront
 // ordering instead of workgroup barriers).
-__device__ __noinline__ void psd_sub_jacobi(double* q) {
+__device__ __noinline__ void psd_sub_jacobi(double* q, int max_sweeps) {
     PsdSub& L = psd_sub_lds();
     const int t = threadIdx.x, n = blockDim.x;
     for (int e = t; e < kPsdSub * kPsdSub; e += n) L.Q[e / kPsdSub][e % kPsdSub] = (e / kPsdSub == e % kPsdSub) ? 1.0 : 0.0;
@@ -486,7 +492,7 @@ __device__ __noinline__ void psd_sub_jacobi(double* q) {
         constexpr int kPer = kHalf * kPsdSub / WAVE;            // (pair, index) items per lane
         const double tol2 = (1e-16 * kPsdSub) * (1e-16 * kPsdSub);
         double prev = 1.0;
-        for (int sweep = 0; sweep < 30; ++sweep) {
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
             double off = 0.0, tot = 0.0;
             for (int e = t; e < kPsdSub * kPsdSub; e += WAVE) {
                 const double v = L.S[e / kPsdSub][e % kPsdSub] * L.S[e / kPsdSub][e % kPsdSub];
@@ -566,7 +572,7 @@ __device__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
         L.S[a][b] = (ga >= 0 && gb >= 0) ? at(ga, gb) : 0.0;
     }
     __syncthreads();
-    psd_sub_jacobi(q);
+    psd_sub_jacobi(q, kPsdInnerSweeps);
 }
 
 // Subproblem of tile pair h of round `nr`, taken from the matrix after round
@@ -623,7 +629,7 @@ __device__ __noinline__ void psd_next_sub(int k, int nt, int ntt, int r, int nr,
     __syncthreads();
     if (t < kPsdSub * kPsdSub) L.S[t / kPsdSub][t % kPsdSub] = s_;
     __syncthreads();
-    psd_sub_jacobi(q);
+    psd_sub_jacobi(q, kPsdInnerSweeps);
 }
 
 // `buf` holds 4 k*k doubles (matrix, its turned copy, Vt and its turned copy);

@@ -47,8 +47,11 @@ def cg_op_bytes(nnz, m, n, bval=8):
 
 def op_units(info):
     """CG-operator equivalents one solve launch processes: every CG iteration
-    is one; every linear step adds two (right-hand side, initial residual and
-    the y-part product); every termination check adds one (A x and A^T y)."""
+    is one; every linear step adds two (the right-hand side A^T r_y with the
+    y-part product A x, and the first CG pass's product K u0; the start
+    r0 = rhs - K xw costs no product, and its recomputation from scratch every
+    64th iteration is not counted); every termination check adds one (A x and
+    A^T y)."""
     iters = info["iters"] + 1
     linear_steps = iters + (info["iters"] - info["k0"])
     return info["cg_iters"] + 2 * linear_steps + iters
@@ -154,7 +157,7 @@ def sdp_exp_leg(sscs, G, iters=150):
     """The mixed PSD / exponential-cone instance (64 sparse-PCA blocks of
     order 64 and one of order 256, l1 logistic regression with 5000 samples x
     1000 features; n = 349033, m = 535113): `iters` iterations of Algorithm 1
-    timed (a complete solve to 1e-6 takes about 4300), reported as iterations
+    timed (a complete solve to 1e-6 takes about 4000), reported as iterations
     per second, FP64, AA memory 5."""
     import torch
     p = G.config3_sdp_exp()

@@ -73,6 +73,7 @@ extern __shared__ __attribute__((aligned(16))) double sscs_dyn_lds[];
 struct BlockTeam {
     static constexpr bool kLds = false;
     static constexpr bool kBlock = true;
+    static constexpr bool kPsdTeam = false;
     using lds_t = double;
     MatPart mp[2];    // A, A^T: all rows, global memory
     double* lu = nullptr;   // LDS copies of the CG's gathered vectors (n and m
@@ -130,11 +131,15 @@ __device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned lo
 // read after it, also across groups through the leaders' fences.  A wait that exceeds `timeout_ticks` of the wall clock raises
 // the abort flag; later barriers then return at once, so every wave of the
 // grid still reaches the kernel's end.
-template <bool LDS, typename TL = double>
+// PT: the form that projects PSD blocks above order 64 with the whole team;
+// instances without such blocks run the form without that code, so the
+// registers its call tree takes do not cost the solve kernel spills.
+template <bool LDS, typename TL = double, bool PT = true>
 struct GridTeam {
     static constexpr bool kLds = LDS;   // operator rows held in LDS ...
     using lds_t = TL;                   // ... with values of this type
     static constexpr bool kBlock = false;
+    static constexpr bool kPsdTeam = PT;
     MatPart mp[2];              // this workgroup's rows of A and A^T
     unsigned long long* bar;    // BAR_WORDS words, zero at launch
     int* abort_flag;

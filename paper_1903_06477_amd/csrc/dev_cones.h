@@ -482,7 +482,7 @@ constexpr int kPsdInnerSweeps = 1;
 // whole workgroup: the sweeps run on the first wavefront alone (eight
 // rotations of a round, parameters passed by lane shuffles, wavefront
 // ordering instead of workgroup barriers).
-__device__ __noinline__ void psd_sub_jacobi(double* q, int max_sweeps) {
+__device__ __noinline__ void psd_sub_jacobi(double* q) {
     PsdSub& L = psd_sub_lds();
     const int t = threadIdx.x, n = blockDim.x;
     for (int e = t; e < kPsdSub * kPsdSub; e += n) L.Q[e / kPsdSub][e % kPsdSub] = (e / kPsdSub == e % kPsdSub) ? 1.0 : 0.0;
@@ -492,7 +492,7 @@ __device__ __noinline__ void psd_sub_jacobi(double* q, int max_sweeps) {
         constexpr int kPer = kHalf * kPsdSub / WAVE;            // (pair, index) items per lane
         const double tol2 = (1e-16 * kPsdSub) * (1e-16 * kPsdSub);
         double prev = 1.0;
-        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        for (int sweep = 0; sweep < kPsdInnerSweeps; ++sweep) {
             double off = 0.0, tot = 0.0;
             for (int e = t; e < kPsdSub * kPsdSub; e += WAVE) {
                 const double v = L.S[e / kPsdSub][e % kPsdSub] * L.S[e / kPsdSub][e % kPsdSub];
@@ -572,7 +572,7 @@ __device__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
         L.S[a][b] = (ga >= 0 && gb >= 0) ? at(ga, gb) : 0.0;
     }
     __syncthreads();
-    psd_sub_jacobi(q, kPsdInnerSweeps);
+    psd_sub_jacobi(q);
 }
 
 // Subproblem of tile pair h of round `nr`, taken from the matrix after round
@@ -629,7 +629,112 @@ __device__ __noinline__ void psd_next_sub(int k, int nt, int ntt, int r, int nr,
     __syncthreads();
     if (t < kPsdSub * kPsdSub) L.S[t / kPsdSub][t % kPsdSub] = s_;
     __syncthreads();
-    psd_sub_jacobi(q, kPsdInnerSweeps);
+    psd_sub_jacobi(q);
+}
+
+// Pieces of the team block Jacobi, out of line and with bounded unrolling:
+// the solve kernel calls the PSD team path from inside its projection passes,
+// and every register this call tree touches is one the kernel cannot keep a
+// value in across the call, so the tree is kept small.  Each piece is run by
+// every thread of the team over the index range r0, r0 + R, ...
+
+// C = A B (transB = false) or A B^T (true), k x k row-major.
+__device__ __noinline__ void psd_team_mm(int r0, int R, int k, const double* A, const double* B, double* C,
+                                         bool transB) {
+    for (int idx = r0; idx < k * k; idx += R) {
+        const int i = idx / k, j = idx - (idx / k) * k;
+        double s_ = 0.0;
+        if (transB) {
+#pragma unroll 4
+            for (int e = 0; e < k; ++e) s_ += A[(size_t)i * k + e] * B[(size_t)j * k + e];
+        } else {
+#pragma unroll 4
+            for (int e = 0; e < k; ++e) s_ += A[(size_t)i * k + e] * B[(size_t)e * k + j];
+        }
+        C[idx] = s_;
+    }
+}
+
+// Step (a) of a team block Jacobi round: output blocks (pair hi, pair hc) of
+// Q^T mat Q into out, one workgroup per block; on the sweep's last round also
+// the squared off-diagonal and total mass of the output (added to off, tot).
+__device__ __noinline__ void psd_team_blocks(int blk, int nblk, int k, int nt, int ntt, int np, int round, bool last,
+                                             const double* mat, double* out, const double* qr, double* acc) {
+    PsdSub& L = psd_sub_lds();
+    double off = 0.0, tot = 0.0;
+    for (int bid = blk; bid < np * np; bid += nblk) {
+        const int hi = bid / np, hc = bid - (bid / np) * np;
+        int i1, i2, c1, c2;
+        psd_tile_pair(ntt, round, hi, i1, i2);
+        psd_tile_pair(ntt, round, hc, c1, c2);
+        const double* qi = qr + (size_t)hi * kPsdSub * kPsdSub;
+        const double* qc = qr + (size_t)hc * kPsdSub * kPsdSub;
+        const int e = threadIdx.x;
+        if (e < kPsdSub * kPsdSub) {               // L.S = mat[block] Q_c
+            const int x = e / kPsdSub, cb = e % kPsdSub;
+            const int gx = psd_slot_index(k, nt, i1, i2, x);
+            double v = 0.0;
+            if (gx >= 0) {
+#pragma unroll 4
+                for (int y = 0; y < kPsdSub; ++y) {
+                    const int gy = psd_slot_index(k, nt, c1, c2, y);
+                    if (gy >= 0) v += mat[(size_t)gx * k + gy] * qc[y * kPsdSub + cb];
+                }
+            }
+            L.S[x][cb] = v;
+        }
+        __syncthreads();
+        if (e < kPsdSub * kPsdSub) {               // block of the output = Q_i^T L.S
+            const int ia = e / kPsdSub, cb = e % kPsdSub;
+            const int gi = psd_slot_index(k, nt, i1, i2, ia), gc = psd_slot_index(k, nt, c1, c2, cb);
+            if (gi >= 0 && gc >= 0) {
+                double v = 0.0;
+#pragma unroll 4
+                for (int x = 0; x < kPsdSub; ++x) v += qi[x * kPsdSub + ia] * L.S[x][cb];
+                out[(size_t)gi * k + gc] = v;
+                if (last) {
+                    tot += v * v;
+                    if (gi != gc) off += v * v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    acc[0] = off;
+    acc[1] = tot;
+}
+
+// Step (b): vout = Q^T vin on the rows of each pair of the round.
+__device__ __noinline__ void psd_team_rows(int r0, int R, int k, int nt, int ntt, int round, const double* qr,
+                                           const double* vin, double* vout) {
+    for (int idx = r0; idx < k * k; idx += R) {
+        const int rw = idx / k, j = idx - (idx / k) * k;
+        int side;
+        const int h = psd_tile_owner(ntt, round, rw / kPsdTile, side);
+        int t1, t2;
+        psd_tile_pair(ntt, round, h, t1, t2);
+        const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
+        const int ip = side * kPsdTile + rw % kPsdTile;
+        double sv = 0.0;
+#pragma unroll 4
+        for (int x = 0; x < kPsdSub; ++x) {
+            const int gx = psd_slot_index(k, nt, t1, t2, x);
+            if (gx >= 0) sv += q[x * kPsdSub + ip] * vin[(size_t)gx * k + j];
+        }
+        vout[idx] = sv;
+    }
+}
+
+// Packed output: outv = svec(Wt^T Vt), Wt = diag(lam+) Vt.
+__device__ __noinline__ void psd_team_recon(int r0, int R, int k, const double* wt, const double* vt, double* outv) {
+    for (int idx = r0; idx < k * (k + 1) / 2; idx += R) {
+        int i, j;
+        psd_unpack_index(k, idx, i, j);
+        double s_ = 0.0;
+#pragma unroll 4
+        for (int e = 0; e < k; ++e) s_ += wt[(size_t)e * k + i] * vt[(size_t)e * k + j];
+        outv[idx] = (i == j) ? s_ : s_ * 1.41421356237309504880;
+    }
 }
 
 // `buf` holds 4 k*k doubles (matrix, its turned copy, Vt and its turned copy);
@@ -660,19 +765,9 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     tm.sync();
     const bool use_warm = V0 != nullptr && *warm != 0;
     if (use_warm) {
-        for (int idx = r0; idx < k * k; idx += R_) {    // tmp = Vt0 A
-            const int i = idx / k, j = idx - (idx / k) * k;
-            double s_ = 0.0;
-            for (int e = 0; e < k; ++e) s_ += V0[i * k + e] * mat[e * k + j];
-            tmp[idx] = s_;
-        }
+        psd_team_mm(r0, R_, k, V0, mat, tmp, false);     // tmp = Vt0 A
         tm.sync();
-        for (int idx = r0; idx < k * k; idx += R_) {    // vm2 = (Vt0 A) Vt0^T
-            const int i = idx / k, j = idx - (idx / k) * k;
-            double s_ = 0.0;
-            for (int e = 0; e < k; ++e) s_ += tmp[i * k + e] * V0[j * k + e];
-            vm2[idx] = s_;
-        }
+        psd_team_mm(r0, R_, k, tmp, V0, vm2, true);      // vm2 = (Vt0 A) Vt0^T
         tm.sync();
         for (int idx = r0; idx < k * k; idx += R_) {
             const int i = idx / k, j = idx - (idx / k) * k;
@@ -713,63 +808,15 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
         double prev = 1.0;
         long long g = 0;                                  // rounds done; Q of round g is in qbuf[g & 1]
         for (int sweep = 0; sweep < 30; ++sweep) {
-            double off = 0.0, tot = 0.0;
+            double acc[2] = {0.0, 0.0};
             for (int round = 0; round < ntt - 1; ++round, ++g) {
                 const double* qr = qbuf[g & 1];
                 const bool last = round == ntt - 2;
                 // (a) mat2 = Q^T mat Q, block by block: output block (pair hi, pair hc)
-                // needs input block (hi, hc) and the two pairs' Q only
-                for (int bid = tm.blk(); bid < np * np; bid += tm.nblk()) {
-                    const int hi = bid / np, hc = bid - (bid / np) * np;
-                    int i1, i2, c1, c2;
-                    psd_tile_pair(ntt, round, hi, i1, i2);
-                    psd_tile_pair(ntt, round, hc, c1, c2);
-                    const double* qi = qr + (size_t)hi * kPsdSub * kPsdSub;
-                    const double* qc = qr + (size_t)hc * kPsdSub * kPsdSub;
-                    const int e = threadIdx.x;
-                    if (e < kPsdSub * kPsdSub) {               // L.S = mat[block] Q_c
-                        const int x = e / kPsdSub, cb = e % kPsdSub;
-                        const int gx = psd_slot_index(k, nt, i1, i2, x);
-                        double v = 0.0;
-                        if (gx >= 0)
-                            for (int y = 0; y < kPsdSub; ++y) {
-                                const int gy = psd_slot_index(k, nt, c1, c2, y);
-                                if (gy >= 0) v += mat[(size_t)gx * k + gy] * qc[y * kPsdSub + cb];
-                            }
-                        L.S[x][cb] = v;
-                    }
-                    __syncthreads();
-                    if (e < kPsdSub * kPsdSub) {               // block of mat2 = Q_i^T L.S
-                        const int ia = e / kPsdSub, cb = e % kPsdSub;
-                        const int gi = psd_slot_index(k, nt, i1, i2, ia), gc = psd_slot_index(k, nt, c1, c2, cb);
-                        if (gi >= 0 && gc >= 0) {
-                            double v = 0.0;
-                            for (int x = 0; x < kPsdSub; ++x) v += qi[x * kPsdSub + ia] * L.S[x][cb];
-                            tmp[(size_t)gi * k + gc] = v;
-                            if (last) {
-                                tot += v * v;
-                                if (gi != gc) off += v * v;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-                // (b) vm2 = Q^T Vt on the rows of each pair
-                for (int idx = r0; idx < k * k; idx += R_) {
-                    const int rw = idx / k, j = idx - (idx / k) * k;
-                    int side;
-                    const int h = psd_tile_owner(ntt, round, rw / kPsdTile, side);
-                    int t1, t2;
-                    psd_tile_pair(ntt, round, h, t1, t2);
-                    const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
-                    const int ip = side * kPsdTile + rw % kPsdTile;
-                    double sv = 0.0;
-                    for (int x = 0; x < kPsdSub; ++x) {
-                        const int gx = psd_slot_index(k, nt, t1, t2, x);
-                        if (gx >= 0) sv += q[x * kPsdSub + ip] * vm[(size_t)gx * k + j];
-                    }
-                    vm2[idx] = sv;
-                }
+                // needs input block (hi, hc) and the two pairs' Q only; (b) the
+                // pairs' rows of Vt
+                psd_team_blocks(tm.blk(), tm.nblk(), k, nt, ntt, np, round, last, mat, tmp, qr, acc);
+                psd_team_rows(r0, R_, k, nt, ntt, round, qr, vm, vm2);
                 // (c) Q of the next round (the next sweep's first after the last)
                 // from mat and this round's Q; unused if the sweeps stop here
                 for (int h = tm.blk(); h < np; h += tm.nblk())
@@ -782,8 +829,8 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
                 vm = vm2;
                 vm2 = sw;
                 if (last) {
-                    put(sh, 0, off);
-                    put(sh, 1, tot);
+                    put(sh, 0, acc[0]);
+                    put(sh, 1, acc[1]);
                     tm.reduce(sh, 2);
                 } else {
                     tm.sync();
@@ -799,13 +846,7 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     tm.sync();
     for (int idx = r0; idx < k * k; idx += R_) tmp[idx] = vm[idx] * in[idx / k];
     tm.sync();
-    for (int idx = r0; idx < k * (k + 1) / 2; idx += R_) {
-        int i, j;
-        psd_unpack_index(k, idx, i, j);
-        double s_ = 0.0;
-        for (int e = 0; e < k; ++e) s_ += tmp[e * k + i] * vm[e * k + j];
-        outv[idx] = (i == j) ? s_ : s_ * 1.41421356237309504880;
-    }
+    psd_team_recon(r0, R_, k, tmp, vm, outv);
     if (V0 != nullptr) {
         for (int idx = r0; idx < k * k; idx += R_) V0[idx] = vm[idx];
         if (r0 == 0) *warm = 1;
@@ -881,7 +922,7 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
             for (int e = threadIdx.x; e < len; e += blockDim.x) emit(o + e, pout[e]);
             __syncthreads();
         }
-        if constexpr (kGrid) {
+        if constexpr (kGrid && Team::kPsdTeam) {
             if (K.psd_kmax > kPsdTeamOrder) {
                 double* tb = K.psd_team;                     // 4 kmax^2 matrices, then input / output
                 double* tin = tb + 4 * (size_t)K.psd_kmax * K.psd_kmax;

@@ -58,8 +58,8 @@ struct FlatTeam {
 
 // Workgroup b of a grid kernel owns rows [part[b], part[b+1]) of A and of A^T
 // and, when the operator fits, keeps them in LDS for the whole launch.
-template <bool LDS, typename TL>
-__device__ inline void grid_team_init(GridTeam<LDS, TL>& tm, const Prob& P) {
+template <bool LDS, typename TL, bool PT>
+__device__ inline void grid_team_init(GridTeam<LDS, TL, PT>& tm, const Prob& P) {
     int off = 0;
     load_part(tm.mp[0], op_mat<TL>(P, 0), P.partA, blockIdx.x, LDS, &off);
     load_part(tm.mp[1], op_mat<TL>(P, 1), P.partAt, blockIdx.x, LDS, &off);
@@ -86,7 +86,7 @@ struct Desc {
 };
 
 // TV: value type of the CG operator (double, or float for mixed precision).
-template <bool LDS, typename TV>
+template <bool LDS, typename TV, bool PT>
 __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S, Result* res,
                                                        unsigned long long* bar, int* abort_flag,
                                                        double* part, long long timeout_ticks) {
@@ -98,16 +98,16 @@ __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S,
         d.S = S;
     }
     __syncthreads();
-    GridTeam<LDS, TV> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
     grid_team_init(tm, d.P);
     sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res);
 }
 
-template <bool LDS, typename TV>
+template <bool LDS, typename TV, bool PT>
 __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, unsigned long long* bar,
                                                     int* abort_flag, double* part, long long timeout_ticks) {
     __shared__ Shared sh;
-    GridTeam<LDS, TV> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
     grid_team_init(tm, P);
     const int n = P.n, m = P.m, N = P.N;
     if (a.op == OP_LINEAR) {
@@ -661,21 +661,29 @@ int check_abort(sscs_work* w) {
 
 // Kernel instantiation for the operator placement (LDS or global) and the
 // precision of the CG operator.
-const void* solve_grid_fn(bool lds, bool mixed) {
-    if (mixed) return lds ? (const void*)k_solve_grid<true, float> : (const void*)k_solve_grid<false, float>;
-    return lds ? (const void*)k_solve_grid<true, double> : (const void*)k_solve_grid<false, double>;
+// The grid kernels for an instance: operator in LDS or not, FP32 or FP64 CG
+// operator, with or without the team path for PSD blocks above order 64.
+template <template <bool, typename, bool> class K_>
+const void* pick_grid(bool lds, bool mixed, bool pt) {
+    if (pt) {
+        if (mixed) return lds ? (const void*)K_<true, float, true>::fn : (const void*)K_<false, float, true>::fn;
+        return lds ? (const void*)K_<true, double, true>::fn : (const void*)K_<false, double, true>::fn;
+    }
+    if (mixed) return lds ? (const void*)K_<true, float, false>::fn : (const void*)K_<false, float, false>::fn;
+    return lds ? (const void*)K_<true, double, false>::fn : (const void*)K_<false, double, false>::fn;
 }
+template <bool L, typename T, bool P> struct SolveGridK { static constexpr auto fn = k_solve_grid<L, T, P>; };
+template <bool L, typename T, bool P> struct OpGridK { static constexpr auto fn = k_op_grid<L, T, P>; };
 
-const void* op_grid_fn(bool lds, bool mixed) {
-    if (mixed) return lds ? (const void*)k_op_grid<true, float> : (const void*)k_op_grid<false, float>;
-    return lds ? (const void*)k_op_grid<true, double> : (const void*)k_op_grid<false, double>;
-}
+bool team_psd(const Inst& I) { return I.K.psd_kmax > kPsdTeamOrder; }
+const void* solve_grid_fn(bool lds, const Inst& I) { return pick_grid<SolveGridK>(lds, I.mixed, team_psd(I)); }
+const void* op_grid_fn(bool lds, const Inst& I) { return pick_grid<OpGridK>(lds, I.mixed, team_psd(I)); }
 
 int run_op(sscs_work* w, int op, const double* in, double* out1, double* out2, double tol, int maxit) {
     Prob P = make_prob(w->I);
     OpArgs a{op, in, out1, out2, w->scal, tol, maxit};
     void* args[] = {&P, &w->V, &a, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-    TRY(launch_grid_kernel(w, const_cast<void*>(op_grid_fn(w->I.lds_bytes > 0, w->I.mixed)), args));
+    TRY(launch_grid_kernel(w, const_cast<void*>(op_grid_fn(w->I.lds_bytes > 0, w->I)), args));
     HIP_TRY(hipGetLastError());
     return check_abort(w);
 }
@@ -726,9 +734,9 @@ int choose_grid(sscs_work* w) {
     int dev = 0, ncu = 0, occ = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_grid_fn(false, w->I.mixed), kBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_grid_fn(false, w->I), kBlock, 0));
     int occ2 = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, op_grid_fn(false, w->I.mixed), kBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, op_grid_fn(false, w->I), kBlock, 0));
     occ = std::max(1, std::min(occ, occ2));
     w->ncu = ncu;
     w->max_grid = std::max(1, ncu * occ);
@@ -759,7 +767,7 @@ int set_partitions(sscs_work* w, bool try_lds) {
     // dynamic LDS left next to the kernels' static LDS (Shared, descriptors,
     // the PSD rotation tables)
     long long stat = 0;
-    for (const void* f : {solve_grid_fn(true, I.mixed), op_grid_fn(true, I.mixed)}) {
+    for (const void* f : {solve_grid_fn(true, I), op_grid_fn(true, I)}) {
         hipFuncAttributes fa{};
         HIP_TRY(hipFuncGetAttributes(&fa, f));
         stat = std::max<long long>(stat, (long long)fa.sharedSizeBytes);
@@ -777,10 +785,10 @@ int set_partitions(sscs_work* w, bool try_lds) {
         I.lds_bytes = 0;
         if (!try_lds || w->grid < 2 || need > limit) break;
         int o1 = 0, o2 = 0;
-        HIP_TRY(hipFuncSetAttribute(solve_grid_fn(true, I.mixed), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
-        HIP_TRY(hipFuncSetAttribute(op_grid_fn(true, I.mixed), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, solve_grid_fn(true, I.mixed), kBlock, (size_t)need));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, op_grid_fn(true, I.mixed), kBlock, (size_t)need));
+        HIP_TRY(hipFuncSetAttribute(solve_grid_fn(true, I), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        HIP_TRY(hipFuncSetAttribute(op_grid_fn(true, I), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, solve_grid_fn(true, I), kBlock, (size_t)need));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, op_grid_fn(true, I), kBlock, (size_t)need));
         const int cap = w->ncu * std::min(o1, o2);
         if (cap >= w->grid) { I.lds_bytes = (int)need; break; }
         if (cap < 2) break;
@@ -970,7 +978,7 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
             k_solve_block<double><<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
     } else {
         void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-        TRY(launch_grid_kernel(w, const_cast<void*>(solve_grid_fn(w->I.lds_bytes > 0, w->I.mixed)), args));
+        TRY(launch_grid_kernel(w, const_cast<void*>(solve_grid_fn(w->I.lds_bytes > 0, w->I)), args));
     }
     HIP_TRY(hipGetLastError());
     TRY(stage_out(w, x, V.out_x, n));

@@ -151,13 +151,13 @@ struct BatchInst {
     Vecs V;
 };
 
-// Up to four workgroups per CU (waves_per_eu 4, as LDS allows): the
-// one-workgroup engine is bound by memory latency, and more resident
-// instances hide more of it than the registers spilled by the tighter budget
-// cost (the CG routine, where the time goes, is out of line and keeps its own
-// allocation).
+// Three workgroups per CU (waves_per_eu 3, up to 168 registers per lane):
+// the one-workgroup engine is bound by memory latency, so resident instances
+// hide latency, but at four per CU the 128-register budget made the rest of
+// the solve (projections, directions, termination) spill heavily; three was
+// measured fastest (two and four slower).
 template <typename TV>
-__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) k_solve_batch(
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_solve_batch(
     const BatchInst* __restrict__ insts, const int* __restrict__ order, int count, Params S, Result* res, int* queue,
     int stage_doubles) {
     __shared__ Shared sh;

@@ -209,6 +209,88 @@ def measured_traffic():
         return None
 
 
+def performance_ratios(T):
+    """Dolan-More ratios r[p, s] = t[p, s] / min_s' t[p, s'] (Sec. V-A,
+    equation (performance_ratio)); T is problems x solvers with inf where a
+    solver failed, and a row every solver failed stays inf."""
+    T = np.asarray(T, dtype=float)
+    best = T.min(axis=1, keepdims=True)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        R = np.where(np.isfinite(T), T / best, np.inf)
+    return R
+
+
+def performance_profile(R, taus):
+    """rho_s(tau) = |{p : r[p, s] <= tau}| / |P| for each tau (rows) and
+    solver (columns)."""
+    R = np.asarray(R, dtype=float)
+    return np.array([(R <= tau).mean(axis=0) for tau in taus])
+
+
+def shifted_geometric_mean(t, sigma):
+    """sgm_sigma of Sec. V-A: failures (inf) count as 100 x the largest
+    finite time of that solver, and the mean of ln max(1, sigma + t_p) over
+    the problems is taken (the printed sum reads as the geometric mean's
+    average; with a plain sum the value would grow with |P|)."""
+    t = np.asarray(t, dtype=float)
+    fin = t[np.isfinite(t)]
+    fill = 100.0 * fin.max() if fin.size else np.inf
+    tt = np.where(np.isfinite(t), t, fill)
+    return float(np.exp(np.mean(np.log(np.maximum(1.0, sigma + tt)))) - sigma)
+
+
+DM_METHODS = [("SCS-like relaxed DRS", dict(direction="zero", c0=0.0)),
+              ("RB (mem:10)", dict(direction="rb", mem=10)),
+              ("RB (mem:16)", dict(direction="rb", mem=16)),
+              ("AA (mem:5)", dict(direction="aa", mem=5)),
+              ("AA (mem:10)", dict(direction="aa", mem=10))]
+
+
+def dm_leg(sscs, G, seeds=1, eps=1e-4, max_time=5.0, log=None):
+    """The LASSO family of Sec. V-C (48 (n, kappa, mu) combinations x `seeds`)
+    solved by each method to eps on the GPU, one problem at a time (data on
+    the device, setup not timed), with a time limit per solve standing for
+    the paper's failure rule.  Returns per-method success, sgm and the
+    Dolan-More profile.  RB memories above 16 are outside the engine's
+    limit, so 10 and 16 stand in for the paper's 50 and 100."""
+    import torch
+    probs = G.lasso_dm_family(seeds)
+    T = np.full((len(probs), len(DM_METHODS)), np.inf)
+    iters = np.zeros_like(T)
+    for ip, p in enumerate(probs):
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty(p.m, dtype=torch.float64, device="cuda:0")
+        s = torch.empty(p.m, dtype=torch.float64, device="cuda:0")
+        for js, (_, kw) in enumerate(DM_METHODS):
+            st = sscs.Settings(eps=eps, lam=1.5, c1=0.9999, q=0.999, cg_tol=1e-12, cg_adapt=0.2, cg_max=500,
+                               max_iters=10**7, max_time=max_time, data_on_device=True, **kw)
+            with sscs.Solver(p, st) as sv:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = sv.solve(out=(x, y, s))[3]
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            iters[ip, js] = info["iters"]
+            if info["status"] == sscs.SOLVED:
+                T[ip, js] = dt
+        if log:
+            log(f"dm {ip + 1}/{len(probs)} {p.name}: " + " ".join(f"{v:.3f}" for v in T[ip]))
+    R = performance_ratios(T)
+    taus = [1.0, 1.25, 1.5, 2.0, 4.0, 10.0, 100.0]
+    rho = performance_profile(R, taus)
+    out = {"workload": f"LASSO family of Sec. V-C: n in (631, 1000, 1585, 2512), m = ceil(n/5), kappa_A in "
+                       f"(10, 215, 4600, 1e5), mu in (0.01, 0.1, 1); {len(probs)} problems, eps {eps:g}, "
+                       f"time limit {max_time:g} s per solve",
+           "time_unit": "ms", "sgm_shift_ms": 10.0, "methods": {}}
+    for js, (name, _) in enumerate(DM_METHODS):
+        out["methods"][name] = {
+            "success": float(np.isfinite(T[:, js]).mean()),
+            "sgm10_ms": shifted_geometric_mean(T[:, js] * 1e3, 10.0),
+            "median_iters": float(np.median(iters[:, js])),
+            "rho": {f"{tau:g}": float(rho[i, js]) for i, tau in enumerate(taus)}}
+    return out
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters (run under rocprofv3 --pmc)."""
@@ -238,9 +320,18 @@ def main():
                     help="iteration cap of the PSD / exponential-cone leg (a large cap times a complete solve)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--dm", type=int, default=0, metavar="SEEDS",
+                    help="only run the Dolan-More / sgm comparison on the LASSO family (SEEDS problems per "
+                         "(n, kappa, mu) combination)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.dm > 0:
+        from paper_1903_06477_amd import generators as G
+        from paper_1903_06477_amd import sscs
+        res = dm_leg(sscs, G, seeds=args.dm, log=lambda s: print(s, file=sys.stderr, flush=True))
+        print(json.dumps(res))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "

@@ -276,6 +276,36 @@ def config5_instance(i: int, A: sp.csr_matrix) -> Problem:
     return lasso_socp(A, b, mu, name=f"lasso5_{i}")
 
 
+def lasso_dm_instance(n: int, kappa: float, mu: float, seed: int = 0) -> Problem:
+    """One problem of the LASSO benchmark family of Sec. V-C: A in R^{m x n}
+    with m = ceil(n/5) and condition number kappa (A = U diag(s) V^T, U, V
+    with orthonormal columns drawn from Gaussian matrices, s geometric from 1
+    down to 1/kappa), b = A x0 + 0.05 N(0,1) with 10%-sparse x0, weight mu
+    (the paper's n in {631, 1000, 1585, 2512}, kappa in {10, 215, 4600, 1e5},
+    mu in {0.01, 0.1, 1}).  The paper does not publish its generator; this one
+    fixes the stated sizes, conditioning and weights, with a dense A."""
+    rng = rng_for(6, seed)
+    md = int(math.ceil(n / 5))
+    U, _ = np.linalg.qr(rng.standard_normal((md, md)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, md)))
+    s = np.geomspace(1.0, 1.0 / kappa, md)
+    Ad = (U * s[None, :]) @ V.T
+    x0 = np.zeros(n)
+    k = max(1, int(round(0.1 * n)))
+    idx = rng.choice(n, size=k, replace=False)
+    x0[idx] = rng.standard_normal(k)
+    b = Ad @ x0 + 0.05 * rng.standard_normal(md)
+    return lasso_socp(sp.csr_matrix(Ad), b, mu, name=f"lasso_dm_n{n}_k{kappa:g}_mu{mu:g}_{seed}")
+
+
+def lasso_dm_family(seeds: int = 1) -> List[Problem]:
+    """The 48 (n, kappa, mu) combinations of the family, `seeds` problems each."""
+    return [lasso_dm_instance(n, kap, mu, 1000 * i + s)
+            for i, (n, kap, mu) in enumerate((n, kap, mu) for n in (631, 1000, 1585, 2512)
+                                             for kap in (10.0, 215.0, 4600.0, 1e5) for mu in (0.01, 0.1, 1.0))
+            for s in range(seeds)]
+
+
 # ---------------------------------------------------------------------------
 # mixed SDP / exponential-cone instance: sparse PCA blocks plus an
 # l1-regularised logistic regression, one block-diagonal problem

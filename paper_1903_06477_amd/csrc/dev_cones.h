@@ -411,14 +411,13 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
 // The same projection computed by a whole grid team, for blocks too large for
 // one workgroup to turn over quickly (the order-256 block of the sparse-PCA
 // instance): a two-sided *block* Jacobi method.  The indices are cut into
-// tiles of kPsdTile; each round pairs the tiles round-robin, and workgroup w
-// diagonalises pair w's 2-tile principal submatrix in LDS (cyclic Jacobi to
-// the rounding level), producing an orthogonal Q_w.  Then, spread over the
-// whole team, the rows of A and of Vt are turned by Q^T (A' = Q^T A,
-// Vt' = Q^T Vt) and the columns of A' by Q (A'' = A' Q) -- dense products of
-// 2-tile panels.  Three team barriers per round and k/kPsdTile - 1 rounds per
-// sweep, instead of one barrier per round over k - 1 rounds.  Warm start and
-// stopping rule as in psd_project_block.
+// tiles of kPsdTile; each round pairs the tiles round-robin, workgroup w
+// diagonalises (approximately: one inner sweep) pair w's 2-tile principal
+// submatrix in LDS, producing an orthogonal Q_w, and the team turns A into
+// Q^T A Q and Vt into Q^T Vt, block by block.  One team barrier per round and
+// k/kPsdTile - 1 rounds per sweep, instead of one barrier per round over
+// k - 1 rounds (the round structure is described at psd_project_team).  Warm
+// start and stopping rule as in psd_project_block.
 constexpr int kPsdTile = 8;
 constexpr int kPsdSub = 2 * kPsdTile;
 

@@ -440,7 +440,7 @@ __device__ int setup_gdelta(Team& tm, Shared& sh, Prob& P, const Vecs& V, double
 // uncorrected linear-step output in V.ut and tau (and stored back corrected);
 // returns ||R u||^2 and leaves ||u||^2 in sh.out[1].
 template <typename Team>
-__device__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, double tau) {
+__device__ __noinline__ double residual_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, double tau) {
     double acc = 0.0, au = 0.0;
     project_C(tm, sh, P.n, P.N, P.K,
               [&](int i) { return 2.0 * corrected(P, V.ut, tau, i) - V.u[i]; },
@@ -469,7 +469,7 @@ struct Term {
 // The measures land in sh.term (LDS), read by every thread after the call,
 // which keeps them out of the registers of the long-lived solve loop.
 template <typename Team>
-__device__ void termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+__device__ __noinline__ void termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
                                  bool timed_out) {
     const int n = P.n, m = P.m;
     const double tau = V.ub[P.N - 1];
@@ -563,7 +563,7 @@ struct DirState {
 // Anderson: push the pending pair into the ring, update the Gram matrix and
 // solve for t; then d = -Ru - (Z - Xi) t, fused with the K0 update of u.
 template <typename Team>
-__device__ void direction_aa(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+__device__ __noinline__ void direction_aa(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
                              DirState& ds, bool k0) {
     const int N = P.N, mem = S.mem;
     int slot = -1;
@@ -635,7 +635,7 @@ __device__ void direction_aa(Team& tm, Shared& sh, const Prob& P, const Vecs& V,
 // all inner products replaces the m' sequential dot/axpy steps.  W holds
 // <z_i, zt_j> and is updated with every new pair.
 template <typename Team>
-__device__ void direction_rb(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+__device__ __noinline__ void direction_rb(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
                              DirState& ds, bool k0) {
     const int N = P.N, mem = S.mem;
     const int mp = ds.rb_m;
@@ -782,6 +782,26 @@ __device__ void write_trace(Team& tm, const Vecs& V, long long nu, double res, i
     }
 }
 
+// Trial point w = u + a d of the line search (Algorithm 1): w~ = u~ + a d~ by
+// linearity (Sec. IV-B), R w = w~ - Pi_C(2 w~ - w) into V.Rw; leaves ||R w||^2
+// in sh.out[0] and <R w, d> in sh.out[1].  Out of line, like the other
+// passes, so the solve loop's registers stay its own.
+template <typename Team>
+__device__ __noinline__ void trial_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, double a, double tau_d) {
+    double acc_w = 0.0, acc_d = 0.0;
+    project_C(tm, sh, P.n, P.N, P.K,
+              [&](int i) { return 2.0 * (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - (V.u[i] + a * V.d[i]); },
+              [&](int i, double v) {
+                  const double rw = (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - v;
+                  V.Rw[i] = rw;
+                  acc_w += rw * rw;
+                  acc_d += rw * V.d[i];
+              });
+    put(sh, 0, acc_w);
+    put(sh, 1, acc_d);
+    tm.reduce(sh, 2);
+}
+
 template <typename TV, typename Team>
 __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S, Result* res) {
     const int n = P.n, m = P.m, N = P.N;
@@ -876,20 +896,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         double coef = 0.0;
         for (ls = 0; ls < S.ls_max; ++ls) {
             const double a = alpha;
-            double acc_w = 0.0, acc_d = 0.0;
-            project_C(tm, sh, n, N, P.K,
-                      [&](int i) {
-                          return 2.0 * (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - (V.u[i] + a * V.d[i]);
-                      },
-                      [&](int i, double v) {
-                          const double rw = (V.ut[i] + a * corrected(P, V.dt, tau_d, i)) - v;
-                          V.Rw[i] = rw;
-                          acc_w += rw * rw;
-                          acc_d += rw * V.d[i];
-                      });
-            put(sh, 0, acc_w);
-            put(sh, 1, acc_d);
-            tm.reduce(sh, 2);
+            trial_pass(tm, sh, P, V, a, tau_d);
             const double nRw2 = sh.out[0];
             const double nRw = sqrt(nRw2);
             const double rho = nRw2 - a * sh.out[1];        // <Rw, u - T w>, T w = w - Rw

@@ -435,6 +435,11 @@ __device__ int setup_gdelta(Team& tm, Shared& sh, Prob& P, const Vecs& V, double
 }
 
 // ------------------------------------------------------------------ passes
+//
+// The passes of an outer iteration are out-of-line functions: the solve loop
+// that calls them then holds only its own few values across the calls, and
+// each pass gets a register allocation of its own (inlined, they made the
+// solve kernel spill heavily).
 
 // u-bar = Pi_C(2 u~ - u), R u = u~ - u-bar, where u~ is formed from the
 // uncorrected linear-step output in V.ut and tau (and stored back corrected);

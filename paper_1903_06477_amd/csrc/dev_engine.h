@@ -473,9 +473,10 @@ struct Term {
 // Sec. IV-C.  sig-bar = psi-bar - 2 psi~ + psi; candidate (chi, psi, sig)-bar / tau-bar.
 // The measures land in sh.term (LDS), read by every thread after the call,
 // which keeps them out of the registers of the long-lived solve loop.
+// Partial sums of the termination measures (Sec. IV-C) into slots 0..6; the
+// candidate is the barred iterate.  Returns its tau.
 template <typename Team>
-__device__ __noinline__ void termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
-                                 bool timed_out) {
+__device__ __forceinline__ double term_partials(Team& tm, Shared& sh, const Prob& P, const Vecs& V, bool timed_out) {
     const int n = P.n, m = P.m;
     const double tau = V.ub[P.N - 1];
     double a_p = 0.0, a_u = 0.0, a_d = 0.0, a_i = 0.0, a_cx = 0.0, a_by = 0.0;
@@ -500,31 +501,41 @@ __device__ __noinline__ void termination_pass(Team& tm, Shared& sh, const Prob& 
     put(sh, 4, a_cx);
     put(sh, 5, a_by);
     put(sh, 6, (tm.rank() == 0 && timed_out) ? 1.0 : 0.0);
-    tm.reduce(sh, 7);
-    if (threadIdx.x == 0) {
-        Term T;
-        const double cx = sh.out[4], by = sh.out[5];
-        T.tau = tau;
-        T.cx = cx;
-        T.by = by;
-        T.timeout = sh.out[6] > 0.0;
-        T.pr = T.dr = T.gap = T.ic = T.uc = INFINITY;
-        T.pobj = T.dobj = NAN;
-        if (tau > 0.0) {
-            T.pr = sqrt(sh.out[0]) / tau / (1.0 + P.nb);
-            T.dr = sqrt(sh.out[2]) / tau / (1.0 + P.nc);
-            T.gap = fabs(cx + by) / tau / (1.0 + fabs(cx) / tau + fabs(by) / tau);
-            T.pobj = cx / tau;
-            T.dobj = -by / tau;
-        }
-        if (by < 0.0) T.ic = P.nb * sqrt(sh.out[3]) / (-by);
-        if (cx < 0.0) T.uc = P.nc * sqrt(sh.out[1]) / (-cx);
-        T.status = 0;
-        if (tau > 0.0 && T.pr <= S.eps && T.dr <= S.eps && T.gap <= S.eps) T.status = ST_SOLVED;
-        else if (T.ic < S.eps) T.status = ST_INFEASIBLE;
-        else if (T.uc < S.eps) T.status = ST_UNBOUNDED;
-        *reinterpret_cast<Term*>(sh.term) = T;
+    return tau;
+}
+
+// The measures and status from the reduced slots 0..6 into sh.term (thread 0).
+__device__ __forceinline__ void term_finish(Shared& sh, const Prob& P, const Params& S, double tau) {
+    Term T;
+    const double cx = sh.out[4], by = sh.out[5];
+    T.tau = tau;
+    T.cx = cx;
+    T.by = by;
+    T.timeout = sh.out[6] > 0.0;
+    T.pr = T.dr = T.gap = T.ic = T.uc = INFINITY;
+    T.pobj = T.dobj = NAN;
+    if (tau > 0.0) {
+        T.pr = sqrt(sh.out[0]) / tau / (1.0 + P.nb);
+        T.dr = sqrt(sh.out[2]) / tau / (1.0 + P.nc);
+        T.gap = fabs(cx + by) / tau / (1.0 + fabs(cx) / tau + fabs(by) / tau);
+        T.pobj = cx / tau;
+        T.dobj = -by / tau;
     }
+    if (by < 0.0) T.ic = P.nb * sqrt(sh.out[3]) / (-by);
+    if (cx < 0.0) T.uc = P.nc * sqrt(sh.out[1]) / (-cx);
+    T.status = 0;
+    if (tau > 0.0 && T.pr <= S.eps && T.dr <= S.eps && T.gap <= S.eps) T.status = ST_SOLVED;
+    else if (T.ic < S.eps) T.status = ST_INFEASIBLE;
+    else if (T.uc < S.eps) T.status = ST_UNBOUNDED;
+    *reinterpret_cast<Term*>(sh.term) = T;
+}
+
+template <typename Team>
+__device__ __noinline__ void termination_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                                              bool timed_out) {
+    const double tau = term_partials(tm, sh, P, V, timed_out);
+    tm.reduce(sh, 7);
+    if (threadIdx.x == 0) term_finish(sh, P, S, tau);
     __syncthreads();
 }
 
@@ -567,10 +578,15 @@ struct DirState {
 
 // Anderson: push the pending pair into the ring, update the Gram matrix and
 // solve for t; then d = -Ru - (Z - Xi) t, fused with the K0 update of u.
+// Anderson (Sec. IV-D-2), in three parts so that the dot products can share
+// a reduction with the termination check.  (1) Push the pending (z, xi) pair
+// into the FIFO memory and put <Xi_i, Ru> (and <Xi_i, Xi_new> for a new
+// column) into slots base.. (same element-to-thread map as the copy: no
+// barrier needed); returns the new column's slot or -1.
 template <typename Team>
-__device__ __noinline__ void direction_aa(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
-                             DirState& ds, bool k0) {
-    const int N = P.N, mem = S.mem;
+__device__ __forceinline__ int aa_push_dots(Team& tm, Shared& sh, const Vecs& V, const Params& S, DirState& ds, int N,
+                                            int base) {
+    const int mem = S.mem;
     int slot = -1;
     if (ds.pend) {
         slot = ds.aa_head;
@@ -585,22 +601,12 @@ __device__ __noinline__ void direction_aa(Team& tm, Shared& sh, const Prob& P, c
         if (ds.aa_k < mem) ds.aa_k++;
     }
     const int k = ds.aa_k;
-    if (k == 0) {
-        for (int e = tm.rank(); e < N; e += tm.size()) {
-            const double d = -V.Ru[e];
-            V.d[e] = d;
-            if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
-        }
-        tm.sync();
-        return;
-    }
-    // dots: <Xi_i, Ru> for every slot, <Xi_i, Xi_slot> for the new column
-    // (same element-to-thread map as the copy above: no barrier needed)
+    if (k == 0) return slot;
     for (int i = 0; i < k; ++i) {
         const double* Yi = V.Yb + (size_t)i * N;
         double acc = 0.0;
         for (int e = tm.rank(); e < N; e += tm.size()) acc += Yi[e] * V.Ru[e];
-        put(sh, i, acc);
+        put(sh, base + i, acc);
     }
     if (slot >= 0) {
         const double* Ys = V.Yb + (size_t)slot * N;
@@ -608,23 +614,35 @@ __device__ __noinline__ void direction_aa(Team& tm, Shared& sh, const Prob& P, c
             const double* Yi = V.Yb + (size_t)i * N;
             double acc = 0.0;
             for (int e = tm.rank(); e < N; e += tm.size()) acc += Yi[e] * Ys[e];
-            put(sh, k + i, acc);
+            put(sh, base + k + i, acc);
         }
     }
-    tm.reduce(sh, slot >= 0 ? 2 * k : k);
-    if (threadIdx.x == 0) {
-        if (slot >= 0)
-            for (int i = 0; i < k; ++i) {
-                sh.G[slot * MEMMAX + i] = sh.out[k + i];
-                sh.G[i * MEMMAX + slot] = sh.out[k + i];
-            }
-        double tr = 0.0;
-        for (int i = 0; i < k; ++i) tr += sh.G[i * MEMMAX + i];
-        const bool ok = small_chol_solve(sh.G, MEMMAX, k, S.aa_reg * tr / k, sh.out, sh.coef, sh.L);
-        if (!ok)
-            for (int i = 0; i < k; ++i) sh.coef[i] = 0.0;
-    }
-    __syncthreads();
+    return slot;
+}
+
+// Slots the dot products of aa_push_dots take.
+__device__ __forceinline__ int aa_slots(int k, int slot) { return k == 0 ? 0 : (slot >= 0 ? 2 * k : k); }
+
+// (2) Thread 0: the Gram matrix's new column and t from the reduced slots
+// base.. ((Xi^T Xi + mu I) t = Xi^T Ru, by Cholesky) into sh.coef.
+__device__ __forceinline__ void aa_gram(Shared& sh, const Params& S, int k, int slot, int base) {
+    if (slot >= 0)
+        for (int i = 0; i < k; ++i) {
+            sh.G[slot * MEMMAX + i] = sh.out[base + k + i];
+            sh.G[i * MEMMAX + slot] = sh.out[base + k + i];
+        }
+    double tr = 0.0;
+    for (int i = 0; i < k; ++i) tr += sh.G[i * MEMMAX + i];
+    const bool ok = small_chol_solve(sh.G, MEMMAX, k, S.aa_reg * tr / k, sh.out + base, sh.coef, sh.L);
+    if (!ok)
+        for (int i = 0; i < k; ++i) sh.coef[i] = 0.0;
+}
+
+// (3) d = -Ru - sum_i (Z_i - Y_i) t_i (d = -Ru with an empty memory); a K0
+// step applies it at once.
+template <typename Team>
+__device__ __noinline__ void aa_apply(Team& tm, Shared& sh, const Prob& P, const Vecs& V, int k, bool k0) {
+    const int N = P.N;
     for (int e = tm.rank(); e < N; e += tm.size()) {
         double d = -V.Ru[e];
         for (int i = 0; i < k; ++i) d -= (V.Zb[(size_t)i * N + e] - V.Yb[(size_t)i * N + e]) * sh.coef[i];
@@ -632,6 +650,24 @@ __device__ __noinline__ void direction_aa(Team& tm, Shared& sh, const Prob& P, c
         if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
     }
     tm.sync();
+}
+
+// The termination check and Anderson's dot products in one pass and one
+// reduction (they depend only on the residual pass's output, not on each
+// other): one barrier fewer per iteration.  aa_apply follows once the
+// status is known.
+template <typename Team>
+__device__ __noinline__ void termination_aa_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                                                 DirState& ds, bool timed_out) {
+    const double tau = term_partials(tm, sh, P, V, timed_out);
+    const int slot = aa_push_dots(tm, sh, V, S, ds, P.N, 7);
+    const int k = ds.aa_k;
+    tm.reduce(sh, 7 + aa_slots(k, slot));
+    if (threadIdx.x == 0) {
+        term_finish(sh, P, S, tau);
+        if (k > 0) aa_gram(sh, S, k, slot, 7);
+    }
+    __syncthreads();
 }
 
 // Restarted Broyden (Algorithm 2).  H = (I + zt_m z_m^T) ... (I + zt_1 z_1^T);
@@ -845,7 +881,8 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             tol = fmin(1e-3, fmax(S.cg_tol, S.cg_adapt * nRu / fmax(nu_, 1e-300)));
         }
         const bool late = S.max_ticks > 0 && (wall_clock64() - t_start) > S.max_ticks;
-        termination_pass(tm, sh, P, V, S, late);
+        if (S.direction == DIR_AA) termination_aa_pass(tm, sh, P, V, S, ds, late);
+        else termination_pass(tm, sh, P, V, S, late);
         if (nu == 0) eta0 = eta = r_safe = nRu;
         status = T.status;
         if (!isfinite(nRu)) status = ST_NUMERICAL;
@@ -855,7 +892,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         if (status) { write_trace(tm, V, nu, nRu, -1, 0); break; }
         const bool k0 = nRu <= S.c0 * eta;
         if (S.direction == DIR_AA) {
-            direction_aa(tm, sh, P, V, S, ds, k0);
+            aa_apply(tm, sh, P, V, ds.aa_k, k0);            // its dot products went with the termination check
         } else if (S.direction == DIR_RB) {
             direction_rb(tm, sh, P, V, S, ds, k0);
         } else {

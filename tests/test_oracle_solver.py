@@ -266,6 +266,109 @@ def test_unbounded_certificate(seed):
     assert s.min() >= -1e-12
 
 
+def _planted_kkt_lp(seed, m=9, n=4):
+    """LP min c'x, Ax + s = b, s >= 0 with a planted KKT point: y* and s*
+    nonnegative with disjoint supports, b = A x* + s*, c = -A'y*; then the
+    primal and dual residuals vanish and c'x* + b'y* = y*'s* = 0."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    x = rng.standard_normal(n)
+    y = np.zeros(m)
+    s = np.zeros(m)
+    act = rng.permutation(m)[: m // 2]
+    y[act] = rng.uniform(0.5, 2.0, act.size)
+    rest = np.setdiff1d(np.arange(m), act)
+    s[rest] = rng.uniform(0.5, 2.0, rest.size)
+    return DirectLinSys(A, A @ x + s, -A.T @ y), x, y, s
+
+
+def _hsde_points(x, y, s, tau, ut_y):
+    """(u, u~, u-bar) whose termination read-out is (x, y, s) scaled by tau:
+    u-bar = (tau x, tau y, tau) and the slack tau s = y-bar - 2 u~_y + u_y
+    (Sec. IV-C), for any choice of u~_y."""
+    n, m = x.size, y.size
+    ub = np.concatenate([tau * x, tau * y, [tau]])
+    ut = np.concatenate([np.zeros(n), ut_y, [tau]])
+    u = np.concatenate([np.zeros(n), tau * s - tau * y + 2.0 * ut_y, [tau]])
+    return u, ut, ub
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.37, 12.5])
+def test_termination_reads_out_planted_kkt_point(tau):
+    """At a planted KKT point pr = dr = gap = 0 (up to rounding) for any
+    tau > 0 (the read-out divides by tau), the status is SOLVED and
+    (x, y, s) = (chi, psi, sigma) / tau."""
+    lin, x, y, s = _planted_kkt_lp(3)
+    ut_y = np.random.default_rng(4).standard_normal(y.size)
+    u, ut, ub = _hsde_points(x, y, s, tau, ut_y)
+    st, info, (xo, yo, so) = S.termination(lin, u, ut, ub, 1e-9)
+    assert st == S.SOLVED
+    assert max(info["pr"], info["dr"], info["gap"]) <= 1e-13
+    np.testing.assert_allclose(xo, x, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(yo, y, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(so, s, rtol=0, atol=1e-13)
+    assert info["pobj"] == pytest.approx(lin.c @ x, abs=1e-12)
+    assert info["dobj"] == pytest.approx(-lin.b @ y, abs=1e-12)
+
+
+def test_termination_residuals_of_known_perturbations():
+    """Moving x* by delta along coordinate j leaves dr at 0 and makes
+    pr = |delta| ||A e_j|| / (1 + ||b||) and the gap |delta c_j| over
+    1 + |c'x| + |b'y|; moving y* by delta along an inactive row i makes
+    dr = |delta| ||A' e_i|| / (1 + ||c||).  Neither reaches eps = 1e-6 here,
+    so the status is 0 (continue)."""
+    lin, x, y, s = _planted_kkt_lp(5)
+    A = lin.A.toarray()
+    b, c = lin.b, lin.c
+    delta, j = 0.25, 2
+    xp = x.copy(); xp[j] += delta
+    st, info, _ = S.termination(lin, *_hsde_points(xp, y, s, 2.0, np.zeros(y.size)), 1e-6)
+    assert st == 0
+    assert info["pr"] == pytest.approx(abs(delta) * np.linalg.norm(A[:, j]) / (1 + np.linalg.norm(b)), rel=1e-12)
+    assert info["dr"] <= 1e-14
+    cx, by = c @ xp, b @ y
+    assert info["gap"] == pytest.approx(abs(delta * c[j]) / (1 + abs(cx) + abs(by)), rel=1e-10)
+    i = int(np.flatnonzero(y == 0)[0])
+    yp = y.copy(); yp[i] += delta
+    st, info, _ = S.termination(lin, *_hsde_points(x, yp, s, 1.0, np.zeros(y.size)), 1e-6)
+    assert st == 0
+    assert info["dr"] == pytest.approx(abs(delta) * np.linalg.norm(A[i]) / (1 + np.linalg.norm(c)), rel=1e-12)
+    assert info["pr"] <= 1e-14
+
+
+def test_termination_certificates_at_tau_zero():
+    """tau = 0: a psi with A'psi = 0, psi >= 0 and b'psi < 0 is a certificate
+    of primal infeasibility (ic = 0), returned as y = psi / (-b'psi); a chi
+    with A chi + sigma = 0, sigma >= 0 and c'chi < 0 certifies unboundedness
+    (uc = 0), returned as (x, s) = (chi, sigma) / (-c'chi)."""
+    rng = np.random.default_rng(7)
+    # infeasible: rows 0 and 1 are a'x + s0 = 1 and -a'x + s1 = -2 (sum: s0 + s1 = -1)
+    a = rng.standard_normal(3)
+    A = np.vstack([a, -a, rng.standard_normal((2, 3))])
+    b = np.array([1.0, -2.0, 1.0, 1.0])
+    lin = DirectLinSys(A, b, rng.standard_normal(3))
+    psi = np.array([3.0, 3.0, 0.0, 0.0])
+    ub = np.concatenate([np.zeros(3), psi, [0.0]])
+    z = np.zeros(7)
+    st, info, (xo, yo, so) = S.termination(lin, z, z, ub, 1e-8)
+    assert st == S.INFEASIBLE
+    assert info["ic"] <= 1e-15
+    np.testing.assert_allclose(yo, psi / 3.0, rtol=0, atol=1e-15)
+    assert lin.b @ yo == pytest.approx(-1.0, abs=1e-15)
+    assert np.isnan(xo).all() and np.isnan(so).all()
+    # unbounded: min -x0 with x0 free of every row: A chi = 0 for chi = e0
+    A = np.hstack([np.zeros((4, 1)), rng.standard_normal((4, 2))])
+    lin = DirectLinSys(A, rng.uniform(1, 2, 4), np.array([-2.0, 0.5, 0.5]))
+    chi = np.array([1.5, 0.0, 0.0])
+    ub = np.concatenate([chi, np.zeros(4), [0.0]])
+    st, info, (xo, yo, so) = S.termination(lin, z, z, ub, 1e-8)
+    assert st == S.UNBOUNDED
+    assert info["uc"] <= 1e-15
+    np.testing.assert_allclose(xo, chi / 3.0, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(so, np.zeros(4), rtol=0, atol=1e-15)
+    assert np.isnan(yo).all()
+
+
 def _lasso_fista(Ad, bd, mu, iters=200000, tol=1e-13):
     A = Ad.toarray()
     L = np.linalg.norm(A, 2) ** 2

@@ -251,20 +251,40 @@ __global__ void k_scatter_t(const int* __restrict__ rp, const int* __restrict__ 
         }
 }
 
-// Sorts each row of the transpose by column (insertion sort, one thread per
-// row) so that its order, and every sum over it, is deterministic; then the
-// Jacobi diagonal 1 / (1 + ||row||^2).
+// Shellsort gaps of Ciura (2001, "Best increments for the average case of
+// Shellsort"), extended by the factor 2.25, up to the int range.
+__constant__ int kShellGaps[26] = {1,       4,        10,       23,        57,        132,       301,
+                                   701,     1750,     3937,     8858,      19930,     44842,     100894,
+                                   227011,  510774,   1149241,  2585792,   5818032,   13090572,  29453787,
+                                   66271020, 149109795, 335497038, 754868335, 1698453753};
+
+// Sorts each row of the transpose by column (Shellsort, one thread per row:
+// the scatter leaves a long column of A, thousands of entries, in arbitrary
+// order, where insertion sort's quadratic count of dependent moves took
+// hundreds of ms), so that its order, and every sum over it, is
+// deterministic: the keys of a row are distinct, so the sorted order is
+// unique.  Then the Jacobi diagonal 1 / (1 + ||row||^2).
 __global__ void k_sort_rows(const int* __restrict__ trp, int rows, int* __restrict__ tci, double* __restrict__ tv,
                             double* __restrict__ dinv) {
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         const int k0 = trp[r], k1 = trp[r + 1];
-        for (int k = k0 + 1; k < k1; ++k) {
-            const int key = tci[k];
-            const double val = tv[k];
-            int j = k - 1;
-            while (j >= k0 && tci[j] > key) { tci[j + 1] = tci[j]; tv[j + 1] = tv[j]; --j; }
-            tci[j + 1] = key;
-            tv[j + 1] = val;
+        const int len = k1 - k0;
+        int gi = 0;
+        while (gi < 25 && kShellGaps[gi + 1] < len) ++gi;
+        for (; gi >= 0; --gi) {
+            const int g = kShellGaps[gi];
+            for (int k = k0 + g; k < k1; ++k) {
+                const int key = tci[k];
+                const double val = tv[k];
+                int j = k - g;
+                while (j >= k0 && tci[j] > key) {
+                    tci[j + g] = tci[j];
+                    tv[j + g] = tv[j];
+                    j -= g;
+                }
+                tci[j + g] = key;
+                tv[j + g] = val;
+            }
         }
         double s = 0.0;
         for (int k = k0; k < k1; ++k) s += tv[k] * tv[k];

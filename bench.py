@@ -104,6 +104,35 @@ def bench_settings(sscs, max_iters):
                          data_on_device=True)
 
 
+def host_io_leg(sscs, prob, stream):
+    """The same workload through host buffers: the instance is uploaded and
+    set up on the device (transpose, Jacobi diagonal, g and delta), solved,
+    and x, y, s are copied back to host memory.  Reports the rate of create +
+    solve (a fresh instance per solve) and of solve alone with host outputs;
+    `value` is the device-resident rate, these are context."""
+    import torch
+    st = bench_settings(sscs, 20000)
+    st.data_on_device = False
+    A = prob.A
+    up = A.nnz * 12 + (A.shape[0] + 1) * 4 + 8 * (prob.m + prob.n)
+    down = 8 * (prob.n + 2 * prob.m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv = sscs.Solver(prob, st, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = sv.solve()[3]
+    t2 = time.perf_counter()
+    info2 = sv.solve()[3]
+    t3 = time.perf_counter()
+    sv.close()
+    ok = info["status"] == sscs.SOLVED and info2["status"] == sscs.SOLVED
+    return {"create_s": t1 - t0, "solve_s": t2 - t1, "second_solve_s": t3 - t2,
+            "create_and_solve_per_s": 1.0 / (t2 - t0) if ok else 0.0,
+            "solve_host_out_per_s": 1.0 / (t3 - t2) if ok else 0.0,
+            "upload_bytes": up, "download_bytes": down, "iters": info2["iters"]}
+
+
 def batched_leg(sscs, G, count=4096, precision="fp64", probs=None):
     """The batched LASSO family: `count` independent instances (n in 20..400,
     rows in n/2..2n, density 5%) in one persistent launch, AA memory 5,
@@ -316,6 +345,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-sdp", action="store_true", help="skip the PSD / exponential-cone leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain DRS leg")
+    ap.add_argument("--no-host-io", action="store_true", help="skip the host-buffer (PCIe-inclusive) leg")
     ap.add_argument("--sdp-iters", type=int, default=150,
                     help="iteration cap of the PSD / exponential-cone leg (a large cap times a complete solve)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -421,6 +451,8 @@ def main():
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }
     solver.close()
+    if not args.no_host_io:
+        out["host_io"] = host_io_leg(sscs, prob, stream)
     if not args.no_mixed:
         # the same workload with the mixed-precision linear step
         stm = bench_settings(sscs, args.max_iters)

@@ -260,8 +260,8 @@ __constant__ int kShellGaps[26] = {1,       4,        10,       23,        57,  
 
 // Sorts each row of the transpose by column (Shellsort, one thread per row:
 // the scatter leaves a long column of A, thousands of entries, in arbitrary
-// order, where insertion sort's quadratic count of dependent moves took
-// hundreds of ms), so that its order, and every sum over it, is
+// order, where insertion sort's quadratic count of dependent moves took over a
+// second), so that its order, and every sum over it, is
 // deterministic: the keys of a row are distinct, so the sorted order is
 // unique.  Then the Jacobi diagonal 1 / (1 + ||row||^2).
 __global__ void k_sort_rows(const int* __restrict__ trp, int rows, int* __restrict__ tci, double* __restrict__ tv,

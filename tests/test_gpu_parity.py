@@ -81,6 +81,48 @@ def test_spmv_matches_scipy(sscs, maker):
         np.testing.assert_allclose(s.spmv(y, transpose=True), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
 
 
+def _long_column_problem(seed):
+    """A with columns of 30000, 5000 and 700 entries (rows of the transpose
+    that the row sort orders with several Shellsort gaps) plus a sparse rest,
+    values spread over 16 decades so that sums depend on their order."""
+    r = np.random.default_rng(seed)
+    m, n = 30000, 40
+    rows, cols = [np.arange(m)], [np.zeros(m, dtype=np.int64)]
+    for j, cnt in [(1, 5000), (2, 700)]:
+        rows.append(r.choice(m, cnt, replace=False))
+        cols.append(np.full(cnt, j))
+    rest = sp.random(m, n - 3, density=0.002, random_state=seed, format="coo")
+    rows.append(rest.row)
+    cols.append(rest.col + 3)
+    ri, ci = np.concatenate(rows), np.concatenate(cols)
+    vals = r.standard_normal(ri.size) * 10.0 ** r.uniform(-8, 8, ri.size)
+    A = sp.csr_matrix((vals, (ri, ci)), shape=(m, n))
+    A.sum_duplicates()
+    cone = G.Cone(z=0, l=m, q=[], s=[], ep=0)
+    return G.Problem(A=A, b=r.standard_normal(m), c=r.standard_normal(n), cone=cone, name="long_columns")
+
+
+def test_transpose_rows_with_long_columns(sscs):
+    """The device-built transpose of a matrix with long columns: A^T y equals
+    scipy's within the summation error bound of each row, and two
+    independently set-up instances give bitwise equal products, which needs
+    each row of the transpose in the same (sorted) order whatever order the
+    scatter left it in."""
+    prob = _long_column_problem(3)
+    y = np.random.default_rng(4).standard_normal(prob.m)
+    ref = prob.A.T @ y
+    # any summation order stays within (len + 1) u sum|a_ij y_i| of the exact
+    # value (recursive summation bound), scipy's result as well
+    lens = np.diff(prob.A.tocsc().indptr)
+    bound = 2 * (lens + 1) * 2.0 ** -53 * (abs(prob.A).T @ np.abs(y))
+    outs = []
+    for _ in range(2):
+        with sscs.Solver(prob) as s:
+            outs.append(s.spmv(y, transpose=True))
+    assert np.all(np.abs(outs[0] - ref) <= bound)
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_project_dual_cone_matches_oracle(sscs, seed):
     from oracle.cones import proj_dual_cone

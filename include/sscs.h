@@ -120,6 +120,14 @@ typedef struct {
                                      points u~ + alpha d~ carry the error of u~ alone;
                                      0 = at the relative tolerance of its own right-hand
                                      side (a much tighter absolute accuracy) */
+    int32_t check_every;          /* termination test (Sec. IV-C) every check_every-th
+                                     iteration and at the iteration cap; 0 or 1: every
+                                     iteration.  A time limit is noticed at a tested
+                                     iteration. */
+    int32_t workgroups;           /* 0: the library sizes the grid; k >= 1: single-instance
+                                     solves run on k workgroups (1: the one-workgroup
+                                     kernel), capped by what stays co-resident.  Read at
+                                     create; update_settings may not change it. */
 } sscs_settings;
 
 /* Result of a solve. */
@@ -141,9 +149,11 @@ typedef struct sscs_work  sscs_work;
 typedef struct sscs_batch sscs_batch;
 
 /* Fills *st with defaults: eps 1e-6, AA mem 5, c0 0.99 (0.1 is the paper's
- * advice for RB, Sec. IV-D-1), c1 0.99, q 0.99, sigma 0.01, lambda 1,
+ * advice for RB, Sec. IV-D-1), c1 0.9999, q 0.999, sigma 0.01, lambda 1.5,
  * thetabar 0.1, ls_max 10, FP64, cg_tol 1e-10, cg_max 500, aa_reg 1e-12,
- * cg_adapt 0, cg_d_match 1. */
+ * cg_adapt 0, cg_d_match 1, check_every 1, workgroups 0.  Algorithm 1 leaves
+ * c1, q and lambda open; with c1 = q = 0.99 and lambda = 1 Anderson can stall
+ * in K2 steps and restarted Broyden in steps at the backtracking cap. */
 int sscs_default_settings(sscs_settings *st);
 
 /* Validates and uploads (A, b, c, K), builds A^T and the per-instance
@@ -186,17 +196,22 @@ int sscs_spmv_bench(sscs_work *w, int32_t transpose, int32_t reps, double *ms);
 
 /* Per-iteration record of the last solve (settings.record_trace != 0):
  * res[i] = ||R u^i||, kind[i] in {0:K0, 1:K1, 2:K2, 3:KM, -1: stopped},
- * ls[i] = backtracks.  Copies min(cap, iterations + 1) records; *count gets
- * the number available. */
+ * ls[i] = backtracks, eta[i] and r_safe[i] = the safeguards of Algorithm 1
+ * after the step of iteration i.  Copies min(cap, iterations + 1) records
+ * into every non-NULL output (host arrays); *count gets the number available. */
 int sscs_get_trace(sscs_work *w, int64_t cap, double *res, int32_t *kind, int32_t *ls,
-                   int64_t *count);
+                   double *eta, double *r_safe, int64_t *count);
 
 /* Batched solves: count independent instances in one persistent launch, one
  * workgroup per instance taken from a device work queue.  Instances whose
  * rowptr, colind and val pointers equal those of instance 0 share one device
  * copy of A.  Packed vectors concatenate per-instance vectors in instance
  * order (u0: N_i each; x: n_i; y, s: m_i).  Settings (including
- * data_on_device) are shared.  The batched engine computes in FP64. */
+ * data_on_device) are shared; settings.workgroups does not apply.  The
+ * batched engine runs the FP64 operator (SSCS_E_UNSUPPORTED for
+ * SSCS_PREC_MIXED).  PSD blocks of a batched instance are limited to order 64
+ * (SSCS_E_UNSUPPORTED above).  Each instance's time limit (max_time_s) runs
+ * from the moment a workgroup takes it from the queue. */
 int sscs_batch_create(int32_t count, const sscs_data *data, const sscs_cone *cones,
                       const sscs_settings *st, void *hip_stream, sscs_batch **out);
 /* Replaces b and c of every instance (packed like y and x). */

@@ -24,6 +24,9 @@ Readings of silent or garbled points (each named where it is used):
   R10 returned triplet is the barred one; certificates normalised to
       <b, y> = -1 and <c, x> = -1.  R11 Euclidean norms throughout.
   R12 precedence: SOLVED, then INFEASIBLE, then UNBOUNDED.
+  R17 c0, c1, q, sigma, lambda are inputs of Algorithm 1 without values in the
+      paper except c0 = 0.1 for restarted Broyden (Sec. IV-D-1); defaults
+      c0 0.99 (0.1 for RB), c1 0.9999, q 0.999, sigma 0.01, lambda 1.5.
 """
 from __future__ import annotations
 
@@ -48,10 +51,10 @@ class Settings:
     direction: str = "aa"          # "rb" (Algorithm 2), "aa" (Anderson), "none" (d = -Ru), "zero" (d = 0)
     mem: int = 5
     c0: Optional[float] = None     # default 0.1 for RB (Sec. IV-D-1), 0.99 for AA
-    c1: float = 0.99
-    q: float = 0.99
-    sigma: float = 0.01
-    lam: float = 1.0
+    c1: float = 0.9999             # c1, q, lam: reading R17 (the paper leaves them open); with
+    q: float = 0.999               # c1 = q = 0.99 and lam = 1 Anderson stalls in K2 steps and
+    sigma: float = 0.01            # restarted Broyden in backtracking-cap steps on some SOCPs
+    lam: float = 1.5
     thetabar: float = 0.1
     ls_max: int = 10
     max_iters: int = 10000
@@ -281,7 +284,8 @@ def solve(prob, settings: Settings = Settings(), u0=None, lin: DirectLinSys = No
             d = np.zeros_like(Ru)
         else:
             d = -Ru
-        rec = dict(nu=nu, res=nRu, pr=info["pr"], dr=info["dr"], gap=info["gap"])
+        rec = dict(nu=nu, res=nRu, pr=info["pr"], dr=info["dr"], gap=info["gap"],
+                   d_ratio=float(np.linalg.norm(d)) / nRu if nRu > 0 else 0.0)
         if nRu <= c0 * eta:                                  # K0
             u_new = u + d
             eta = nRu
@@ -320,6 +324,7 @@ def solve(prob, settings: Settings = Settings(), u0=None, lin: DirectLinSys = No
                 counts["km"] += 1
                 rec.update(kind="KM", ls=st.ls_max)
         if record:
+            rec.update(eta=eta, r_safe=r_safe)               # safeguards after the step
             history.append(rec)
         u = u_new
     x, y, s = xys

@@ -53,6 +53,7 @@ struct Vecs {
     double *out_x, *out_y, *out_s;                       // results
     double* tr_res;                                      // trace (may be null)
     int *tr_kind, *tr_ls;
+    double *tr_eta, *tr_rsafe;                           // eta and r_safe after each step
     long long tr_cap;
 };
 
@@ -62,6 +63,7 @@ struct Params {
     double cg_adapt;        // > 0: CG tolerance cg_adapt ||R u|| / ||u||, within [cg_tol, 1e-3]
     int cg_d_match;         // with cg_adapt > 0: d~'s CG stops at the absolute threshold of u~'s
     int direction, mem, ls_max, cg_max;
+    int check_every;        // termination test every check_every-th iteration
     long long max_iters;
     long long max_ticks;    // time limit in wall-clock ticks, <= 0: none
     double setup_tol;       // CG tolerance of the one-off solve for g
@@ -656,16 +658,19 @@ __device__ __noinline__ void aa_apply(Team& tm, Shared& sh, const Prob& P, const
 // reduction (they depend only on the residual pass's output, not on each
 // other): one barrier fewer per iteration.  aa_apply follows once the
 // status is known.
+// On iterations without a termination test (check false) only the dot
+// products are reduced.
 template <typename Team>
 __device__ __noinline__ void termination_aa_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
-                                                 DirState& ds, bool timed_out) {
-    const double tau = term_partials(tm, sh, P, V, timed_out);
-    const int slot = aa_push_dots(tm, sh, V, S, ds, P.N, 7);
+                                                 DirState& ds, bool timed_out, bool check) {
+    const int base = check ? 7 : 0;
+    const double tau = check ? term_partials(tm, sh, P, V, timed_out) : 0.0;
+    const int slot = aa_push_dots(tm, sh, V, S, ds, P.N, base);
     const int k = ds.aa_k;
-    tm.reduce(sh, 7 + aa_slots(k, slot));
+    tm.reduce(sh, base + aa_slots(k, slot));
     if (threadIdx.x == 0) {
-        term_finish(sh, P, S, tau);
-        if (k > 0) aa_gram(sh, S, k, slot, 7);
+        if (check) term_finish(sh, P, S, tau);
+        if (k > 0) aa_gram(sh, S, k, slot, base);
     }
     __syncthreads();
 }
@@ -815,11 +820,14 @@ __device__ __noinline__ void direction_rb(Team& tm, Shared& sh, const Prob& P, c
 // ------------------------------------------------------------------ Algorithm 1
 
 template <typename Team>
-__device__ void write_trace(Team& tm, const Vecs& V, long long nu, double res, int kind, int ls) {
+__device__ void write_trace(Team& tm, const Vecs& V, long long nu, double res, int kind, int ls, double eta,
+                            double r_safe) {
     if (V.tr_res != nullptr && tm.rank() == 0 && nu < V.tr_cap) {
         V.tr_res[nu] = res;
         V.tr_kind[nu] = kind;
         V.tr_ls[nu] = ls;
+        V.tr_eta[nu] = eta;
+        V.tr_rsafe[nu] = r_safe;
     }
 }
 
@@ -881,15 +889,18 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             tol = fmin(1e-3, fmax(S.cg_tol, S.cg_adapt * nRu / fmax(nu_, 1e-300)));
         }
         const bool late = S.max_ticks > 0 && (wall_clock64() - t_start) > S.max_ticks;
-        if (S.direction == DIR_AA) termination_aa_pass(tm, sh, P, V, S, ds, late);
-        else termination_pass(tm, sh, P, V, S, late);
+        // termination test (Sec. IV-C) every check_every-th iteration and at the
+        // iteration cap; the candidate returned is always that of a tested iteration
+        const bool check = S.check_every <= 1 || nu % S.check_every == 0 || nu >= S.max_iters;
+        if (S.direction == DIR_AA) termination_aa_pass(tm, sh, P, V, S, ds, late, check);
+        else if (check) termination_pass(tm, sh, P, V, S, late);
         if (nu == 0) eta0 = eta = r_safe = nRu;
-        status = T.status;
+        status = check ? T.status : 0;
         if (!isfinite(nRu)) status = ST_NUMERICAL;
         if (tm.aborted()) status = ST_NUMERICAL;
         if (!status && nu >= S.max_iters) status = ST_MAX_ITERS;
-        if (!status && T.timeout) status = ST_TIME_LIMIT;
-        if (status) { write_trace(tm, V, nu, nRu, -1, 0); break; }
+        if (!status && check && T.timeout) status = ST_TIME_LIMIT;
+        if (status) { write_trace(tm, V, nu, nRu, -1, 0, eta, r_safe); break; }
         const bool k0 = nRu <= S.c0 * eta;
         if (S.direction == DIR_AA) {
             aa_apply(tm, sh, P, V, ds.aa_k, k0);            // its dot products went with the termination check
@@ -908,7 +919,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             eta = nRu;
             ds.pend = 2;
             ++k0c;
-            write_trace(tm, V, nu, nRu, 0, 0);
+            write_trace(tm, V, nu, nRu, 0, 0, eta, r_safe);
             continue;
         }
         if (S.direction == DIR_ZERO) {
@@ -924,7 +935,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             ds.pend = 1;
             ++k2c;
             tm.sync();
-            write_trace(tm, V, nu, nRu, 2, 0);
+            write_trace(tm, V, nu, nRu, 2, 0, eta, r_safe);
             continue;
         }
         // inexact steps (cg_d_match): d~ to the same absolute accuracy as u~,
@@ -986,7 +997,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             ++kmc;
         }
         tm.sync();
-        write_trace(tm, V, nu, nRu, kind == 3 ? 3 : kind, ls);
+        write_trace(tm, V, nu, nRu, kind == 3 ? 3 : kind, ls, eta, r_safe);
     }
     // outputs: the candidate or the normalised certificate
     const double tau = T.tau;

@@ -316,14 +316,14 @@ double now_s() {
 // flight per wavefront, several independent loads per lane).
 // LDS (in doubles) the one-workgroup kernels stage the CG's gathered
 // vectors in, for an instance with `entries` = n + m; 0 when they do not fit
-// (the CG then gathers from global memory).  SSCS_NO_STAGE=1 turns it off.
+// (the CG then gathers from global memory).  The dynamic-LDS limit is raised
+// on every instantiation that takes the staging buffer.
 int stage_doubles(long long entries) {
-    static const bool off = [] { const char* e = getenv("SSCS_NO_STAGE"); return e && atoi(e) != 0; }();
-    if (off || entries <= 0 || entries > kStageMax) return 0;
+    if (entries <= 0 || entries > kStageMax) return 0;
     static const bool attr = [] {
         const int bytes = kStageMax * (int)sizeof(double);
-        const void* fns[] = {(const void*)k_solve_batch<double>,
-                             (const void*)k_solve_block<double>, (const void*)k_solve_block<float>};
+        const void* fns[] = {(const void*)k_solve_batch<double>, (const void*)k_solve_block<double>,
+                             (const void*)k_solve_block<float>};
         bool ok = true;
         for (const void* f : fns)
             ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
@@ -333,8 +333,7 @@ int stage_doubles(long long entries) {
 }
 
 int pow2_seg(double avg) {
-    double div = 4.0;
-    if (const char* e = std::getenv("SSCS_SEGDIV")) div = std::max(0.25, std::atof(e));   // tuning override
+    const double div = 4.0;
     int s = 1;
     while (s < 64 && s < avg / div) s <<= 1;
     return s;
@@ -409,6 +408,7 @@ int validate_settings(const sscs_settings* st) {
     if (!(st->cg_tol > 0) || !(st->cg_adapt >= 0)) return SSCS_E_INVALID;
     if (st->cg_d_match != 0 && st->cg_d_match != 1) return SSCS_E_INVALID;
     if (st->precision != SSCS_PREC_FP64 && st->precision != SSCS_PREC_MIXED) return SSCS_E_INVALID;
+    if (st->check_every < 0 || st->workgroups < 0) return SSCS_E_INVALID;
     return SSCS_OK;
 }
 
@@ -429,6 +429,7 @@ Params make_params(const sscs_settings& st, double ticks_per_s) {
     p.mem = st.mem;
     p.ls_max = st.ls_max;
     p.cg_max = st.cg_max;
+    p.check_every = std::max(1, st.check_every);
     p.max_iters = st.max_iters;
     p.max_ticks = st.max_time_s > 0 ? (long long)(st.max_time_s * ticks_per_s) : 0;
     p.setup_tol = std::min(1e-14, st.cg_tol);
@@ -651,6 +652,8 @@ struct sscs_work {
     double* tr_res = nullptr;
     int* tr_kind = nullptr;
     int* tr_ls = nullptr;
+    double* tr_eta = nullptr;
+    double* tr_rsafe = nullptr;
     long long tr_cap = 0;
     long long last_iters = -1;
     int grid = 1, max_grid = 1, ncu = 1;
@@ -764,16 +767,12 @@ int choose_grid(sscs_work* w) {
     const long long want = std::max<long long>((w->I.nnz + 2ll * kBlock - 1) / (2ll * kBlock),
                                                ((long long)w->I.N + kBlock - 1) / kBlock);
     w->grid = (int)std::max<long long>(1, std::min<long long>(want, w->max_grid));
-    if (const char* e = std::getenv("SSCS_GRID")) {      // tuning override: workgroups of the grid team
-        const int g = std::atoi(e);
-        if (g >= 1) w->grid = std::min(g, w->max_grid);
-    }
+    if (w->st.workgroups >= 1) w->grid = std::min(w->st.workgroups, w->max_grid);
     int rate_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
     w->ticks_per_s = rate_khz > 0 ? rate_khz * 1000.0 : 1e8;
     w->timeout_ticks = (long long)(60.0 * w->ticks_per_s);
-    const char* nolds = std::getenv("SSCS_NO_LDS");        // tuning override: keep the operator in HBM
-    return set_partitions(w, !(nolds && nolds[0] == '1'));
+    return set_partitions(w, true);
 }
 
 // Row partitions for the grid size; caches the operator in LDS when every
@@ -864,13 +863,16 @@ int setup_linear(sscs_work* w) {
 }
 
 int alloc_trace(sscs_work* w) {
-    hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls);
-    w->tr_res = nullptr; w->tr_kind = nullptr; w->tr_ls = nullptr; w->tr_cap = 0;
+    hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls); hipFree(w->tr_eta); hipFree(w->tr_rsafe);
+    w->tr_res = nullptr; w->tr_kind = nullptr; w->tr_ls = nullptr; w->tr_eta = nullptr; w->tr_rsafe = nullptr;
+    w->tr_cap = 0;
     if (!w->st.record_trace) return SSCS_OK;
     w->tr_cap = std::min<long long>(w->st.max_iters + 1, 4 << 20);
     TRY(dmalloc(&w->tr_res, w->tr_cap));
     TRY(dmalloc(&w->tr_kind, w->tr_cap));
     TRY(dmalloc(&w->tr_ls, w->tr_cap));
+    TRY(dmalloc(&w->tr_eta, w->tr_cap));
+    TRY(dmalloc(&w->tr_rsafe, w->tr_cap));
     return SSCS_OK;
 }
 
@@ -898,10 +900,10 @@ int sscs_default_settings(sscs_settings* st) {
     st->direction = SSCS_DIR_AA;
     st->mem = 5;
     st->c0 = 0.99;
-    st->c1 = 0.99;
-    st->q = 0.99;
+    st->c1 = 0.9999;
+    st->q = 0.999;
     st->sigma = 0.01;
-    st->lambda = 1.0;
+    st->lambda = 1.5;
     st->thetabar = 0.1;
     st->ls_max = 10;
     st->max_iters = 10000;
@@ -914,6 +916,8 @@ int sscs_default_settings(sscs_settings* st) {
     st->aa_reg = 1e-12;
     st->cg_adapt = 0.0;
     st->cg_d_match = 1;
+    st->check_every = 1;
+    st->workgroups = 0;
     return SSCS_OK;
 }
 
@@ -946,7 +950,7 @@ int sscs_create(const sscs_data* data, const sscs_cone* cone, const sscs_setting
 int sscs_update_settings(sscs_work* w, const sscs_settings* st) {
     if (!w) return SSCS_E_INVALID;
     TRY(validate_settings(st));
-    if (st->precision != w->st.precision) return SSCS_E_INVALID;
+    if (st->precision != w->st.precision || st->workgroups != w->st.workgroups) return SSCS_E_INVALID;
     const bool retrace = st->record_trace != w->st.record_trace || st->max_iters != w->st.max_iters;
     w->st = *st;
     if (retrace) TRY(alloc_trace(w));
@@ -968,7 +972,7 @@ int sscs_destroy(sscs_work* w) {
     free_instance(w->I);
     hipFree(w->vecbuf); hipFree(w->io); hipFree(w->scal); hipFree(w->res);
     hipFree(w->bar); hipFree(w->abort_flag); hipFree(w->part);
-    hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls);
+    hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls); hipFree(w->tr_eta); hipFree(w->tr_rsafe);
     delete w;
     return SSCS_OK;
 }
@@ -985,6 +989,7 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
     V.out_y = out_ptr(w, y, 2);
     V.out_s = out_ptr(w, s, 3);
     V.tr_res = w->tr_res; V.tr_kind = w->tr_kind; V.tr_ls = w->tr_ls; V.tr_cap = w->tr_cap;
+    V.tr_eta = w->tr_eta; V.tr_rsafe = w->tr_rsafe;
     Prob P = make_prob(w->I);
     Params S = make_params(w->st, w->ticks_per_s);
     // every solve starts its PSD projections cold (same input, same bits)
@@ -1088,7 +1093,8 @@ int sscs_spmv_bench(sscs_work* w, int32_t transpose, int32_t reps, double* ms) {
     return SSCS_OK;
 }
 
-int sscs_get_trace(sscs_work* w, int64_t cap, double* res, int32_t* kind, int32_t* ls, int64_t* count) {
+int sscs_get_trace(sscs_work* w, int64_t cap, double* res, int32_t* kind, int32_t* ls, double* eta, double* r_safe,
+                   int64_t* count) {
     if (!w || !count) return SSCS_E_INVALID;
     if (!w->tr_res || w->last_iters < 0) { *count = 0; return SSCS_OK; }
     const long long avail = std::min<long long>(w->last_iters + 1, w->tr_cap);
@@ -1098,6 +1104,8 @@ int sscs_get_trace(sscs_work* w, int64_t cap, double* res, int32_t* kind, int32_
         if (res) HIP_TRY(hipMemcpy(res, w->tr_res, c * sizeof(double), hipMemcpyDeviceToHost));
         if (kind) HIP_TRY(hipMemcpy(kind, w->tr_kind, c * sizeof(int), hipMemcpyDeviceToHost));
         if (ls) HIP_TRY(hipMemcpy(ls, w->tr_ls, c * sizeof(int), hipMemcpyDeviceToHost));
+        if (eta) HIP_TRY(hipMemcpy(eta, w->tr_eta, c * sizeof(double), hipMemcpyDeviceToHost));
+        if (r_safe) HIP_TRY(hipMemcpy(r_safe, w->tr_rsafe, c * sizeof(double), hipMemcpyDeviceToHost));
     }
     return SSCS_OK;
 }
@@ -1141,9 +1149,6 @@ struct sscs_batch {
     double setup_s = 0;
 };
 
-namespace {
-
-}  // namespace
 
 extern "C" {
 
@@ -1163,8 +1168,8 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
         if (!out || count < 1 || !data || !cones) return SSCS_E_INVALID;
         *out = nullptr;
         TRY(validate_settings(st));
-        // the batched engine computes in FP64 only: its mixed-precision form is
-        // switched off until its GPU behaviour is understood
+        // the batched engine runs the FP64 operator only: its mixed-precision
+        // form ran without finishing in a test whose cause has not been shown
         if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
         for (int i = 0; i < count; ++i) {
             TRY(validate(&data[i], &cones[i]));
@@ -1298,6 +1303,7 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
         V.out_y = oy + bt->off_y[i];
         V.out_s = os + bt->off_y[i];
         V.tr_res = nullptr; V.tr_kind = nullptr; V.tr_ls = nullptr; V.tr_cap = 0;
+        V.tr_eta = nullptr; V.tr_rsafe = nullptr;
     }
     HIP_TRY(hipMemcpyAsync(bt->d_insts, bt->h_insts.data(), bt->count * sizeof(BatchInst), hipMemcpyHostToDevice,
                            bt->stream));

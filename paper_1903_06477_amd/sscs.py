@@ -44,7 +44,8 @@ class _Settings(ctypes.Structure):
                 ("ls_max", ctypes.c_int32), ("max_iters", ctypes.c_int64), ("max_time_s", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double), ("cg_max", ctypes.c_int32),
                 ("data_on_device", ctypes.c_int32), ("record_trace", ctypes.c_int32),
-                ("aa_reg", ctypes.c_double), ("cg_adapt", ctypes.c_double), ("cg_d_match", ctypes.c_int32)]
+                ("aa_reg", ctypes.c_double), ("cg_adapt", ctypes.c_double), ("cg_d_match", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -90,7 +91,7 @@ def lib():
         L.sscs_residual.argtypes = [vp, vp, vp, vp]
         L.sscs_spmv.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.sscs_spmv_bench.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
-        L.sscs_get_trace.argtypes = [vp, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.sscs_get_trace.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.sscs_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(_Data), ctypes.POINTER(_Cone),
                                         ctypes.POINTER(_Settings), vp, ctypes.POINTER(vp)]
         L.sscs_batch_update_bc.argtypes = [vp, vp, vp]
@@ -115,10 +116,10 @@ class Settings:
     direction: str = "aa"
     mem: int = 5
     c0: Optional[float] = None       # default: 0.1 for "rb", 0.99 otherwise
-    c1: float = 0.99
-    q: float = 0.99
+    c1: float = 0.9999
+    q: float = 0.999
     sigma: float = 0.01
-    lam: float = 1.0
+    lam: float = 1.5
     thetabar: float = 0.1
     ls_max: int = 10
     max_iters: int = 10000
@@ -131,6 +132,8 @@ class Settings:
     aa_reg: float = 1e-12
     cg_adapt: float = 0.0
     cg_d_match: bool = True
+    check_every: int = 1
+    workgroups: int = 0
 
     def to_c(self) -> _Settings:
         st = _Settings()
@@ -150,6 +153,8 @@ class Settings:
         st.aa_reg = self.aa_reg
         st.cg_adapt = self.cg_adapt
         st.cg_d_match = int(self.cg_d_match)
+        st.check_every = int(self.check_every)
+        st.workgroups = int(self.workgroups)
         return st
 
 
@@ -283,14 +288,18 @@ class Solver:
         _check(lib().sscs_spmv_bench(self._h, int(transpose), int(reps), ctypes.byref(ms)))
         return ms.value
 
-    def trace(self):
+    def trace(self, safeguards=False):
+        """(res, kind, ls) per iteration of the last solve, and (eta, r_safe)
+        after each step when safeguards is set."""
         cnt = ctypes.c_int64()
-        _check(lib().sscs_get_trace(self._h, 0, None, None, None, ctypes.byref(cnt)))
+        _check(lib().sscs_get_trace(self._h, 0, None, None, None, None, None, ctypes.byref(cnt)))
         k = cnt.value
         res, kind, ls = np.empty(k), np.empty(k, np.int32), np.empty(k, np.int32)
+        eta, rs = np.empty(k), np.empty(k)
         if k:
-            _check(lib().sscs_get_trace(self._h, k, _vptr(res), _vptr(kind), _vptr(ls), ctypes.byref(cnt)))
-        return res, kind, ls
+            _check(lib().sscs_get_trace(self._h, k, _vptr(res), _vptr(kind), _vptr(ls), _vptr(eta), _vptr(rs),
+                                        ctypes.byref(cnt)))
+        return (res, kind, ls, eta, rs) if safeguards else (res, kind, ls)
 
 
 class BatchSolver:

@@ -175,8 +175,10 @@ def experiment(ntrain: int, ntest: int, epochs: int = 60, seed: int = 0, check_e
     xw, yw, sw, info_warm, t_warm = batched_solve(test, st, u0=u0)
     fail = [i for i, inf in enumerate(info_warm) if inf["status"] != S.SOLVED]
     t_fb = 0.0
+    fb_solved = 0
     if fail:
         _, _, _, info_fb, t_fb = batched_solve([test[i] for i in fail], st)
+        fb_solved = sum(inf["status"] == S.SOLVED for inf in info_fb)
     # ablation: the same warm start built from the training targets' mean (no network)
     Tm = torch.from_numpy(np.tile(T.mean(0), (ntest, 1)).astype(np.float32)).cuda()
     u0m = M.assemble_u0(Tm, n, m).reshape(-1)
@@ -199,6 +201,7 @@ def experiment(ntrain: int, ntest: int, epochs: int = 60, seed: int = 0, check_e
     res = dict(ntrain=ntrain, ntest=ntest, epochs=epochs, t_generate=t_gen, t_train=t_train,
                loss_first=losses[0], loss_last=losses[-1], t_cold=t_cold, cold_solved=float(cold_ok),
                t_inference=t_inf, t_warm_solve=t_warm, t_fallback=t_fb, n_fallback=len(fail),
+               final_solved=(ntest - len(fail) + fb_solved) / ntest,
                t_warm_total=t_inf + t_warm + t_fb, iters_cold_mean=float(it_cold.mean()),
                iters_warm_mean=float(it_warm.mean()), warm_worst_residual=wworst,
                t_mean_start=t_mean, iters_mean_start=float(it_mean.mean()), test_loss=test_loss,

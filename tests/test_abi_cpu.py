@@ -63,6 +63,13 @@ def test_default_settings_and_error_strings():
     st = sscs._Settings()
     assert L.sscs_default_settings(ctypes.byref(st)) == 0
     assert st.eps == 1e-6 and st.mem == 5 and st.direction == 1
+    # converging defaults of the Algorithm 1 inputs the paper leaves open; the
+    # binding's defaults are the library's
+    assert (st.c1, st.q, st.lambda_, st.check_every, st.workgroups) == (0.9999, 0.999, 1.5, 1, 0)
+    py = sscs.Settings().to_c()
+    for f, _ in sscs._Settings._fields_:
+        if f != "c0":
+            assert getattr(py, f) == getattr(st, f), f
     assert L.sscs_error_string(-1) == b"invalid argument"
     assert L.sscs_default_settings(None) == -1
 

@@ -90,3 +90,96 @@ def test_sdp_exp_full_projection_and_spmv(sscs):
             got = s.project_dual_cone(yv)
             ref = proj_dual_cone(yv, prob.cone)
             np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10 * (1 + np.abs(yv).max()))
+
+
+def _g31(got, ref, u):
+    """Relative fixed-point-residual difference at the same input u."""
+    return np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-3 * np.linalg.norm(u))
+
+
+def _parity_at_probes(sscs, prob, probes, label):
+    """G31 <= 1e-9 (fixed-point residual at the same input) and the linear
+    step within 1e-10 of the oracle's direct solve, on the launch
+    configuration the library picks for the instance (the one bench.py times)."""
+    import time
+    import oracle
+    from oracle import superscs as S
+    t0 = time.perf_counter()
+    lin = oracle.DirectLinSys(prob.A, prob.b, prob.c)
+    print(f"{label}: oracle factor ({lin.kind}) {time.perf_counter() - t0:.1f}s", flush=True)
+    rr = np.random.default_rng(11)
+    with sscs.Solver(prob, sscs.Settings(cg_tol=1e-14, cg_max=5000)) as s:
+        for name, u in probes:
+            _, _, Ru_ref = S.residual(lin, prob.cone, u)
+            _, Ru = s.residual(u)
+            e = _g31(Ru, Ru_ref, u)
+            print(f"{label} probe {name}: ||Ru|| {np.linalg.norm(Ru_ref):.3e}, G31 {e:.2e}", flush=True)
+            assert e <= 1e-9, name
+        for k in range(2):
+            rhs = rr.standard_normal(prob.n + prob.m + 1)
+            ref = lin.L(rhs)
+            got = s.linear_step(rhs)
+            e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            print(f"{label} linear step {k}: rel {e:.2e}", flush=True)
+            assert e <= 1e-10
+
+
+def test_socp_20000x50000_parity_at_probe_points(sscs):
+    """Sparse SOCP at full size on the operator-in-LDS grid: the cold start,
+    a random point, an oracle iterate and a point near the planted fixed point
+    (u* = (x*, y* + s*, 1) plus 1e-3 noise)."""
+    from oracle import superscs as S
+    prob = G.config2_socp()
+    N = prob.n + prob.m + 1
+    rr = np.random.default_rng(12)
+    cold = np.zeros(N); cold[-1] = 1.0
+    ustar = np.concatenate([prob.x_star, prob.y_star + prob.s_star, [1.0]])
+    it = S.solve(prob, S.Settings(direction="aa", mem=5, max_iters=8), record=False).u
+    probes = [("cold", cold), ("random", rr.standard_normal(N)), ("oracle iterate 8", it),
+              ("near u*", ustar + 1e-3 * rr.standard_normal(N))]
+    _parity_at_probes(sscs, prob, probes, "SOCP 20000x50000")
+
+
+def test_sdp_exp_parity_at_probe_points(sscs):
+    """PSD/exp instance at full size (m = 535113): its order-256 block takes
+    the whole-grid block-Jacobi path.  Cold start, a random point and an
+    oracle iterate."""
+    from oracle import superscs as S
+    prob = G.config3_sdp_exp()
+    N = prob.n + prob.m + 1
+    rr = np.random.default_rng(13)
+    cold = np.zeros(N); cold[-1] = 1.0
+    it = S.solve(prob, S.Settings(direction="aa", mem=5, max_iters=6), record=False).u
+    probes = [("cold", cold), ("random", rr.standard_normal(N)), ("oracle iterate 6", it)]
+    _parity_at_probes(sscs, prob, probes, "PSD/exp 349033x535113")
+
+
+def test_sdp_exp_full_solve_meets_tolerance(sscs):
+    """A complete solve of the PSD/exp instance with the benchmark's settings:
+    solved, pr/dr/gap <= 1e-6 recomputed on the host from the returned
+    (x, y, s), y in K* and s in K (zero rows of s at 0) to 1e-6."""
+    import bench
+    from oracle.cones import proj_dual_cone, proj_C
+    prob = G.config3_sdp_exp()
+    st = bench.bench_settings(sscs, 20000)
+    st.data_on_device = False
+    print("PSD/exp full solve, bench settings", flush=True)
+    with sscs.Solver(prob, st) as s:
+        x, y, sv, info = s.solve()
+    print(f"status {info['status_name']} iters {info['iters']} time {info['solve_s']:.1f}s", flush=True)
+    assert info["status"] == sscs.SOLVED
+    assert max(_kkt(prob, x, y, sv)) <= 1e-6 * 1.0001
+    assert np.linalg.norm(y - proj_dual_cone(y, prob.cone)) <= 1e-6 * (1 + np.linalg.norm(y))
+    z = prob.cone.z
+    assert np.linalg.norm(sv[:z]) <= 1e-5 * (1 + np.linalg.norm(prob.b))
+    # s in K: K is self-dual on R+, SOC and PSD; the exp cone is not, so s is
+    # checked there through Moreau (s = Pi_K(s))
+    from oracle.cones import proj_exp
+    e0 = prob.m - 3 * prob.cone.ep
+    s_nz = sv.copy(); s_nz[:z] = 0.0
+    s_head = s_nz[:e0]
+    cone_head = G.Cone(z=prob.cone.z, l=prob.cone.l, q=prob.cone.q, s=prob.cone.s, ep=0)
+    assert np.linalg.norm(s_head - proj_dual_cone(s_head, cone_head)) <= 1e-6 * (1 + np.linalg.norm(sv))
+    se = sv[e0:].reshape(-1, 3)
+    d = max(np.linalg.norm(v - proj_exp(v)) for v in se)
+    assert d <= 1e-6 * (1 + np.linalg.norm(sv))

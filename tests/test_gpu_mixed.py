@@ -7,7 +7,8 @@ relative at CG tolerance 1e-13 (each refinement round recomputes the residual
 in FP64, so the FP32 operator's 2^-24 relative rounding only slows the
 convergence of the rounds); end-to-end solves meet pr, dr, gap <= eps
 recomputed on the CPU in FP64 from the returned (x, y, s), with the objective
-within 1e-5 relative of the oracle's."""
+within 1e-6 relative of the oracle's (both sides solved to eps 1e-8, since two
+solutions that each just meet 1e-6 can differ in objective by ~1e-5)."""
 import os
 
 import numpy as np
@@ -16,6 +17,8 @@ import pytest
 from paper_1903_06477_amd import generators as G
 
 pytestmark = pytest.mark.gpu
+
+EPS_OBJ = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -70,41 +73,34 @@ def test_end_to_end_precision_and_kernel(sscs, precision, grid):
     kernel and on the one-workgroup kernel (grid forced to 1)."""
     from oracle import superscs as S
     cases = [(G.config1_lp(), "rb", 10), (G.small_socp(2), "aa", 5)]
-    old = os.environ.get("SSCS_GRID")
-    try:
-        if grid == "1":
-            os.environ["SSCS_GRID"] = "1"
-        else:
-            os.environ.pop("SSCS_GRID", None)
-        for prob, d, mem in cases:
-            print(f"solve {prob.name or 'socp'} {precision} grid={grid}", flush=True)
-            ref = S.solve(prob, S.Settings(direction=d, mem=mem))
-            with sscs.Solver(prob, sscs.Settings(direction=d, mem=mem, cg_tol=1e-12, cg_max=5000,
-                                                 precision=precision)) as s:
-                x, y, sv, info = s.solve()
-            assert info["status"] == sscs.SOLVED == ref.status
-            assert max(_kkt(prob, x, y, sv)) <= 1e-6 * 1.0001
-            assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
-    finally:
-        if old is None:
-            os.environ.pop("SSCS_GRID", None)
-        else:
-            os.environ["SSCS_GRID"] = old
+    wg = 1 if grid == "1" else 0
+    for prob, d, mem in cases:
+        print(f"solve {prob.name or 'socp'} {precision} grid={grid}", flush=True)
+        ref = S.solve(prob, S.Settings(direction=d, mem=mem, eps=EPS_OBJ))
+        with sscs.Solver(prob, sscs.Settings(direction=d, mem=mem, eps=EPS_OBJ, cg_tol=1e-12, cg_max=5000,
+                                             precision=precision, workgroups=wg)) as s:
+            x, y, sv, info = s.solve()
+        assert info["status"] == sscs.SOLVED == ref.status
+        assert max(_kkt(prob, x, y, sv)) <= EPS_OBJ * 1.0001
+        assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-6 * (1 + abs(ref.info["pobj"]))
 
 
-@pytest.mark.skip(reason="the batched engine's mixed-precision form ran without finishing on the GPU and "
-                         "is switched off (sscs_batch_create returns SSCS_E_UNSUPPORTED for it) until the "
-                         "cause is found")
+@pytest.mark.skip(reason="the batched engine's mixed-precision form ran without finishing on the GPU in an "
+                         "early test whose code is no longer in the tree; its cause has not been shown (a CPU "
+                         "emulation of the current refinement rounds on these six instances ends every linear "
+                         "step within 129 CG passes and 4 rounds and solves each instance), so the form stays "
+                         "switched off (sscs_batch_create returns SSCS_E_UNSUPPORTED for it)")
 def test_mixed_batch_lasso(sscs):
     from oracle import superscs as S
     probs = [G.config4_instance(i) for i in range(6)]
-    st = sscs.Settings(direction="aa", mem=5, cg_tol=1e-12, cg_max=2000, precision="mixed")
+    st = sscs.Settings(direction="aa", mem=5, eps=EPS_OBJ, cg_tol=1e-12, cg_max=2000, precision="mixed",
+                       max_time=20.0)
     bs = sscs.BatchSolver(probs, st)
     x, y, sv, infos = bs.solve()
     parts = bs.split(x, y, sv)
     for i, p in enumerate(probs):
-        ref = S.solve(p, S.Settings(direction="aa", mem=5))
+        ref = S.solve(p, S.Settings(direction="aa", mem=5, eps=EPS_OBJ))
         assert infos[i]["status"] == sscs.SOLVED
-        assert max(_kkt(p, *parts[i])) <= 1e-6 * 1.0001
-        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
+        assert max(_kkt(p, *parts[i])) <= EPS_OBJ * 1.0001
+        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-6 * (1 + abs(ref.info["pobj"]))
     bs.close()

@@ -7,13 +7,20 @@ with the FP64 reference network twice: (i) with the reference's BF16 operand
 model (every product operand rounded to BF16 as the kernels do), where only
 FP32 accumulation and the FP32 -> BF16 double rounding of intermediates
 differ: relative Frobenius error <= 1e-3 per layer and max entry error <=
-2e-3 of the layer's largest entry; (ii) with exact FP64 arithmetic, which
-bounds what BF16 operands cost: relative Frobenius error <= 5e-2 (25 units of
-BF16 rounding, 2^-9, for an error that passes through up to five rounded
-products) and cosine >= 0.998.  u0 assembly is exact in FP64 of the FP32
-inputs; a few Adam steps on a fixed batch lower the loss;
-a small learned warm start reaches the solver's tolerance, checked on the host
-in FP64."""
+2e-3 of the layer's largest entry; (ii) with exact FP64 arithmetic:
+cosine >= 0.999 and relative Frobenius error <= 2e-2 per tensor, except where
+BF16 operands alone already cost more.  The bound used there is derived, not
+chosen: by the triangle inequality ||g - e|| <= ||g - q|| + ||q - e|| for the
+GPU gradient g, the BF16 operand model q and the exact e, with ||g - q|| <=
+1e-3 ||q|| from bar (i), so rel(g, e) <= rel(q, e) + 2e-3.  rel(q, e) is the
+cost of BF16 operands in exact arithmetic; it exceeds 2e-2 only for the first
+layer's weight gradient of the two larger networks (3.1e-2 and 3.4e-2), where
+ReLU masks of the backward pass flip at pre-activations that BF16 rounding
+moves across zero (110 of 131072 entries in the first hidden layer of the
+2000-512-512-10005 network: sqrt(110/131072) = 2.9% of the error signal).
+u0 assembly is exact in FP64 of the FP32 inputs; a few Adam steps on a fixed
+batch lower the loss; a small learned warm start reaches the solver's
+tolerance, checked on the host in FP64."""
 import numpy as np
 import pytest
 
@@ -64,8 +71,12 @@ def _close_model(a, b):
     return _rel(a, b) <= 1e-3 and np.max(np.abs(a - b)) <= 2e-3 * np.max(np.abs(b))
 
 
-def _close_exact(a, b):
-    return _rel(a, b) <= 5e-2 and _cos(a, b) >= 0.998
+def _close_exact(a, b, model):
+    """GPU value a against the exact FP64 value b, given the BF16 operand
+    model's value: cosine >= 0.999, relative error <= 2e-2 or, where the
+    model itself is further from b, <= rel(model, b) + 2e-3."""
+    bar = max(2e-2, _rel(model, b) + 2e-3)
+    return _rel(a, b) <= bar and _cos(a, b) >= 0.999
 
 
 @pytest.mark.parametrize("widths,batch", [([20, 33, 17, 9], 50), ([300, 128, 96, 700], 130),
@@ -87,15 +98,17 @@ def test_forward_and_gradients_match_oracle(M, widths, batch):
     Y = net.forward(_dev(X)).cpu().numpy()
     Yq, _ = ref.forward(Ws, bs, X, q=ref.bf16_round)
     Ye, _ = ref.forward(Ws, bs, X)
-    assert _close_model(Y, Yq) and _close_exact(Y, Ye)
+    assert _close_model(Y, Yq) and _close_exact(Y, Ye, Yq)
     L, dWs, dbs = net.gradients(_dev(X), _dev(T))
     Lq, dWq, dbq = ref.loss_and_grads(Ws, bs, X, T, q=ref.bf16_round)
     Le, dWe, dbe = ref.loss_and_grads(Ws, bs, X, T)
     assert abs(L - Lq) <= 1e-4 * Lq and abs(L - Le) <= 1e-2 * Le
     for l in range(len(Ws)):
-        print(f"layer {l}: dW rel vs model {_rel(dWs[l], dWq[l]):.2e}, vs exact {_rel(dWs[l], dWe[l]):.2e}")
-        assert _close_model(dWs[l], dWq[l]) and _close_exact(dWs[l], dWe[l]), l
-        assert _close_model(dbs[l], dbq[l]) and _close_exact(dbs[l], dbe[l]), l
+        print(f"layer {l}: dW rel vs model {_rel(dWs[l], dWq[l]):.2e}, vs exact {_rel(dWs[l], dWe[l]):.2e} "
+              f"(model vs exact {_rel(dWq[l], dWe[l]):.2e}), cos vs exact {_cos(dWs[l], dWe[l]):.6f}; "
+              f"db rel vs exact {_rel(dbs[l], dbe[l]):.2e}", flush=True)
+        assert _close_model(dWs[l], dWq[l]) and _close_exact(dWs[l], dWe[l], dWq[l]), l
+        assert _close_model(dbs[l], dbq[l]) and _close_exact(dbs[l], dbe[l], dbq[l]), l
     net.close()
 
 
@@ -148,5 +161,6 @@ def test_small_learned_warm_start_solves(M):
     res = W.experiment(ntrain=192, ntest=32, epochs=30, log=lambda s: print(s, flush=True))
     assert res["cold_solved"] == 1.0
     assert res["loss_last"] < res["loss_first"]
-    assert res["n_fallback"] <= res["ntest"]
-    assert res["warm_worst_residual"] <= 2e-6
+    # every test instance ends solved: by its warm start, or by the cold fallback
+    assert res["final_solved"] == 1.0
+    assert res["warm_worst_residual"] <= 1e-6 * 1.0001

@@ -16,6 +16,11 @@ from paper_1903_06477_amd import generators as G
 
 pytestmark = pytest.mark.gpu
 
+# Objective comparisons solve to eps 1e-8 on both sides where the two
+# trajectories differ: two solutions that each just meet eps 1e-6 differ in
+# objective by up to ~1.4e-5 relative on the LASSO instances.
+EPS_OBJ = 1e-8
+
 
 @pytest.fixture(scope="module")
 def sscs():
@@ -229,6 +234,32 @@ def test_residual_parity_at_probe_points(sscs, maker):
             assert np.linalg.norm(ut - ut_ref) <= 1e-10 * np.linalg.norm(ut_ref)
 
 
+def test_alg1_safeguards_golden(sscs):
+    """Step kinds, backtracks, ||R u||, eta and r_safe of the device engine on
+    the rotation instances of tests/golden/alg1_safeguards.json, whose first
+    seven iterations are derived by hand (Algorithm 1 with d = -Ru)."""
+    import json, os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alg1_safeguards.json")))
+    kinds = {"K0": 0, "K1": 1, "K2": 2, "KM": 3}
+    for case in d["cases"]:
+        theta = case["theta"]
+        prob = G.Problem(A=sp.csr_matrix(np.array([[theta]])), b=np.zeros(1), c=np.zeros(1), cone=G.Cone(z=1))
+        kw = dict(case["settings"])
+        nit = len(case["kind"])
+        st = sscs.Settings(direction="residual", eps=1e-12, max_iters=nit, cg_tol=1e-14, cg_max=100,
+                           record_trace=True, **kw)
+        with sscs.Solver(prob, st) as s:
+            info = s.solve(u0=np.array([1.0, 0.0, 1.0]))[3]
+            res, kind, ls, eta, rs = s.trace(safeguards=True)
+        print(case["name"], info["status_name"], list(kind), flush=True)
+        assert info["status"] == sscs.MAX_ITERS and len(kind) == nit + 1
+        assert list(kind[:nit]) == [kinds[k] for k in case["kind"]], case["name"]
+        assert list(ls[:nit]) == case["ls"], case["name"]
+        np.testing.assert_allclose(res[:nit], case["res"], rtol=1e-12)
+        np.testing.assert_allclose(eta[:nit], case["eta"], rtol=1e-12)
+        np.testing.assert_allclose(rs[:nit], case["r_safe"], rtol=1e-12)
+
+
 # ------------------------------------------------------------------ end to end
 
 def _compare_solve(sscs, prob, st_o, st_g, pobj_tol=1e-6):
@@ -280,11 +311,16 @@ def test_config1_lp_rb(sscs):
     print(f"config1 RB: iters gpu {info['iters']} oracle {ref.iters}, trajectory equal for {ncmp} iterations")
 
 
+@pytest.mark.parametrize("seed", [0, 2])
 @pytest.mark.parametrize("direction,mem", [("aa", 5), ("aa", 10), ("rb", 10), ("none", 5)])
-def test_small_socp_directions(sscs, direction, mem):
-    prob = G.small_socp(2)
+def test_small_socp_directions(sscs, direction, mem, seed):
+    """Default settings (lambda 1.5, c1 0.9999, q 0.999).  Seed 0 is the SOCP on
+    which c1 = q = 0.99, lambda = 1 stall: Anderson in K2 steps with ||Ru||
+    growing, restarted Broyden in backtracking-cap steps with ||d|| ~ 1e4 ||Ru||
+    (no pair is stored after such a step, so the direction never changes)."""
+    prob = G.small_socp(seed)
     _, S = _oracle()
-    max_it = 20000 if direction == "none" else 5000
+    max_it = 30000 if direction == "none" else 10000
     c0 = 1.0 if direction == "none" else None
     _compare_solve(sscs, prob, S.Settings(direction=direction, mem=mem, max_iters=max_it, c0=c0),
                    sscs.Settings(direction=direction, mem=mem, max_iters=max_it, c0=c0, cg_tol=1e-13,
@@ -364,17 +400,19 @@ def test_run_twice_bitwise(sscs):
 def test_lasso_batch_matches_oracle_and_single(sscs):
     _, S = _oracle()
     probs = [G.config4_instance(i) for i in range(6)]
-    st = sscs.Settings(direction="aa", mem=5, cg_tol=1e-12, cg_max=2000)
+    # eps 1e-8 on both sides: two solutions that each just meet 1e-6 differ in
+    # objective by up to ~1.4e-5 relative on these instances
+    st = sscs.Settings(direction="aa", mem=5, eps=EPS_OBJ, cg_tol=1e-12, cg_max=2000)
     bs = sscs.BatchSolver(probs, st)
     x, y, sv, infos = bs.solve()
     parts = bs.split(x, y, sv)
     for i, p in enumerate(probs):
-        ref = S.solve(p, S.Settings(direction="aa", mem=5))
+        ref = S.solve(p, S.Settings(direction="aa", mem=5, eps=EPS_OBJ))
         xi, yi, si = parts[i]
         assert infos[i]["status"] == ref.status == S.SOLVED
         pr, dr, gap = kkt_measures(p, xi, yi, si)
-        assert max(pr, dr, gap) <= 1e-6 * 1.0001
-        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
+        assert max(pr, dr, gap) <= EPS_OBJ * 1.0001
+        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-6 * (1 + abs(ref.info["pobj"]))
     # batch invariance: an instance alone in a batch gives the same bits
     alone = sscs.BatchSolver([probs[2]], st)
     xa, ya, sa, ia = alone.solve()
@@ -385,7 +423,7 @@ def test_lasso_batch_matches_oracle_and_single(sscs):
 # The inexact-mode tests solve to eps = 1e-8 on both sides: their trajectories
 # differ from the oracle's, and two solutions that each just meet eps = 1e-6
 # may differ in objective by more than 1e-5 relative.
-EPS_INEXACT = 1e-8
+EPS_INEXACT = EPS_OBJ
 
 
 def _inexact_settings(sscs, match=True):
@@ -402,25 +440,17 @@ def test_inexact_linear_steps(sscs, engine, match):
     the host (pr/dr/gap <= eps = 1e-8, objective within 1e-5)."""
     import os
     _, S = _oracle()
-    old = os.environ.get("SSCS_GRID")
-    try:
-        if engine == "block":
-            os.environ["SSCS_GRID"] = "1"
-        else:
-            os.environ.pop("SSCS_GRID", None)
-        for prob in [G.config1_lp(), G.small_socp(2), G.small_socp(5)]:
-            print(f"inexact {engine} match={match} {prob.name or 'socp'} n={prob.n} m={prob.m}", flush=True)
-            ref = S.solve(prob, S.Settings(direction="aa", mem=5, eps=EPS_INEXACT, max_iters=20000))
-            with sscs.Solver(prob, _inexact_settings(sscs, match)) as s:
-                x, y, sv, info = s.solve()
-            assert info["status"] == sscs.SOLVED == ref.status
-            assert max(kkt_measures(prob, x, y, sv)) <= EPS_INEXACT * 1.0001
-            assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
-    finally:
-        if old is None:
-            os.environ.pop("SSCS_GRID", None)
-        else:
-            os.environ["SSCS_GRID"] = old
+    wg = 1 if engine == "block" else 0
+    for prob in [G.config1_lp(), G.small_socp(2), G.small_socp(5)]:
+        print(f"inexact {engine} match={match} {prob.name or 'socp'} n={prob.n} m={prob.m}", flush=True)
+        ref = S.solve(prob, S.Settings(direction="aa", mem=5, eps=EPS_INEXACT, max_iters=20000))
+        st = _inexact_settings(sscs, match)
+        st.workgroups = wg
+        with sscs.Solver(prob, st) as s:
+            x, y, sv, info = s.solve()
+        assert info["status"] == sscs.SOLVED == ref.status
+        assert max(kkt_measures(prob, x, y, sv)) <= EPS_INEXACT * 1.0001
+        assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-6 * (1 + abs(ref.info["pobj"]))
 
 
 def test_inexact_linear_steps_batch(sscs):
@@ -437,7 +467,7 @@ def test_inexact_linear_steps_batch(sscs):
         ref = S.solve(p, S.Settings(direction="aa", mem=5, eps=EPS_INEXACT, max_iters=20000))
         assert infos[i]["status"] == ref.status == S.SOLVED
         assert max(kkt_measures(p, *parts[i])) <= EPS_INEXACT * 1.0001
-        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
+        assert abs(infos[i]["pobj"] - ref.info["pobj"]) <= 1e-6 * (1 + abs(ref.info["pobj"]))
     bs.close()
     alone = sscs.BatchSolver([probs[3]], st)
     xa, _, _, ia = alone.solve()

@@ -3,9 +3,9 @@ of orders 4, 4, 7 plus a 30-sample l1 logistic regression, and a variant with
 blocks of orders 4 and 66, whose larger block takes the grid-team projection
 path on the grid kernel): status, pr, dr,
 gap <= eps recomputed on the CPU in FP64 from the returned (x, y, s), the
-returned y in K* and s in K to 1e-6, and the objective within 1e-5 relative
-of the oracle's, in FP64 and mixed precision, on the grid kernel and on the
-one-workgroup kernel."""
+returned y in K* and s in K to 1e-6, and the objective within 1e-6 relative
+of the oracle's (both solved to eps 1e-8), in FP64 and mixed precision, on
+the grid kernel and on the one-workgroup kernel."""
 import os
 
 import numpy as np
@@ -14,6 +14,8 @@ import pytest
 from paper_1903_06477_amd import generators as G
 
 pytestmark = pytest.mark.gpu
+
+EPS_OBJ = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -32,10 +34,10 @@ def reference():
     out = {}
     for seed in (0, 1):
         p = G.small_sdp_exp(seed)
-        out[seed] = (p, S.solve(p, S.Settings(direction="aa", mem=5, max_iters=20000)))
+        out[seed] = (p, S.solve(p, S.Settings(direction="aa", mem=5, eps=EPS_OBJ, max_iters=20000)))
     # one PSD block of order 66: the grid-team projection path
     p = G.config3_sdp_exp(instance=2001, nblk=1, k=4, kbig=66, q=20, p=4, density=0.3)
-    out[2] = (p, S.solve(p, S.Settings(direction="aa", mem=5, max_iters=20000)))
+    out[2] = (p, S.solve(p, S.Settings(direction="aa", mem=5, eps=EPS_OBJ, max_iters=20000)))
     return out
 
 
@@ -46,27 +48,17 @@ def test_sdp_exp_end_to_end(sscs, reference, seed, precision, grid):
     from oracle.cones import proj_dual_cone
     prob, ref = reference[seed]
     assert ref.status == 1
-    old = os.environ.get("SSCS_GRID")
-    try:
-        if grid == "1":
-            os.environ["SSCS_GRID"] = "1"
-        else:
-            os.environ.pop("SSCS_GRID", None)
-        print(f"sdp/exp seed {seed} {precision} grid={grid}", flush=True)
-        with sscs.Solver(prob, sscs.Settings(direction="aa", mem=5, cg_tol=1e-12, cg_max=5000,
-                                             max_iters=20000, precision=precision)) as s:
-            x, y, sv, info = s.solve()
-    finally:
-        if old is None:
-            os.environ.pop("SSCS_GRID", None)
-        else:
-            os.environ["SSCS_GRID"] = old
+    print(f"sdp/exp seed {seed} {precision} grid={grid}", flush=True)
+    with sscs.Solver(prob, sscs.Settings(direction="aa", mem=5, eps=EPS_OBJ, cg_tol=1e-12, cg_max=5000,
+                                         max_iters=20000, precision=precision,
+                                         workgroups=1 if grid == "1" else 0)) as s:
+        x, y, sv, info = s.solve()
     assert info["status"] == sscs.SOLVED
     nb, nc = np.linalg.norm(prob.b), np.linalg.norm(prob.c)
     pr = np.linalg.norm(prob.A @ x + sv - prob.b) / (1 + nb)
     dr = np.linalg.norm(prob.A.T @ y + prob.c) / (1 + nc)
     cx, by = prob.c @ x, prob.b @ y
     gap = abs(cx + by) / (1 + abs(cx) + abs(by))
-    assert max(pr, dr, gap) <= 1e-6 * 1.0001
+    assert max(pr, dr, gap) <= EPS_OBJ * 1.0001
     assert np.linalg.norm(y - proj_dual_cone(y, prob.cone)) <= 1e-6 * (1 + np.linalg.norm(y))
-    assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-5 * (1 + abs(ref.info["pobj"]))
+    assert abs(info["pobj"] - ref.info["pobj"]) <= 1e-6 * (1 + abs(ref.info["pobj"]))

@@ -161,6 +161,55 @@ def test_zero_direction_is_plain_drs():
     assert res.counts["k2"] == 25
 
 
+def rotation_instance(theta):
+    """n = m = 1, A = [theta], b = c = 0, zero cone: (I + Q) acts on (x, y) as
+    the complex scalar 1 - i theta (derivation in tests/golden/alg1_safeguards.json)."""
+    return G.Problem(A=sp.csr_matrix(np.array([[theta]])), b=np.zeros(1), c=np.zeros(1), cone=G.Cone(z=1))
+
+
+def test_alg1_safeguards_golden():
+    """Step kinds, backtracks, ||R u||, eta and r_safe of the first seven
+    iterations against the hand-derived closed forms: pins the K0 reset of eta,
+    the r_safe update with q to the power nu, the K1/K2 tests, backtracking
+    and the step at the backtracking cap (Algorithm 1)."""
+    d = json.load(open(os.path.join(HERE, "golden", "alg1_safeguards.json")))
+    for case in d["cases"]:
+        st = S.Settings(direction="none", eps=1e-12, max_iters=len(case["kind"]), **case["settings"])
+        res = S.solve(rotation_instance(case["theta"]), st, u0=np.array([1.0, 0.0, 1.0]))
+        h = res.history
+        assert res.status == S.MAX_ITERS and len(h) == len(case["kind"]), case["name"]
+        assert [r["kind"] for r in h] == case["kind"], case["name"]
+        assert [r["ls"] for r in h] == case["ls"], case["name"]
+        for key in ("res", "eta", "r_safe"):
+            np.testing.assert_allclose([r[key] for r in h], case[key], rtol=1e-12, err_msg=case["name"] + " " + key)
+
+
+class _PowerIgnoringFloat(float):
+    """A float whose powers are itself: q ** nu == q for every nu."""
+
+    def __pow__(self, other):
+        return float(self)
+
+
+def test_alg1_safeguards_golden_detects_planted_mistakes():
+    """The golden trace catches the misreadings it is meant to catch.  Planted
+    in the oracle: q instead of q^nu in the r_safe update (the recorded r_safe
+    then differs at nu = 0 and from nu = 3 on).  Checked on the fixture itself: with eta kept
+    at eta0 instead of reset after a K0 step, the K0 test would already pass at
+    nu = 3, where the derived trace takes a K1 step."""
+    d = json.load(open(os.path.join(HERE, "golden", "alg1_safeguards.json")))
+    case = d["cases"][0]
+    kw = dict(case["settings"])
+    kw["q"] = _PowerIgnoringFloat(kw["q"])
+    st = S.Settings(direction="none", eps=1e-12, max_iters=len(case["kind"]), **kw)
+    h = S.solve(rotation_instance(case["theta"]), st, u0=np.array([1.0, 0.0, 1.0])).history
+    got = np.array([r["r_safe"] for r in h])
+    assert np.allclose(got[1:3], case["r_safe"][1:3], rtol=1e-12)     # q^1 = q
+    assert not np.isclose(got[0], case["r_safe"][0], rtol=1e-6)         # q^0 = 1
+    assert not np.allclose(got[3:], case["r_safe"][3:], rtol=1e-6)
+    assert case["kind"][3] == "K1" and case["res"][3] <= case["settings"]["c0"] * case["res"][0]
+
+
 # ------------------------------------------------------------ whole solves
 
 def test_closed_form_golden():

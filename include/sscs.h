@@ -220,6 +220,25 @@ int sscs_batch_solve(sscs_batch *bt, const double *u0_packed, double *x_packed,
                      double *y_packed, double *s_packed, sscs_info *infos);
 int sscs_batch_destroy(sscs_batch *bt);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * instance solved by the batched engine exactly as sscs_batch_create +
+ * sscs_batch_solve + sscs_batch_destroy would solve it as a batch of one,
+ * with every device buffer (A and its transpose, b, c, the cone tables, the
+ * iteration vectors, the queue and the result) carved from a static 32 MiB
+ * device array instead of allocated.  Arguments are those of sscs_create and
+ * sscs_solve: data and cone are host arrays; u0 (may be NULL), x, y, s are
+ * host arrays, or device arrays when st->data_on_device is set.
+ * SSCS_E_UNSUPPORTED when the instance does not fit the 32 MiB (about
+ * 12 nnz(A) * 2 + 8 (2 mem + 16) (n + m) bytes), for PSD orders above 64 and
+ * for mixed precision.  Calls no hipMalloc / hipFree.  Each GPU holds one
+ * copy of the array until the process ends and every call on that GPU uses
+ * it, so calls that overlap on one GPU race: one call at a time per GPU.
+ * Work is enqueued on hip_stream and the call returns after it finished. */
+int sscs_solve_noalloc(const sscs_data *data, const sscs_cone *cone, const sscs_settings *st,
+                       void *hip_stream, const double *u0, double *x, double *y, double *s,
+                       sscs_info *info);
+
 const char *sscs_error_string(int code);
 
 #ifdef __cplusplus

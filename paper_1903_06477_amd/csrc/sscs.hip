@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -297,6 +298,7 @@ __global__ void k_sort_rows(const int* __restrict__ trp, int rows, int* __restri
 namespace {
 
 thread_local std::string g_last_hip;
+thread_local const char* g_unsupported = nullptr;   // reason of the last SSCS_E_UNSUPPORTED, if given
 
 #define HIP_TRY(expr)                                                      \
     do {                                                                   \
@@ -1117,7 +1119,10 @@ const char* sscs_error_string(int code) {
         case SSCS_E_INVALID: return "invalid argument";
         case SSCS_E_NOMEM: msg = "out of memory"; break;
         case SSCS_E_HIP: msg = "HIP error"; break;
-        case SSCS_E_UNSUPPORTED: return "unsupported";
+        case SSCS_E_UNSUPPORTED:
+            if (!g_unsupported) return "unsupported";
+            msg = std::string("unsupported: ") + g_unsupported;
+            return msg.c_str();
         case SSCS_E_DEVICE: msg = "device engine failure"; break;
         default: return "unknown error";
     }
@@ -1325,6 +1330,273 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
     if (infos)
         for (int i = 0; i < bt->count; ++i) fill_info(&infos[i], r[i], bt->setup_s, el);
     return SSCS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free one-shot solve
+//
+// sscs_solve_noalloc: the one-instance batched solve (sscs_batch_create +
+// sscs_batch_solve + sscs_batch_destroy for count = 1, the same kernels) with
+// every device buffer carved from one file-scope device array instead of
+// hipMalloc'd memory.  Each GPU holds its own copy of the array until the
+// process ends; calls on one GPU share it, so calls that overlap on one GPU
+// race (one call at a time per GPU).
+
+namespace {
+constexpr size_t kScratchBytes = size_t(32) << 20;      // 32 MiB per GPU
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once per
+// device with that device current.  In host code the array's name is only a
+// host-side handle, never a device address.
+int scratch_base(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_unsupported = "device index beyond the scratch table";
+        return SSCS_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            g_last_hip = "hipGetSymbolAddress returned no address for the scratch array";
+            return SSCS_E_HIP;
+        }
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SSCS_OK;
+}
+
+// Bump allocator over the scratch array (256-byte aligned pieces); only
+// computes offsets, so running it with base = nullptr gives the footprint.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+__global__ void k_fill_int(int* __restrict__ a, long long n, int v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+// Cone offset tables from the block sizes (one thread: the tables of one
+// instance are short).
+__global__ void k_cone_tables(const int* __restrict__ q, int nq, const int* __restrict__ s, int ns,
+                              int* __restrict__ qoff, int* __restrict__ soff) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int run = 0;
+    qoff[0] = 0;
+    for (int i = 0; i < nq; ++i) { run += q[i]; qoff[i + 1] = run; }
+    run = 0;
+    soff[0] = 0;
+    for (int i = 0; i < ns; ++i) { run += s[i] * (s[i] + 1) / 2; soff[i + 1] = run; }
+}
+
+// Ascending list of the rows longer than thr nonzeros (one workgroup; each
+// chunk of rows is compacted with a prefix sum of its flags); *count gets the
+// list length.
+__global__ void __launch_bounds__(256) k_long_rows(const int* __restrict__ rp, int rows, int thr,
+                                                   int* __restrict__ out, int* __restrict__ count) {
+    __shared__ int flag[256];
+    int base = 0;
+    for (int r0 = 0; r0 < rows; r0 += blockDim.x) {
+        const int r = r0 + threadIdx.x;
+        const int f = (r < rows && rp[r + 1] - rp[r] > thr) ? 1 : 0;
+        flag[threadIdx.x] = f;
+        __syncthreads();
+        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+            const int v = threadIdx.x >= (unsigned)o ? flag[threadIdx.x - o] : 0;
+            __syncthreads();
+            flag[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (f) out[base + flag[threadIdx.x] - 1] = r;
+        const int tot = flag[blockDim.x - 1];
+        __syncthreads();
+        base += tot;
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sscs_solve_noalloc(const sscs_data* data, const sscs_cone* cone, const sscs_settings* st, void* hip_stream,
+                       const double* u0, double* x, double* y, double* s, sscs_info* info) {
+    try {
+        g_unsupported = nullptr;
+        if (!x || !y || !s) return SSCS_E_INVALID;
+        TRY(validate(data, cone));
+        TRY(validate_settings(st));
+        if (st->precision != SSCS_PREC_FP64) {                      // as the batched engine
+            g_unsupported = "sscs_solve_noalloc runs the FP64 operator only";
+            return SSCS_E_UNSUPPORTED;
+        }
+        int kmax = 0;
+        long long qsum = 0;
+        for (int i = 0; i < cone->ns; ++i) kmax = std::max(kmax, cone->s[i]);
+        for (int i = 0; i < cone->nq; ++i) qsum += cone->q[i];
+        if (kmax > 64) {
+            g_unsupported = "sscs_solve_noalloc takes PSD blocks up to order 64";
+            return SSCS_E_UNSUPPORTED;
+        }
+        const double t0 = now_s();
+        const hipStream_t strm = (hipStream_t)hip_stream;
+        const int n = data->n, m = data->m, N = n + m + 1, mem = st->mem;
+        const long long nnz = data->nnz;
+        const bool dev = st->data_on_device != 0;
+        // layout of the scratch array for this instance (footprint first)
+        auto carve_all = [&](Carver& c, Inst& I, BatchInst** bi, int** order, int** queue, Result** res,
+                             int** qsz, int** ssz, int** cnt, int** nlong, double** vec, double** io) {
+            *res = c.take<Result>(1);
+            *bi = c.take<BatchInst>(1);
+            *order = c.take<int>(1);
+            *queue = c.take<int>(1);
+            *nlong = c.take<int>(2);
+            I.A_rp = c.take<int>(m + 1);
+            I.A_ci = c.take<int>(nnz);
+            I.A_v = c.take<double>(nnz);
+            I.At_rp = c.take<int>(n + 1);
+            I.At_ci = c.take<int>(nnz);
+            I.At_v = c.take<double>(nnz);
+            I.A_long = c.take<int>(m);
+            I.At_long = c.take<int>(n);
+            *cnt = c.take<int>(n);
+            I.dinv = c.take<double>(n);
+            I.b = c.take<double>(m);
+            I.c = c.take<double>(n);
+            I.g = c.take<double>(n + m);
+            *qsz = c.take<int>(cone->nq);
+            *ssz = c.take<int>(cone->ns);
+            I.qoff = c.take<int>(cone->nq + 1);
+            I.sord = *ssz;
+            I.soff = c.take<int>(cone->ns + 1);
+            I.K.psd_scratch = cone->ns > 0 ? c.take<double>(psd_scratch_doubles(kmax)) : nullptr;
+            *vec = c.take<double>(vec_doubles(n, m, mem));
+            *io = dev ? nullptr : c.take<double>((size_t)N + n + 2 * (size_t)m);
+        };
+        {
+            Carver probe{nullptr};
+            Inst I;
+            BatchInst* bi; int *order, *queue, *qsz, *ssz, *cnt, *nlong; Result* res; double *vec, *io;
+            carve_all(probe, I, &bi, &order, &queue, &res, &qsz, &ssz, &cnt, &nlong, &vec, &io);
+            if (probe.off > kScratchBytes) {
+                g_unsupported = "the instance does not fit the 32 MiB device scratch of sscs_solve_noalloc";
+                return SSCS_E_UNSUPPORTED;
+            }
+        }
+        double* base = nullptr;
+        TRY(scratch_base(&base));
+        Carver cv{reinterpret_cast<char*>(base)};
+        Inst I;
+        BatchInst* d_bi; int *d_order, *d_queue, *d_qsz, *d_ssz, *d_cnt, *d_nlong; Result* d_res; double *d_vec, *d_io;
+        carve_all(cv, I, &d_bi, &d_order, &d_queue, &d_res, &d_qsz, &d_ssz, &d_cnt, &d_nlong, &d_vec, &d_io);
+        I.m = m; I.n = n; I.N = N; I.nnz = nnz; I.owns_A = false;
+        // problem data in (the caller's host arrays, as sscs_create takes them)
+        HIP_TRY(hipMemcpyAsync(I.A_rp, data->rowptr, (m + 1) * sizeof(int), hipMemcpyHostToDevice, strm));
+        if (nnz) {
+            HIP_TRY(hipMemcpyAsync(I.A_ci, data->colind, nnz * sizeof(int), hipMemcpyHostToDevice, strm));
+            HIP_TRY(hipMemcpyAsync(I.A_v, data->val, nnz * sizeof(double), hipMemcpyHostToDevice, strm));
+        }
+        HIP_TRY(hipMemcpyAsync(I.b, data->b, m * sizeof(double), hipMemcpyHostToDevice, strm));
+        HIP_TRY(hipMemcpyAsync(I.c, data->c, n * sizeof(double), hipMemcpyHostToDevice, strm));
+        if (cone->nq) HIP_TRY(hipMemcpyAsync(d_qsz, cone->q, cone->nq * sizeof(int), hipMemcpyHostToDevice, strm));
+        if (cone->ns) HIP_TRY(hipMemcpyAsync(d_ssz, cone->s, cone->ns * sizeof(int), hipMemcpyHostToDevice, strm));
+        // A^T and the Jacobi diagonal: the kernels and launch shapes of upload_instance;
+        // counters cleared by a fill kernel (the array keeps the previous call's contents)
+        const int fb = (int)std::min<long long>(4096, (n + 255) / 256 + 1);
+        k_fill_int<<<fb, 256, 0, strm>>>(d_cnt, n, 0);
+        if (nnz) k_count_cols<<<std::min<long long>(4096, (nnz + 255) / 256), 256, 0, strm>>>(I.A_ci, nnz, d_cnt);
+        k_scan<<<1, 1024, 0, strm>>>(d_cnt, n, I.At_rp);
+        k_fill_int<<<fb, 256, 0, strm>>>(d_cnt, n, 0);
+        k_scatter_t<<<std::min(4096, (m + 255) / 256), 256, 0, strm>>>(I.A_rp, I.A_ci, I.A_v, m, I.At_rp, d_cnt,
+                                                                       I.At_ci, I.At_v);
+        k_sort_rows<<<std::min(4096, (n + 255) / 256), 256, 0, strm>>>(I.At_rp, n, I.At_ci, I.At_v, I.dinv);
+        I.segA = pow2_seg((double)nnz / std::max(1, m));
+        I.segAt = pow2_seg((double)nnz / std::max(1, n));
+        I.lthrA = 64 * I.segA;
+        I.lthrAt = 64 * I.segAt;
+        k_long_rows<<<1, 256, 0, strm>>>(I.A_rp, m, I.lthrA, I.A_long, d_nlong);
+        k_long_rows<<<1, 256, 0, strm>>>(I.At_rp, n, I.lthrAt, I.At_long, d_nlong + 1);
+        k_cone_tables<<<1, 1, 0, strm>>>(d_qsz, cone->nq, d_ssz, cone->ns, I.qoff, I.soff);
+        HIP_TRY(hipGetLastError());
+        int nl[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(nl, d_nlong, sizeof(nl), hipMemcpyDeviceToHost, strm));
+        HIP_TRY(hipStreamSynchronize(strm));
+        I.nlongA = nl[0];
+        I.nlongAt = nl[1];
+        I.K.z = cone->z; I.K.l = cone->l; I.K.nq = cone->nq; I.K.qoff = I.qoff;
+        I.K.ns = cone->ns; I.K.sord = I.sord; I.K.soff = I.soff; I.K.ep = cone->ep;
+        I.K.soc0 = cone->z + cone->l;
+        I.K.psd0 = I.K.soc0 + (int)qsum;
+        long long psum = 0;
+        for (int i = 0; i < cone->ns; ++i) psum += (long long)cone->s[i] * (cone->s[i] + 1) / 2;
+        I.K.exp0 = I.K.psd0 + (int)psum;
+        I.K.psd_kmax = kmax;
+        I.K.psd_team = nullptr; I.K.psd_vecs = nullptr; I.K.psd_warm = nullptr;
+        // the instance record of the batched kernel
+        BatchInst h{};
+        h.P = make_prob(I);
+        h.V = carve(d_vec, n, m, mem);
+        const double* du0 = nullptr;
+        if (u0) {
+            if (dev) du0 = u0;
+            else {
+                HIP_TRY(hipMemcpyAsync(d_io, u0, N * sizeof(double), hipMemcpyHostToDevice, strm));
+                du0 = d_io;
+            }
+        }
+        h.V.u0 = du0;
+        h.V.out_x = dev ? x : d_io + N;
+        h.V.out_y = dev ? y : d_io + N + n;
+        h.V.out_s = dev ? s : d_io + N + n + m;
+        h.V.tr_res = nullptr; h.V.tr_kind = nullptr; h.V.tr_ls = nullptr; h.V.tr_cap = 0;
+        h.V.tr_eta = nullptr; h.V.tr_rsafe = nullptr;
+        HIP_TRY(hipMemcpyAsync(d_bi, &h, sizeof(h), hipMemcpyHostToDevice, strm));
+        k_fill_int<<<1, 64, 0, strm>>>(d_order, 1, 0);
+        k_fill_int<<<1, 64, 0, strm>>>(d_queue, 1, 0);
+        int dv = 0, rate = 0;
+        HIP_TRY(hipGetDevice(&dv));
+        HIP_TRY(hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dv));
+        Params P = make_params(*st, rate > 0 ? rate * 1000.0 : 1e8);
+        const int stage = stage_doubles((long long)n + m);
+        k_solve_batch<double><<<1, kBatchBlock, stage * sizeof(double), strm>>>(d_bi, d_order, 1, P, d_res, d_queue,
+                                                                                stage);
+        HIP_TRY(hipGetLastError());
+        if (!dev) {
+            HIP_TRY(hipMemcpyAsync(x, d_io + N, n * sizeof(double), hipMemcpyDeviceToHost, strm));
+            HIP_TRY(hipMemcpyAsync(y, d_io + N + n, m * sizeof(double), hipMemcpyDeviceToHost, strm));
+            HIP_TRY(hipMemcpyAsync(s, d_io + N + n + m, m * sizeof(double), hipMemcpyDeviceToHost, strm));
+        }
+        Result r{};
+        HIP_TRY(hipMemcpyAsync(&r, d_res, sizeof(Result), hipMemcpyDeviceToHost, strm));
+        HIP_TRY(hipStreamSynchronize(strm));
+        const double el = now_s() - t0;
+        fill_info(info, r, 0.0, el);
+        return SSCS_OK;
+    } catch (...) {
+        return SSCS_E_NOMEM;
+    }
 }
 
 }  // extern "C"

@@ -61,7 +61,7 @@ class _Info(ctypes.Structure):
 EXPORTS = ["sscs_default_settings", "sscs_create", "sscs_solve", "sscs_update_settings", "sscs_update_bc",
            "sscs_destroy", "sscs_linear_step", "sscs_project_dual_cone", "sscs_residual", "sscs_spmv",
            "sscs_spmv_bench", "sscs_get_trace", "sscs_batch_create", "sscs_batch_update_bc",
-           "sscs_batch_solve", "sscs_batch_destroy", "sscs_error_string",
+           "sscs_batch_solve", "sscs_batch_destroy", "sscs_solve_noalloc", "sscs_error_string",
            "sscs_mlp_create", "sscs_mlp_destroy", "sscs_mlp_set_params", "sscs_mlp_get_params",
            "sscs_mlp_forward", "sscs_mlp_train_step", "sscs_mlp_gradients", "sscs_mlp_gemm_nt",
            "sscs_assemble_u0"]
@@ -97,6 +97,8 @@ def lib():
         L.sscs_batch_update_bc.argtypes = [vp, vp, vp]
         L.sscs_batch_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(_Info)]
         L.sscs_batch_destroy.argtypes = [vp]
+        L.sscs_solve_noalloc.argtypes = [ctypes.POINTER(_Data), ctypes.POINTER(_Cone), ctypes.POINTER(_Settings), vp,
+                                         vp, vp, vp, vp, ctypes.POINTER(_Info)]
         _lib = L
     return _lib
 
@@ -364,3 +366,25 @@ class BatchSolver:
         ox = np.concatenate([[0], np.cumsum(self.ns)])
         oy = np.concatenate([[0], np.cumsum(self.ms)])
         return [(x[ox[i]:ox[i + 1]], y[oy[i]:oy[i + 1]], s[oy[i]:oy[i + 1]]) for i in range(self.count)]
+
+
+def solve_noalloc(prob, settings: Optional[Settings] = None, u0=None, out=None, stream=None):
+    """One solve through sscs_solve_noalloc (no device allocation: every
+    device buffer lives in the library's static scratch array).  Host numpy
+    arrays unless settings.data_on_device, in which case u0 and
+    out=(x, y, s) are device tensors."""
+    settings = settings or Settings()
+    mm = _Marshal(prob.A, prob.b, prob.c, prob.cone)
+    m, n = prob.A.shape
+    if settings.data_on_device:
+        x, y, s = out
+    else:
+        x, y, s = out if out is not None else (np.empty(n), np.empty(m), np.empty(m))
+        if u0 is not None:
+            u0 = _f64(u0)
+    st = settings.to_c()
+    inf = _Info()
+    _check(lib().sscs_solve_noalloc(ctypes.byref(mm.data), ctypes.byref(mm.cone), ctypes.byref(st),
+                                    ctypes.c_void_p(stream), _vptr(u0), _vptr(x), _vptr(y), _vptr(s),
+                                    ctypes.byref(inf)))
+    return x, y, s, _info_dict(inf)

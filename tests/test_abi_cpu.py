@@ -89,3 +89,16 @@ def test_create_rejects_bad_input_before_touching_the_device():
         sscs.Solver(bad2)
     with pytest.raises(sscs.SSCSError, match="invalid"):
         sscs.Solver(Problem(A=A, b=np.ones(3), c=np.ones(2), cone=Cone(l=3)), sscs.Settings(mem=0))
+
+
+def test_noalloc_rejects_instances_beyond_its_scratch():
+    # checked on the host before any device work: the 20000 x 50000 SOCP
+    # (1e6 nonzeros) needs more than the 32 MiB static scratch
+    from paper_1903_06477_amd import generators as G
+    from paper_1903_06477_amd import sscs
+    prob = G.config2_socp()
+    with pytest.raises(sscs.SSCSError, match="32 MiB"):
+        sscs.solve_noalloc(prob)
+    bad = G.config1_lp()
+    with pytest.raises(sscs.SSCSError, match="unsupported"):
+        sscs.solve_noalloc(bad, sscs.Settings(precision="mixed"))

@@ -59,11 +59,12 @@ def test_gemm_nt_matches_bf16_product(M, shape):
 
 
 def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
 def _cos(a, b):
-    a, b = a.ravel(), b.ravel()
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
     return float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
 
 

@@ -9,11 +9,14 @@ is resident in HBM before timing; outputs go to device buffers.
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (the persistent solve kernel) and the CPU oracle timed on a bounded sample.
 Further fields measure the other workloads on the same GPU: the same SOCP
-with the mixed-precision linear step and by plain relaxed DRS (no SuperMann
-steps), the stand-alone SpMV of the CG, 4096
-batched LASSO instances in one launch, the learned warm start against the
-cold-started method on the shared-A LASSO family, and iterations per second
-on the mixed PSD / exponential-cone instance.
+with the mixed-precision linear step, by plain relaxed DRS (no SuperMann
+steps) and on further seeded instances; the stand-alone SpMV of the CG on
+the SOCP's matrix and on a 1e8-nonzero matrix past the on-package cache; the
+LP (single and 1024 seeds batched); the mixed PSD / exponential-cone
+instance solved to 1e-6; 4096 batched LASSO instances in one launch; the
+learned warm start (90000 training / 10000 held-out instances) against the
+cold-started method and against a training-mean start; and the oracle timed
+on the host for every workload.
 """
 from __future__ import annotations
 
@@ -94,6 +97,110 @@ def cpu_baseline(prob, gpu_iters, budget_iters=60):
                        f"{cores} host cores in affinity set")}
 
 
+def _cpu_env():
+    """Host cores in the affinity set, BLAS thread count and CPU model."""
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas = max([d.get("num_threads", 1) for d in info] or [1])
+    except Exception:
+        blas = None
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), blas, model
+
+
+def cpu_config1(prob, budget_s=5.0):
+    """The oracle on the LP workload (RB memory 10, direct factorisation),
+    whole solves repeated for about budget_s."""
+    from oracle import superscs as S
+    cores, blas, model = _cpu_env()
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        res = S.solve(prob, S.Settings(direction="rb", mem=10), record=False)
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": k / wall, "unit": "solves/s", "cores": int(blas or cores), "kind": "oracle",
+            "sample": f"{k} complete solves ({res.iters} iterations, {res.status_name}); {cores} host cores, {model}"}
+
+
+def cpu_config3(prob, gpu_iters, budget_iters=8):
+    """The oracle on the PSD/exp instance: sparse factorisation plus
+    budget_iters iterations, extrapolated to the GPU's iteration count."""
+    from oracle import superscs as S
+    from oracle.linsys import DirectLinSys
+    cores, blas, model = _cpu_env()
+    t0 = time.perf_counter()
+    lin = DirectLinSys(prob.A, prob.b, prob.c)
+    t_factor = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    res = S.solve(prob, S.Settings(direction="aa", mem=5, max_iters=budget_iters), lin=lin, record=False)
+    per_iter = (time.perf_counter() - t1) / max(1, res.iters)
+    est = t_factor + per_iter * max(1, gpu_iters)
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": int(blas or cores), "kind": "oracle",
+            "sample": (f"sparse LDL of I + A^T A ({t_factor:.1f} s) + {res.iters} iterations ({per_iter:.2f} s each), "
+                       f"extrapolated to {gpu_iters} iterations; {cores} host cores, {model}")}
+
+
+def _pool_init():
+    try:
+        import threadpoolctl
+        threadpoolctl.threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _oracle_solve_family_instance(arg):
+    """Worker: one oracle solve (AA memory 5, eps 1e-6) of instance i of the
+    batched LASSO family (kind 4) or of the shared-A family (kind 5)."""
+    kind, i = arg
+    from paper_1903_06477_amd import generators as G
+    from oracle import superscs as S
+    if kind == 4:
+        p = G.config4_instance(i)
+    else:
+        p = G.config5_family([i], G.config5_shared_A())[0]
+    t0 = time.perf_counter()
+    res = S.solve(p, S.Settings(direction="aa", mem=5), record=False)
+    return time.perf_counter() - t0, res.status
+
+
+def cpu_family(kind, indices, total, budget_s=20.0):
+    """The oracle on a seeded sample of a batched family, one solve per
+    process (1 BLAS thread each, a pool of one process per core, at most 16):
+    throughput = completed solves / wall time, for the family of `total`."""
+    import multiprocessing as mp
+    cores, _, model = _cpu_env()
+    workers = max(1, min(16, cores))
+    ctx = mp.get_context("spawn")
+    done, t0 = 0, time.perf_counter()
+    per = []
+    with ctx.Pool(workers, initializer=_pool_init) as pool:
+        it = iter(indices)
+        while time.perf_counter() - t0 < budget_s:
+            chunk = [(kind, i) for _, i in zip(range(workers), it)]
+            if not chunk:
+                break
+            for dt, st in pool.map(_oracle_solve_family_instance, chunk):
+                per.append(dt)
+                done += 1
+    wall = time.perf_counter() - t0
+    rate = done / wall
+    return {"value": rate, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{done} of the family's {total} instances (seeded order), one process per core with one "
+                       f"BLAS thread, {wall:.1f} s wall, {np.mean(per):.2f} s per solve; the rate stands for "
+                       f"the whole family ({total / rate:.0f} s extrapolated); {model}")}
+
+
 def bench_settings(sscs, max_iters):
     """Anderson memory 5 (the workload's direction); relaxation 1.5, K1 factor
     0.9999 and safeguard decay 0.999 (Algorithm 1 inputs lambda, c1, q; the
@@ -162,34 +269,39 @@ def batched_leg(sscs, G, count=4096, precision="fp64", probs=None):
             "dtype": "f64" if precision == "fp64" else "f32 operator / f64"}
 
 
-def learned_leg(ntrain=2048, ntest=1024, epochs=60):
+def learned_leg(ntrain=90000, ntest=10000, epochs=60):
     """Learned warm start vs the plain cold-started method on the shared-A
-    LASSO family (A 2000 x 1000 at 2%): cold batched solves of `ntrain`
-    instances give the training targets, the network (2000-512-512-10005,
-    BF16 matrix cores) is trained on them, and `ntest` held-out instances are
-    solved cold and warm; the warm time includes inference and cold
-    fallbacks."""
+    LASSO family (A 2000 x 1000 at 2%): batched solves of `ntrain` instances
+    (to 1e-4, checked on the host) give the training targets, the network
+    (2000-512-512-10005, BF16 matrix cores, minibatches of 1024) is trained on
+    them, and `ntest` held-out instances are solved to 1e-6 cold, warm from
+    the network, and warm from the training targets' mean; the warm time
+    includes inference and cold fallbacks."""
     from paper_1903_06477_amd import warmstart as W
     r = W.experiment(ntrain, ntest, epochs, log=lambda s: print(s, file=sys.stderr, flush=True))
-    return {"workload": f"shared-A LASSO family, {ntrain} training / {ntest} test instances (batches of 1024)",
+    return {"workload": f"shared-A LASSO family (A 2000 x 1000 at 2%), {ntrain} training / {ntest} test instances; "
+                        f"network 2000-512-512-10005, minibatches of 1024",
             "cold_s": r["t_cold"], "warm_total_s": r["t_warm_total"], "inference_s": r["t_inference"],
             "warm_solve_s": r["t_warm_solve"], "fallback_s": r["t_fallback"], "fallbacks": r["n_fallback"],
-            "speedup": r["speedup"], "iters_cold_mean": r["iters_cold_mean"],
-            "iters_warm_mean": r["iters_warm_mean"], "cold_solves_per_s": ntest / r["t_cold"],
-            "warm_solves_per_s": ntest / r["t_warm_total"], "train_loss": [r["loss_first"], r["loss_last"]],
-            "training_data_s": r["t_generate"], "training_s": r["t_train"],
-            "warm_worst_residual": r["warm_worst_residual"], "test_loss": r["test_loss"],
+            "final_solved": r["final_solved"],
+            "speedup_vs_cold": r["speedup"], "speedup_vs_mean_start": r["speedup_vs_mean_start"],
+            "iters_cold_mean": r["iters_cold_mean"], "iters_warm_mean": r["iters_warm_mean"],
+            "cold_solves_per_s": ntest / r["t_cold"], "warm_solves_per_s": ntest / r["t_warm_total"],
+            "train_loss": [r["loss_first"], r["loss_last"]], "test_loss": r["test_loss"],
+            "training_data": {"seconds": r["t_generate"], "eps": r["train_eps"], "iters_mean": r["iters_train_mean"],
+                              "solved": r["train_solved"], "worst_host_residual": r["train_worst_residual"]},
+            "training_s": r["t_train"], "family_generation_s": r["t_family"],
+            "warm_worst_residual": r["warm_worst_residual"],
             "ablation_training_mean_start": {"solve_s": r["t_mean_start"], "iters_mean": r["iters_mean_start"]}}
 
 
-def sdp_exp_leg(sscs, G, iters=150):
+def sdp_exp_leg(sscs, G, iters=20000, prob=None):
     """The mixed PSD / exponential-cone instance (64 sparse-PCA blocks of
     order 64 and one of order 256, l1 logistic regression with 5000 samples x
-    1000 features; n = 349033, m = 535113): `iters` iterations of Algorithm 1
-    timed (a complete solve to 1e-6 takes about 4000), reported as iterations
-    per second, FP64, AA memory 5."""
+    1000 features; n = 349033, m = 535113) solved to 1e-6 (iteration cap
+    `iters`), FP64, AA memory 5; pr, dr, gap recomputed on the host."""
     import torch
-    p = G.config3_sdp_exp()
+    p = prob or G.config3_sdp_exp()
     st = bench_settings(sscs, iters)
     s = sscs.Solver(p, st)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
@@ -201,11 +313,118 @@ def sdp_exp_leg(sscs, G, iters=150):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s.close()
+    pr, dr, gap = host_kkt(p, x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy())
+    solved = info["status"] == sscs.SOLVED and max(pr, dr, gap) <= 1e-6 * 1.0001
     return {"workload": "sparse PCA (64 x order 64 + order 256, lambda 2) + l1 logistic regression "
-                        "(5000 x 1000 at 1%), PSD rows 166016, 10000 exp cones",
+                        "(5000 x 1000 at 1%), PSD rows 166016, 10000 exp cones, eps 1e-6",
             "n": p.n, "m": p.m, "nnz": int(p.A.nnz), "iters": info["iters"], "wall_s": wall,
+            "solves_per_s": 1.0 / wall if solved else 0.0,
             "iterations_per_s": info["iters"] / wall, "cg_iters": info["cg_iters"], "res_fp": info["res_fp"],
-            "status": info["status_name"], "pr": info["pr"], "dr": info["dr"], "gap": info["gap"], "dtype": "f64"}
+            "status": info["status_name"], "pr_host": pr, "dr_host": dr, "gap_host": gap, "dtype": "f64"}
+
+
+def host_kkt(p, x, y, s):
+    """pr, dr, gap of Sec. IV-C recomputed on the host in FP64."""
+    nb, nc = np.linalg.norm(p.b), np.linalg.norm(p.c)
+    pr = float(np.linalg.norm(p.A @ x + s - p.b) / (1 + nb))
+    dr = float(np.linalg.norm(p.A.T @ y + p.c) / (1 + nc))
+    cx, by = float(p.c @ x), float(p.b @ y)
+    return pr, dr, abs(cx + by) / (1 + abs(cx) + abs(by))
+
+
+def config1_leg(sscs, G, reps=20, batch=1024):
+    """The LP workload (300 x 100, 10% density, planted optimum, RB memory 10,
+    eps 1e-6): one instance solved `reps` times on the one-workgroup kernel
+    (latency: microseconds per iteration), and `batch` seeded instances of the
+    same family in one batched launch (throughput)."""
+    import torch
+    p = G.config1_lp()
+    st = sscs.Settings(direction="rb", mem=10, eps=1e-6, cg_tol=1e-12, cg_adapt=0.2, cg_max=500,
+                       max_iters=20000, data_on_device=True)
+    dev = torch.device("cuda:0")
+    x = torch.empty(p.n, dtype=torch.float64, device=dev)
+    y = torch.empty(p.m, dtype=torch.float64, device=dev)
+    sv = torch.empty(p.m, dtype=torch.float64, device=dev)
+    with sscs.Solver(p, st) as s:
+        s.solve(out=(x, y, sv))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            info = s.solve(out=(x, y, sv))[3]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+    pr, dr, gap = host_kkt(p, x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy())
+    probs = [G.config1_lp(i) for i in range(batch)]
+    bs = sscs.BatchSolver(probs, st)
+    out = (torch.empty(batch * p.n, dtype=torch.float64, device=dev),
+           torch.empty(batch * p.m, dtype=torch.float64, device=dev),
+           torch.empty(batch * p.m, dtype=torch.float64, device=dev))
+    bs.solve(out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, infos = bs.solve(out=out)
+    torch.cuda.synchronize()
+    bwall = time.perf_counter() - t0
+    bs.close()
+    solved = [i["status"] == sscs.SOLVED for i in infos]
+    its = np.array([i["iters"] for i in infos])
+    return {"workload": "LP 300 x 100 at 10%, K = R+^300, planted optimum, RB memory 10, eps 1e-6",
+            "solves_per_s": 1.0 / wall if info["status"] == sscs.SOLVED else 0.0, "iters": info["iters"],
+            "us_per_iteration": wall * 1e6 / max(1, info["iters"]), "pr_host": pr, "dr_host": dr, "gap_host": gap,
+            "batched": {"instances": batch, "solves_per_s": int(np.sum(solved)) / bwall,
+                        "solved_frac": float(np.mean(solved)),
+                        "unsolved": [{"instance": k, "status": infos[k]["status_name"], "iters": infos[k]["iters"]}
+                                     for k in range(batch) if not solved[k]],
+                        "iters_mean": float(its.mean()), "wall_s": bwall,
+                        "note": "solves/s counts the instances solved to 1e-6 within the 20000-iteration cap"}}
+
+
+def config2_instances_leg(sscs, G, instances=(1, 2, 3, 4)):
+    """The SOCP workload over further seeded instances (one warm-up and one
+    timed solve each): iteration counts and solves/s vary with the instance,
+    since the trajectory of Algorithm 1 does."""
+    import torch
+    rows = []
+    dev = torch.device("cuda:0")
+    for i in instances:
+        p = G.config2_socp(i)
+        st = bench_settings(sscs, 20000)
+        x = torch.empty(p.n, dtype=torch.float64, device=dev)
+        y = torch.empty(p.m, dtype=torch.float64, device=dev)
+        sv = torch.empty(p.m, dtype=torch.float64, device=dev)
+        with sscs.Solver(p, st) as s:
+            s.solve(out=(x, y, sv))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.solve(out=(x, y, sv))[3]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        pr, dr, gap = host_kkt(p, x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy())
+        ok = info["status"] == sscs.SOLVED and max(pr, dr, gap) <= 1e-6 * 1.0001
+        rows.append({"instance": i, "iters": info["iters"], "solve_s": wall, "solves_per_s": 1.0 / wall if ok else 0.0,
+                     "pr_host": pr, "dr_host": dr})
+    v = np.array([r["solves_per_s"] for r in rows])
+    return {"instances": rows, "solves_per_s_mean": float(v.mean()), "solves_per_s_min": float(v.min()),
+            "solves_per_s_max": float(v.max())}
+
+
+def spmv_large_leg(sscs, G, reps=20):
+    """The CG's SpMV on the SOCP workload's matrix shape scaled to 5e6 x 2e4
+    with 1e8 nonzeros (1.2 GB of values and indices, past the 256 MB
+    on-package cache): A (x of 160 KB, cache-resident) and A^T (gathers from
+    a 40 MB vector), FP64, event-timed on device-resident buffers."""
+    p = G.spmv_scaled()
+    nnz, m, n = int(p.A.nnz), p.m, p.n
+    with sscs.Solver(p, sscs.Settings(cg_tol=1e-10, cg_max=50)) as s:
+        ms_a = s.spmv_bench(False, reps) / reps
+        ms_t = s.spmv_bench(True, reps) / reps
+    ba, bt = spmv_bytes(nnz, m, n), spmv_bytes(nnz, n, m)
+    del p
+    return {"workload": f"{m} x {n}, {nnz} nonzeros (20 per row), N(0,1), FP64 values, int32 indices",
+            "device_copy_GBs": copy_bandwidth(),
+            "A_ms": ms_a, "A_GBs": ba / (ms_a * 1e-3) / 1e9, "A_frac": ba / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "At_ms": ms_t, "At_GBs": bt / (ms_t * 1e-3) / 1e9, "At_frac": bt / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_A": ba, "bytes_At": bt}
 
 
 def source_digest():
@@ -320,6 +539,24 @@ def dm_leg(sscs, G, seeds=1, eps=1e-4, max_time=5.0, log=None):
     return out
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Read + write bandwidth of a plain device copy (torch), event-timed: the
+    attainable streaming rate to set the SpMV's fraction of peak against."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling the FETCH_SIZE and
     WRITE_SIZE counters (run under rocprofv3 --pmc)."""
@@ -346,8 +583,13 @@ def main():
     ap.add_argument("--no-sdp", action="store_true", help="skip the PSD / exponential-cone leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain DRS leg")
     ap.add_argument("--no-host-io", action="store_true", help="skip the host-buffer (PCIe-inclusive) leg")
-    ap.add_argument("--sdp-iters", type=int, default=150,
-                    help="iteration cap of the PSD / exponential-cone leg (a large cap times a complete solve)")
+    ap.add_argument("--sdp-iters", type=int, default=20000,
+                    help="iteration cap of the PSD / exponential-cone leg (the default solves it to 1e-6)")
+    ap.add_argument("--no-config1", action="store_true", help="skip the LP leg")
+    ap.add_argument("--no-instances", action="store_true", help="skip the further SOCP instances")
+    ap.add_argument("--no-spmv-large", action="store_true", help="skip the cache-exceeding SpMV leg")
+    ap.add_argument("--learned-train", type=int, default=90000, help="training instances of the learned leg")
+    ap.add_argument("--learned-test", type=int, default=10000, help="held-out instances of the learned leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--dm", type=int, default=0, metavar="SEEDS",
@@ -451,6 +693,7 @@ def main():
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }
     solver.close()
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
     if not args.no_host_io:
         out["host_io"] = host_io_leg(sscs, prob, stream)
     if not args.no_mixed:
@@ -480,15 +723,43 @@ def main():
         out["plain_drs"] = {"solves_per_s": 1.0 / wp if ip["status"] == sscs.SOLVED else 0.0, "iters": ip["iters"],
                             "cg_iters": ip["cg_iters"], "pr": ip["pr"], "dr": ip["dr"], "gap": ip["gap"],
                             "method": "relaxed Douglas-Rachford (lambda 1.5) without SuperMann steps"}
+    del x, y, s
+    if not args.no_instances:
+        log("bench: further SOCP instances")
+        out["socp_instances"] = config2_instances_leg(sscs, G)
+    if not args.no_config1:
+        log("bench: LP leg")
+        out["config1_lp"] = config1_leg(sscs, G)
+    p3 = None
     if not args.no_sdp:
-        out["sdp_exp"] = sdp_exp_leg(sscs, G, args.sdp_iters)
+        log("bench: PSD/exp leg")
+        p3 = G.config3_sdp_exp()
+        out["sdp_exp"] = sdp_exp_leg(sscs, G, args.sdp_iters, prob=p3)
     if not args.no_batched:
+        log("bench: batched leg")
         probs4 = [G.config4_instance(i) for i in range(4096)]
         out["batched"] = batched_leg(sscs, G, probs=probs4)
+    if not args.no_spmv_large:
+        log("bench: cache-exceeding SpMV leg")
+        out["spmv_large"] = spmv_large_leg(sscs, G)
     if not args.no_learned:
-        out["learned_vs_plain"] = learned_leg()
+        log("bench: learned leg")
+        out["learned_vs_plain"] = learned_leg(args.learned_train, args.learned_test)
     if not args.no_cpu:
+        log("bench: CPU oracle legs")
         out["cpu_baseline"] = cpu_baseline(prob, last["iters"])
+        others = {}
+        if not args.no_config1:
+            others["config1_lp"] = cpu_config1(G.config1_lp())
+        if p3 is not None:
+            others["sdp_exp"] = cpu_config3(p3, out["sdp_exp"]["iters"])
+        if not args.no_batched:
+            others["batched_lasso_4096"] = cpu_family(4, range(4096), 4096)
+        if not args.no_learned:
+            from paper_1903_06477_amd.warmstart import TEST_OFFSET
+            others["learned_family_test_cold"] = cpu_family(5, range(TEST_OFFSET, TEST_OFFSET + args.learned_test),
+                                                            args.learned_test)
+        out["cpu_baselines_other_workloads"] = others
     print(json.dumps(out))
 
 

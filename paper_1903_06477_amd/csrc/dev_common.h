@@ -270,11 +270,6 @@ __device__ __forceinline__ void spmv_gather(Team& tm, const Csr<T>& M, Gx&& gx, 
     }
 }
 
-template <typename Team, typename T, typename TX, typename F>
-__device__ __forceinline__ void spmv_rows(Team& tm, const Csr<T>& M, const TX* __restrict__ x, F&& f) {
-    spmv_gather<1>(tm, M, [&](int c) { return x[c]; }, f);
-}
-
 // Team SpMV over the rows a workgroup owns (MatPart): for every owned row r,
 // f(r, sum_k v[k] gx(ci[k])) is called by the first lane of the segment that
 // owns r.  Same segment scheme and ROWS-way batching as spmv_gather, with the

@@ -46,13 +46,6 @@ struct OpArgs {
     int maxit;
 };
 
-// A flat team over a plain (non-cooperative) grid: no barriers, used by
-// kernels that never synchronise across workgroups.
-struct FlatTeam {
-    __device__ int rank() const { return blockIdx.x * blockDim.x + threadIdx.x; }
-    __device__ int size() const { return gridDim.x * blockDim.x; }
-};
-
 }  // namespace
 
 // ------------------------------------------------------------------ kernels
@@ -207,9 +200,99 @@ __global__ void k_to_f32(const double* __restrict__ a, long long n, float* __res
         b[i] = (float)a[i];
 }
 
+// Stand-alone SpMV for operators that stay in the caches: the CG's
+// row-segmented scheme over a flat grid (seg lanes per row, chosen from the
+// mean row length).
+struct FlatTeam {
+    __device__ int rank() const { return blockIdx.x * blockDim.x + threadIdx.x; }
+    __device__ int size() const { return gridDim.x * blockDim.x; }
+};
+
 __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __restrict__ y) {
     FlatTeam tm;
-    spmv_rows(tm, M, x, [&](int r, double s) { y[r] = s; });
+    spmv_gather<1>(tm, M, [&](int c) { return x[c]; }, [&](int r, double s) { y[r] = s; });
+}
+
+// Stand-alone SpMV, column-panel form, for operators that stream from HBM:
+// the input vector is cut into panels of at most kPanelCols entries, and a
+// workgroup of 1024 threads (one per CU: the panel fills the LDS) stages its
+// panel of x in LDS once and then runs the row-segmented product over a chunk
+// of rows, gathering from LDS instead of the cache hierarchy (measured: with
+// x in L2 each 8-byte gather costs a cache-line transfer and caps the product
+// far below the streaming rate of the operator).  Work item i is (panel p,
+// share c, shares C) in items[3 i .. 3 i + 2]: the C workgroups of panel p
+// interleave its rows segment by segment (at any moment the grid streams
+// through one region of the operator).  With one panel the sums go to
+// y; with several, row r's entries of panel p are the contiguous range
+// [cut[r (P+1) + p], cut[r (P+1) + p + 1]) of the CSR arrays (columns are
+// sorted) and its partial sum goes to part[p rows + r], summed over the
+// panels in order by k_panel_sum.
+constexpr int kPanelCols = 20480;      // 160 KB of FP64 entries per panel
+constexpr int kPanelThreads = 1024;
+template <int S>
+__global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(Csr<double> M, const int* __restrict__ items, int nitems,
+                                                              int P, int pc, const int* __restrict__ cut,
+                                                              const double* __restrict__ x, double* __restrict__ y,
+                                                              double* __restrict__ part) {
+    double* xs = sscs_dyn_lds;
+    int cur = -1;
+    const int seg = threadIdx.x / S, nseg = blockDim.x / S, ls = threadIdx.x & (S - 1);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int p = items[3 * it], c = items[3 * it + 1], C = items[3 * it + 2];
+        const int c0 = p * pc;
+        if (p != cur) {
+            __syncthreads();
+            const int len = min(pc, M.cols - c0);
+            for (int i = threadIdx.x; i < len; i += blockDim.x) xs[i] = x[c0 + i];
+            __syncthreads();
+            cur = p;
+        }
+        for (int r = c * nseg + seg; r < M.rows; r += C * nseg) {
+            int kb, ke;
+            if (P == 1) {
+                kb = M.rp[r];
+                ke = M.rp[r + 1];
+            } else {
+                kb = cut[(size_t)r * (P + 1) + p];
+                ke = cut[(size_t)r * (P + 1) + p + 1];
+            }
+            double acc = 0.0;
+            for (int k = kb + ls; k < ke; k += S) acc += M.v[k] * xs[M.ci[k] - c0];
+#pragma unroll
+            for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+            if (ls == 0) {
+                if (P == 1) y[r] = acc;
+                else part[(size_t)p * M.rows + r] = acc;
+            }
+        }
+    }
+}
+
+__global__ void k_panel_sum(const double* __restrict__ part, int P, int rows, double* __restrict__ y) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int p = 0; p < P; ++p) a += part[(size_t)p * rows + r];
+        y[r] = a;
+    }
+}
+
+// Split points of every row at the panel boundaries (first entry with column
+// >= p pc, by binary search over the row's sorted columns).
+__global__ void k_panel_cuts(const int* __restrict__ rp, const int* __restrict__ ci, int rows, int P, int pc,
+                             int* __restrict__ cut) {
+    const long long total = (long long)rows * (P + 1);
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(t / (P + 1)), p = (int)(t % (P + 1));
+        int lo = rp[r], hi = rp[r + 1];
+        if (p == P) { cut[t] = hi; continue; }
+        const int key = p * pc;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        cut[t] = lo;
+    }
 }
 
 // --- setup: CSR transpose ------------------------------------------------------
@@ -367,13 +450,15 @@ struct Inst {
     int lds_bytes = 0;                     // dynamic LDS of the grid kernels (0: operator in HBM)
 };
 
-int validate(const sscs_data* d, const sscs_cone* k) {
+// check_csr = false skips the walk over A (an instance that shares instance
+// 0's arrays, already checked).
+int validate(const sscs_data* d, const sscs_cone* k, bool check_csr = true) {
     if (!d || !k) return SSCS_E_INVALID;
     if (d->m < 1 || d->n < 1 || d->nnz < 0) return SSCS_E_INVALID;
     if (!d->rowptr || (d->nnz > 0 && (!d->colind || !d->val)) || !d->b || !d->c) return SSCS_E_INVALID;
     if (d->nnz >= (1ll << 31)) return SSCS_E_UNSUPPORTED;
     if (d->rowptr[0] != 0 || d->rowptr[d->m] != d->nnz) return SSCS_E_INVALID;
-    for (int i = 0; i < d->m; ++i) {
+    for (int i = 0; check_csr && i < d->m; ++i) {
         if (d->rowptr[i + 1] < d->rowptr[i]) return SSCS_E_INVALID;
         for (int kk = d->rowptr[i]; kk < d->rowptr[i + 1]; ++kk) {
             const int j = d->colind[kk];
@@ -639,8 +724,19 @@ Vecs carve(double* base, int n, int m, int mem) {
 
 // ------------------------------------------------------------------ single instance
 
+// Plan of the column-panel SpMV for one matrix (built at its first
+// stand-alone product).
+struct PanelPlan {
+    bool built = false, use = false;
+    int P = 1, pc = 0, S = 8, nitems = 0;
+    int* items = nullptr;
+    int* cut = nullptr;
+    double* part = nullptr;
+};
+
 struct sscs_work {
     hipStream_t stream = nullptr;
+    PanelPlan panel[2];          // A, A^T
     sscs_settings st{};
     Inst I;
     double* vecbuf = nullptr;
@@ -703,6 +799,97 @@ template <bool L, typename T, bool P> struct OpGridK { static constexpr auto fn 
 bool team_psd(const Inst& I) { return I.K.psd_kmax > kPsdTeamOrder; }
 const void* solve_grid_fn(bool lds, const Inst& I) { return pick_grid<SolveGridK>(lds, I.mixed, team_psd(I)); }
 const void* op_grid_fn(bool lds, const Inst& I) { return pick_grid<OpGridK>(lds, I.mixed, team_psd(I)); }
+
+// The column-panel kernel for S lanes per row.
+const void* panel_kernel(int S) {
+    switch (S) {
+        case 1: return (const void*)k_spmv_panel<1>;
+        case 2: return (const void*)k_spmv_panel<2>;
+        case 4: return (const void*)k_spmv_panel<4>;
+        case 8: return (const void*)k_spmv_panel<8>;
+        case 16: return (const void*)k_spmv_panel<16>;
+        case 32: return (const void*)k_spmv_panel<32>;
+        default: return (const void*)k_spmv_panel<64>;
+    }
+}
+
+// The column-panel plan of A (which = 0) or A^T (1).  It is used when staging
+// the panels costs at most a quarter of the operator's bytes (so large
+// operators take it, small cache-resident ones keep the stream form).
+int panel_plan(sscs_work* w, int which) {
+    PanelPlan& pl = w->panel[which];
+    if (pl.built) return SSCS_OK;
+    pl.built = true;
+    const Inst& I = w->I;
+    const int rows = which ? I.n : I.m, cols = which ? I.m : I.n;
+    const long long nnz = I.nnz;
+    pl.P = (cols + kPanelCols - 1) / kPanelCols;
+    pl.pc = (cols + pl.P - 1) / pl.P;
+    const int G = std::max(1, w->ncu);
+    const int chunks = pl.P >= G ? 1 : (G + pl.P - 1) / pl.P;
+    const double staging = (double)pl.P * chunks * pl.pc * 8.0;
+    pl.use = staging * 4.0 <= (double)nnz * 12.0;
+    if (!pl.use) return SSCS_OK;
+    const double mean = (double)nnz / std::max(1.0, (double)rows * pl.P);
+    pl.S = 1;
+    while (pl.S < 64 && pl.S < mean / 2.5) pl.S <<= 1;
+    std::vector<int> items;
+    for (int p = 0; p < pl.P; ++p)
+        for (int c = 0; c < chunks; ++c) items.insert(items.end(), {p, c, chunks});
+    pl.nitems = (int)items.size() / 3;
+    TRY(dmalloc(&pl.items, items.size()));
+    HIP_TRY(hipMemcpy(pl.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (pl.P > 1) {
+        TRY(dmalloc(&pl.cut, (size_t)rows * (pl.P + 1)));
+        TRY(dmalloc(&pl.part, (size_t)rows * pl.P));
+        const int* drp = which ? I.At_rp : I.A_rp;
+        const int* dci = which ? I.At_ci : I.A_ci;
+        const long long total = (long long)rows * (pl.P + 1);
+        k_panel_cuts<<<(int)std::min<long long>(65535, (total + 255) / 256), 256, 0, w->stream>>>(drp, dci, rows, pl.P,
+                                                                                              pl.pc, pl.cut);
+        HIP_TRY(hipGetLastError());
+    }
+    static const bool attr = [] {
+        bool ok = true;
+        for (const void* f : {panel_kernel(1), panel_kernel(2), panel_kernel(4), panel_kernel(8), panel_kernel(16),
+                              panel_kernel(32), panel_kernel(64)})
+            ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kPanelCols * (int)sizeof(double)) == hipSuccess;
+        return ok;
+    }();
+    if (!attr) pl.use = false;
+    return SSCS_OK;
+}
+
+// y = M x for M = A (transpose 0) or A^T (1), device vectors, on the
+// workspace stream: the column-panel form when the plan takes it, the stream
+// form otherwise.
+int launch_spmv(sscs_work* w, int transpose, const double* dx, double* dy) {
+    TRY(panel_plan(w, transpose ? 1 : 0));
+    const PanelPlan& pl = w->panel[transpose ? 1 : 0];
+    Prob P = make_prob(w->I);
+    const Csr<double>& M = transpose ? P.At : P.A;
+    if (pl.use) {
+        const int grid = std::max(1, std::min(pl.nitems, w->ncu));
+        Csr<double> Mv = M;
+        const int* items = pl.items;
+        int nitems = pl.nitems, np = pl.P, pc = pl.pc;
+        const int* cut = pl.cut;
+        double* part = pl.part;
+        void* args[] = {&Mv, &items, &nitems, &np, &pc, &cut, &dx, &dy, &part};
+        HIP_TRY(hipLaunchKernel(panel_kernel(pl.S), dim3(grid), dim3(kPanelThreads), args,
+                                (size_t)pl.pc * sizeof(double), w->stream));
+        if (pl.P > 1)
+            k_panel_sum<<<std::max(1, std::min(65535, (M.rows + 255) / 256)), 256, 0, w->stream>>>(pl.part, pl.P, M.rows,
+                                                                                                  dy);
+    } else {
+        const long long threads = (long long)M.rows * M.seg;
+        const int grid = (int)std::max<long long>(1, std::min<long long>(65535, (threads + 255) / 256));
+        k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);
+    }
+    HIP_TRY(hipGetLastError());
+    return SSCS_OK;
+}
 
 int run_op(sscs_work* w, int op, const double* in, double* out1, double* out2, double tol, int maxit) {
     Prob P = make_prob(w->I);
@@ -975,6 +1162,7 @@ int sscs_destroy(sscs_work* w) {
     hipFree(w->vecbuf); hipFree(w->io); hipFree(w->scal); hipFree(w->res);
     hipFree(w->bar); hipFree(w->abort_flag); hipFree(w->part);
     hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls); hipFree(w->tr_eta); hipFree(w->tr_rsafe);
+    for (auto& pl : w->panel) { hipFree(pl.items); hipFree(pl.cut); hipFree(pl.part); }
     delete w;
     return SSCS_OK;
 }
@@ -1060,12 +1248,7 @@ int sscs_spmv(sscs_work* w, int32_t transpose, const double* x, double* y) {
     const double* dx = nullptr;
     TRY(stage_in(w, x, lin, 0, &dx));
     double* dy = out_ptr(w, y, 1);
-    Prob P = make_prob(w->I);
-    const Csr<double>& M = transpose ? P.At : P.A;
-    const long long threads = (long long)M.rows * M.seg;
-    const int grid = (int)std::min<long long>(65535, (threads + 255) / 256);
-    k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);
-    HIP_TRY(hipGetLastError());
+    TRY(launch_spmv(w, transpose, dx, dy));
     TRY(stage_out(w, y, dy, lout));
     HIP_TRY(hipStreamSynchronize(w->stream));
     return SSCS_OK;
@@ -1073,18 +1256,14 @@ int sscs_spmv(sscs_work* w, int32_t transpose, const double* x, double* y) {
 
 int sscs_spmv_bench(sscs_work* w, int32_t transpose, int32_t reps, double* ms) {
     if (!w || !ms || reps < 1) return SSCS_E_INVALID;
-    Prob P = make_prob(w->I);
-    const Csr<double>& M = transpose ? P.At : P.A;
     const double* dx = transpose ? w->V.Ru + w->I.n : w->V.Ru;   // any resident vector of the right length
     double* dy = w->V.Rw;
-    const long long threads = (long long)M.rows * M.seg;
-    const int grid = (int)std::min<long long>(65535, (threads + 255) / 256);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);     // warm-up
+    TRY(launch_spmv(w, transpose, dx, dy));     // warm-up (and the plan)
     HIP_TRY(hipEventRecord(e0, w->stream));
-    for (int r = 0; r < reps; ++r) k_spmv<<<grid, 256, 0, w->stream>>>(M, dx, dy);
+    for (int r = 0; r < reps; ++r) TRY(launch_spmv(w, transpose, dx, dy));
     HIP_TRY(hipEventRecord(e1, w->stream));
     HIP_TRY(hipEventSynchronize(e1));
     float f = 0.f;
@@ -1177,7 +1356,10 @@ int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* con
         // form ran without finishing in a test whose cause has not been shown
         if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
         for (int i = 0; i < count; ++i) {
-            TRY(validate(&data[i], &cones[i]));
+            const bool shared = i > 0 && data[i].rowptr == data[0].rowptr && data[i].colind == data[0].colind &&
+                                data[i].val == data[0].val && data[i].m == data[0].m && data[i].n == data[0].n &&
+                                data[i].nnz == data[0].nnz;
+            TRY(validate(&data[i], &cones[i], !shared));
             for (int j = 0; j < cones[i].ns; ++j)
                 if (cones[i].s[j] > 64) return SSCS_E_UNSUPPORTED;
         }

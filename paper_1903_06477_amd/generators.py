@@ -276,6 +276,39 @@ def config5_instance(i: int, A: sp.csr_matrix) -> Problem:
     return lasso_socp(A, b, mu, name=f"lasso5_{i}")
 
 
+def config5_family(indices, A: sp.csr_matrix) -> List[Problem]:
+    """Instances of the shared-A LASSO family with one conic matrix object
+    shared by all of them (the same data as config5_instance(i, A), built
+    without re-assembling the conic matrix per instance)."""
+    base = lasso_socp(A, np.zeros(A.shape[0]), 1.0)
+    md, n = A.shape
+    out = []
+    for i in indices:
+        rng = rng_for(5, int(i))
+        _, bd, mu = lasso_data(rng, md, n, 0.0, A=A)
+        b = np.concatenate([np.zeros(2 * n), -bd, [-0.5, 0.5]])
+        c = np.concatenate([np.zeros(n), mu * np.ones(n), [0.5]])
+        out.append(Problem(A=base.A, b=b, c=c, cone=base.cone, name=f"lasso5_{int(i)}",
+                           meta=dict(Ad=A, bd=bd, mu=mu, n_data=n, m_data=md)))
+    return out
+
+
+def spmv_scaled(m: int = 5_000_000, n: int = 20_000, per_row: int = 20, seed: int = 0) -> Problem:
+    """The SOCP workload's matrix shape scaled in its rows to exceed the
+    on-package cache: m x n with per_row N(0,1) nonzeros in every row (the
+    SOCP has 20 per row on average), columns distinct and sorted (sorted
+    uniform draws spread by their rank), K = R+^m, b = c = 0.  For
+    measuring the CG's products; not a solve workload."""
+    rng = rng_for(7, seed)
+    cols = np.sort(rng.integers(0, n - per_row + 1, size=(m, per_row), dtype=np.int32), axis=1)
+    cols += np.arange(per_row, dtype=np.int32)[None, :]
+    vals = rng.standard_normal(m * per_row)
+    indptr = np.arange(0, m * per_row + 1, per_row, dtype=np.int64)
+    A = sp.csr_matrix((vals, cols.reshape(-1), indptr.astype(np.int32)), shape=(m, n))
+    A.has_sorted_indices = True
+    return Problem(A=A, b=np.zeros(m), c=np.zeros(n), cone=Cone(l=m), name=f"spmv_{m}x{n}")
+
+
 def lasso_dm_instance(n: int, kappa: float, mu: float, seed: int = 0) -> Problem:
     """One problem of the LASSO benchmark family of Sec. V-C: A in R^{m x n}
     with m = ceil(n/5) and condition number kappa (A = U diag(s) V^T, U, V

@@ -311,20 +311,22 @@ class BatchSolver:
                  share_A: bool = False):
         self.settings = settings or Settings()
         self.count = len(probs)
-        self._marsh: List[_Marshal] = []
-        first = None
-        for p in probs:
-            mm = _Marshal(p.A, p.b, p.c, p.cone)
-            if share_A and first is not None:
-                mm.data.rowptr, mm.data.colind, mm.data.val = first.data.rowptr, first.data.colind, first.data.val
-            if first is None:
-                first = mm
-            self._marsh.append(mm)
-        datas = (_Data * self.count)(*[mm.data for mm in self._marsh])
-        cones = (_Cone * self.count)(*[mm.cone for mm in self._marsh])
         if share_A:
-            for i in range(1, self.count):
-                datas[i].rowptr, datas[i].colind, datas[i].val = datas[0].rowptr, datas[0].colind, datas[0].val
+            # one marshalled copy of A (and the cone sizes); per instance only b and c
+            first = _Marshal(probs[0].A, probs[0].b, probs[0].c, probs[0].cone)
+            self._marsh = [first]
+            self._bc = [(_f64(p.b), _f64(p.c)) for p in probs]
+            datas = (_Data * self.count)()
+            cones = (_Cone * self.count)()
+            for i, (b, c) in enumerate(self._bc):
+                d = _Data(first.data.m, first.data.n, first.data.nnz, first.data.rowptr, first.data.colind,
+                          first.data.val, _ptr(b, ctypes.c_double), _ptr(c, ctypes.c_double))
+                datas[i] = d
+                cones[i] = first.cone
+        else:
+            self._marsh = [_Marshal(p.A, p.b, p.c, p.cone) for p in probs]
+            datas = (_Data * self.count)(*[mm.data for mm in self._marsh])
+            cones = (_Cone * self.count)(*[mm.cone for mm in self._marsh])
         self.ns = np.array([p.A.shape[1] for p in probs])
         self.ms = np.array([p.A.shape[0] for p in probs])
         st = self.settings.to_c()
@@ -332,8 +334,7 @@ class BatchSolver:
         _check(lib().sscs_batch_create(self.count, datas, cones, ctypes.byref(st), ctypes.c_void_p(stream),
                                        ctypes.byref(h)))
         self._h = h
-        if share_A:
-            self._marsh = [self._marsh[0]]   # only instance 0's arrays were read for A
+        self._bc = None
 
     def close(self):
         if getattr(self, "_h", None):
@@ -347,7 +348,12 @@ class BatchSolver:
             pass
 
     def update_bc(self, b_packed, c_packed):
-        b, c = _f64(b_packed), _f64(c_packed)
+        """Packed b and c: device tensors when settings.data_on_device, else
+        host arrays."""
+        if self.settings.data_on_device:
+            b, c = b_packed, c_packed
+        else:
+            b, c = _f64(b_packed), _f64(c_packed)
         _check(lib().sscs_batch_update_bc(self._h, _vptr(b), _vptr(c)))
 
     def solve(self, u0_packed=None, out=None):

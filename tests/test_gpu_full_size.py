@@ -183,3 +183,25 @@ def test_sdp_exp_full_solve_meets_tolerance(sscs):
     se = sv[e0:].reshape(-1, 3)
     d = max(np.linalg.norm(v - proj_exp(v)) for v in se)
     assert d <= 1e-6 * (1 + np.linalg.norm(sv))
+
+
+@pytest.mark.parametrize("m,n,per_row", [(2_000_000, 2000, 10), (5_000_000, 20_000, 20)])
+def test_spmv_column_panel_form(sscs, m, n, per_row):
+    """The stand-alone SpMV on operators large enough for its column-panel
+    form (x panels staged in LDS; A^T of these shapes has 98 and 245 panels
+    whose partial sums are added in order), against scipy in FP64: every
+    entry within the summation bound 1e-13 of the row's |v| |x| sum."""
+    p = G.spmv_scaled(m=m, n=n, per_row=per_row)
+    r = np.random.default_rng(m + n)
+    print(f"column-panel SpMV {m} x {n}, {p.A.nnz} nonzeros", flush=True)
+    with sscs.Solver(p, sscs.Settings(cg_tol=1e-10, cg_max=50)) as s:
+        x = r.standard_normal(n)
+        got = s.spmv(x)
+        ref = p.A @ x
+        bound = abs(p.A) @ np.abs(x)
+        assert np.all(np.abs(got - ref) <= 1e-13 * bound + 1e-300)
+        t = r.standard_normal(m)
+        got_t = s.spmv(t, transpose=True)
+        ref_t = p.A.T @ t
+        bound_t = abs(p.A).T @ np.abs(t)
+        assert np.all(np.abs(got_t - ref_t) <= 1e-13 * bound_t + 1e-300)

@@ -155,13 +155,20 @@ def test_assemble_u0_exact(M):
 
 
 def test_small_learned_warm_start_solves(M):
-    """End to end on the LASSO family: cold solves for training data, a few
-    epochs of training, predictions assembled into u0, warm batched solve;
-    every warm-solved instance meets the tolerance recomputed on the host."""
+    """End to end on the LASSO family: solves for training data, a few epochs
+    of training, predictions assembled into u0, warm batched solve; every
+    warm-solved instance meets the tolerance recomputed on the host, and the
+    warm start takes fewer iterations than the cold start on the held-out
+    instances.  Against the warm start built from the training targets' mean
+    the result is printed, not asserted: at this training size the network
+    does not beat it (the full-size comparison is a benchmark leg)."""
     from paper_1903_06477_amd import warmstart as W
     res = W.experiment(ntrain=192, ntest=32, epochs=30, log=lambda s: print(s, flush=True))
+    print(f"iterations: cold {res['iters_cold_mean']:.0f}, network warm {res['iters_warm_mean']:.0f}, "
+          f"training-mean warm {res['iters_mean_start']:.0f}", flush=True)
     assert res["cold_solved"] == 1.0
     assert res["loss_last"] < res["loss_first"]
+    assert res["iters_warm_mean"] < res["iters_cold_mean"]
     # every test instance ends solved: by its warm start, or by the cold fallback
     assert res["final_solved"] == 1.0
     assert res["warm_worst_residual"] <= 1e-6 * 1.0001

@@ -9,10 +9,10 @@ the paper it follows; see each module's docstring.
 from .cones import (proj_zero_dual, proj_nonneg, proj_soc, proj_psd, proj_exp,
                     proj_exp_dual, proj_dual_cone, proj_C, svec, smat)
 from .linsys import DirectLinSys
-from .superscs import Settings, solve, residual, termination, RestartedBroyden, Anderson
+from .superscs import Settings, solve, solve_scs, residual, termination, RestartedBroyden, Anderson
 
 __all__ = [
     "proj_zero_dual", "proj_nonneg", "proj_soc", "proj_psd", "proj_exp", "proj_exp_dual",
     "proj_dual_cone", "proj_C", "svec", "smat", "DirectLinSys", "Settings", "solve",
-    "residual", "termination", "RestartedBroyden", "Anderson",
+    "residual", "termination", "RestartedBroyden", "Anderson", "solve_scs",
 ]

@@ -9,6 +9,7 @@ Sources in the paper:
   * Termination (pr, dr, gap, ic, uc), Sec. IV-C.
   * Restarted Broyden directions, Sec. IV-D-1 and Algorithm 2.
   * Anderson's acceleration, Sec. IV-D-2.
+  * SCS's splitting (DRS on N_C + Q), Sec. IV-A: solve_scs.
 Readings of silent or garbled points (each named where it is used):
   R1 cold start u0 = (0, 0, 1).           R2 w = u + d in a K0 step.
   R3 backtracking capped at ls_max, then the KM step u - lambda R u.
@@ -24,6 +25,7 @@ Readings of silent or garbled points (each named where it is used):
   R10 returned triplet is the barred one; certificates normalised to
       <b, y> = -1 and <c, x> = -1.  R11 Euclidean norms throughout.
   R12 precedence: SOLVED, then INFEASIBLE, then UNBOUNDED.
+  R27 SCS's splitting (solve_scs): the candidate's s is psi-bar - z_psi.
   R17 c0, c1, q, sigma, lambda are inputs of Algorithm 1 without values in the
       paper except c0 = 0.1 for restarted Broyden (Sec. IV-D-1); defaults
       c0 0.99 (0.1 for RB), c1 0.9999, q 0.999, sigma 0.01, lambda 1.5.
@@ -330,3 +332,62 @@ def solve(prob, settings: Settings = Settings(), u0=None, lin: DirectLinSys = No
     x, y, s = xys
     return Result(status=status, x=x, y=y, s=s, iters=nu, info=info, history=history,
                   counts=counts, u=u, setup_s=setup_s, solve_s=time.perf_counter() - t0)
+
+
+# ----------------------------------------------------------------------------
+# SCS's splitting
+# ----------------------------------------------------------------------------
+
+def solve_scs(prob, settings: Settings = Settings(), z0=None, lin: DirectLinSys = None,
+              record: bool = True) -> Result:
+    """SCS as the paper describes it (Sec. IV-A, "SCS and DRS"): Douglas-
+    Rachford splitting on N_C + Q, the reverse order of (drs), relaxed by
+    lambda (equation (km-updates) applied to that splitting's operator):
+        u-bar = Pi_C(z),   u~ = (I + Q)^{-1}(2 u-bar - z),
+        R z = u-bar - u~,  z+ = z - lambda R z.
+    No SuperMann steps.  Termination (Sec. IV-C) on the candidate u-bar =
+    (chi, psi, tau)-bar with sigma-bar = psi-bar - z_psi: at a fixed point
+    u~ = u-bar, so (I + Q) u-bar = 2 u-bar - z and u-bar - z = Q u-bar, whose
+    psi part is b tau - A chi (reading R27).  Cold start z0 = (0, 0, 1)."""
+    t_setup = time.perf_counter()
+    A, cone = prob.A, prob.cone
+    m, n = A.shape
+    assert cone.rows() == m, "cone sizes must add up to the number of rows"
+    if lin is None:
+        lin = DirectLinSys(A, prob.b, prob.c)
+    setup_s = time.perf_counter() - t_setup
+    t0 = time.perf_counter()
+    st = settings
+    z = np.zeros(n + m + 1)
+    z[-1] = 1.0
+    if z0 is not None:
+        z = np.asarray(z0, dtype=np.float64).copy()
+    history = []
+    status, info, xys = 0, {}, None
+    nu = 0
+    for nu in range(st.max_iters + 1):
+        ub = proj_C(z, n, cone)
+        ut = lin.L(2.0 * ub - z)
+        Rz = ub - ut
+        nRz = float(np.linalg.norm(Rz))
+        # termination with sigma-bar = psi-bar - z_psi: the paper's read-out
+        # psi-bar - 2 psi~ + psi evaluated with psi~ = psi = z_psi
+        status, info, xys = termination(lin, z, z, ub, st.eps)
+        info["res_fp"] = nRz
+        if not math.isfinite(nRz):
+            status = NUMERICAL
+        if status:
+            break
+        if nu == st.max_iters:
+            status = MAX_ITERS
+            break
+        if time.perf_counter() - t0 > st.max_time:
+            status = TIME_LIMIT
+            break
+        if record:
+            history.append(dict(nu=nu, res=nRz, pr=info["pr"], dr=info["dr"], gap=info["gap"], kind="K2", ls=0))
+        z = z - st.lam * Rz
+    x, y, s = xys
+    return Result(status=status, x=x, y=y, s=s, iters=nu, info=info, history=history,
+                  counts=dict(k0=0, k1=0, k2=nu, km=0, backtracks=0), u=z, setup_s=setup_s,
+                  solve_s=time.perf_counter() - t0)

@@ -459,3 +459,56 @@ def test_status_limits():
     bad.b = bad.b.copy(); bad.b[0] = np.nan
     res = S.solve(bad, S.Settings(max_iters=5))
     assert res.status == S.NUMERICAL
+
+
+# ------------------------------------------------------------ SCS's splitting
+
+def test_scs_splitting_is_conjugate_to_drs():
+    """DRS on N_C + Q and on Q + N_C are conjugate through the reflection
+    R_L = 2 (I + Q)^{-1} - I (an isometry, Q being skew): with z0 = R_L u0, the
+    relaxed iterates satisfy z^k = R_L u^k for every k, where u^k follows
+    equation (drs) with relaxation (written out here step by step)."""
+    p, lin = _lin_and_cone(4)
+    lam = 1.3
+    u = np.zeros(p.n + p.m + 1); u[-1] = 1.0
+    u[:p.n] = np.random.default_rng(1).standard_normal(p.n) * 0.1
+    z0 = 2.0 * lin.L(u) - u
+    for k in (1, 7, 30):
+        res = S.solve_scs(p, S.Settings(lam=lam, max_iters=k, eps=1e-14), z0=z0, lin=lin)
+        uk = u.copy()
+        for _ in range(k):
+            ut = lin.L(uk)
+            Tu = uk + C.proj_C(2 * ut - uk, p.n, p.cone) - ut          # equation (drs)
+            uk = (1 - lam) * uk + lam * Tu                               # relaxed
+        np.testing.assert_allclose(res.u, 2.0 * lin.L(uk) - uk, rtol=1e-10, atol=1e-12)
+
+
+def test_scs_splitting_planted_fixed_point():
+    """z* = u* - Q u* with u* = (x*, y*, 1) the planted optimum is a fixed
+    point of SCS's splitting: R z* = 0 and the read-out returns (x*, y*, s*)."""
+    p = G.config1_lp()
+    lin = DirectLinSys(p.A, p.b, p.c)
+    ustar = np.concatenate([p.x_star, p.y_star, [1.0]])
+    zstar = ustar - Q_dense(p.A, p.b, p.c) @ ustar
+    res = S.solve_scs(p, S.Settings(eps=1e-9), z0=zstar, lin=lin)
+    assert res.status == S.SOLVED and res.iters == 0
+    assert res.info["res_fp"] <= 1e-12 * np.linalg.norm(zstar)
+    np.testing.assert_allclose(res.x, p.x_star, atol=1e-10)
+    np.testing.assert_allclose(res.s, p.s_star, atol=1e-10)
+
+
+@pytest.mark.parametrize("maker", ["lp", "socp"])
+def test_scs_splitting_solves_planted_problems(maker):
+    p = G.config1_lp() if maker == "lp" else G.small_socp(2)
+    res = S.solve_scs(p, S.Settings(eps=1e-8, lam=1.5, max_iters=50000))
+    assert res.status == S.SOLVED
+    pstar = float(p.c @ p.x_star)
+    assert abs(res.info["pobj"] - pstar) <= 1e-6 * (1 + abs(pstar))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_scs_splitting_certificates(seed):
+    r1 = S.solve_scs(G.infeasible_lp(seed), S.Settings(eps=1e-7, max_iters=50000))
+    assert r1.status == S.INFEASIBLE
+    r2 = S.solve_scs(G.unbounded_lp(seed), S.Settings(eps=1e-7, max_iters=50000))
+    assert r2.status == S.UNBOUNDED

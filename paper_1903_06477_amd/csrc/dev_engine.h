@@ -23,7 +23,7 @@ namespace sscs {
 
 enum { ST_SOLVED = 1, ST_INFEASIBLE = 2, ST_UNBOUNDED = 3, ST_MAX_ITERS = 4, ST_TIME_LIMIT = 5,
        ST_NUMERICAL = 6 };
-enum { DIR_RB = 0, DIR_AA = 1, DIR_RES = 2, DIR_ZERO = 3 };
+enum { DIR_RB = 0, DIR_AA = 1, DIR_RES = 2, DIR_ZERO = 3, DIR_SCS = 4 };
 
 struct Prob {
     int n, m, N;
@@ -477,13 +477,16 @@ struct Term {
 // which keeps them out of the registers of the long-lived solve loop.
 // Partial sums of the termination measures (Sec. IV-C) into slots 0..6; the
 // candidate is the barred iterate.  Returns its tau.
+// scs: the candidate's sigma is psi-bar - z_psi (SCS's splitting, z in V.u)
+// instead of psi-bar - 2 psi~ + psi.
 template <typename Team>
-__device__ __forceinline__ double term_partials(Team& tm, Shared& sh, const Prob& P, const Vecs& V, bool timed_out) {
+__device__ __forceinline__ double term_partials(Team& tm, Shared& sh, const Prob& P, const Vecs& V, bool timed_out,
+                                                bool scs = false) {
     const int n = P.n, m = P.m;
     const double tau = V.ub[P.N - 1];
     double a_p = 0.0, a_u = 0.0, a_d = 0.0, a_i = 0.0, a_cx = 0.0, a_by = 0.0;
     spmv_part<1>(tm, P.A, 0, [&](int c_) { return V.ub[c_]; }, [&](int i, double s) {
-        const double sig = V.ub[n + i] - 2.0 * V.ut[n + i] + V.u[n + i];
+        const double sig = scs ? V.ub[n + i] - V.u[n + i] : V.ub[n + i] - 2.0 * V.ut[n + i] + V.u[n + i];
         const double v = s + sig;
         a_u += v * v;
         const double w = v - P.b[i] * tau;
@@ -1027,6 +1030,118 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         res->pobj = T.pobj; res->dobj = T.dobj; res->res = nRu;
     }
     tm.sync();
+}
+
+// SCS's splitting (Sec. IV-A, "SCS and DRS"): Douglas-Rachford splitting on
+// N_C + Q, the reverse order of equation (drs), relaxed by lambda, without
+// SuperMann steps:
+//   u-bar = Pi_C(z),  u~ = (I + Q)^{-1}(2 u-bar - z),  R z = u-bar - u~,
+//   z+ = z - lambda R z.
+// z lives in V.u, u-bar in V.ub, 2 u-bar - z in V.d, u~ in V.ut, R z in V.Ru.
+// Termination (Sec. IV-C) on the candidate u-bar with sigma = psi-bar - z_psi
+// (at a fixed point u-bar - z = Q u-bar).  The same linear step, projections,
+// termination read-out and inexact-CG rule as Algorithm 1; out of line, so
+// Algorithm 1's loop keeps its register allocation.
+template <typename TV, typename Team>
+__device__ __noinline__ void solve_scs(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                                       Result* res) {
+    const int n = P.n, m = P.m, N = P.N;
+    const long long t_start = wall_clock64();
+    for (int i = tm.rank(); i < N; i += tm.size())
+        V.u[i] = V.u0 ? V.u0[i] : (i == N - 1 ? 1.0 : 0.0);
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        V.xw_u[j] = 0.0;
+        V.q_u[j] = 0.0;
+    }
+    tm.sync();
+    const Term& T = *reinterpret_cast<const Term*>(sh.term);
+    long long cgc = 0, nu = 0;
+    int status = 0;
+    double nRz = 0.0, tol = S.cg_adapt > 0.0 ? 1e-6 : S.cg_tol, thr = 0.0;
+    for (nu = 0;; ++nu) {
+        // u-bar = Pi_C(z), the linear step's input 2 u-bar - z
+        project_C(tm, sh, n, N, P.K, [&](int i) { return V.u[i]; }, [&](int i, double v) {
+            V.ub[i] = v;
+            V.d[i] = 2.0 * v - V.u[i];
+        });
+        tm.sync();
+        const bool refresh = !(S.cg_adapt > 0.0) || nu % 64 == 0;
+        const double tau = linear_step<TV>(tm, sh, P, V, V.d, V.ut, V.xw_u, tol, S.cg_max, &cgc, 0.0, &thr, V.q_u,
+                                           refresh);
+        // R z = u-bar - u~ and the termination sums in one reduction
+        double a_r = 0.0, a_z = 0.0;
+        for (int i = tm.rank(); i < N; i += tm.size()) {
+            const double ut = corrected(P, V.ut, tau, i);
+            V.ut[i] = ut;
+            const double r = V.ub[i] - ut;
+            V.Ru[i] = r;
+            a_r += r * r;
+            a_z += V.u[i] * V.u[i];
+        }
+        const bool late = S.max_ticks > 0 && (wall_clock64() - t_start) > S.max_ticks;
+        const bool check = S.check_every <= 1 || nu % S.check_every == 0 || nu >= S.max_iters;
+        double ttau = 0.0;
+        if (check) ttau = term_partials(tm, sh, P, V, late, true);
+        put(sh, 7, a_r);
+        put(sh, 8, a_z);
+        if (check) {
+            tm.reduce(sh, 9);
+            if (threadIdx.x == 0) term_finish(sh, P, S, ttau);
+        } else {
+            for (int k = 0; k < 7; ++k) put(sh, k, 0.0);
+            tm.reduce(sh, 9);
+        }
+        __syncthreads();
+        nRz = sqrt(sh.out[7]);
+        if (S.cg_adapt > 0.0) tol = fmin(1e-3, fmax(S.cg_tol, S.cg_adapt * nRz / fmax(sqrt(sh.out[8]), 1e-300)));
+        status = check ? T.status : 0;
+        if (!isfinite(nRz)) status = ST_NUMERICAL;
+        if (tm.aborted()) status = ST_NUMERICAL;
+        if (!status && nu >= S.max_iters) status = ST_MAX_ITERS;
+        if (!status && check && T.timeout) status = ST_TIME_LIMIT;
+        if (status) {
+            write_trace(tm, V, nu, nRz, -1, 0, 0.0, 0.0);
+            break;
+        }
+        for (int i = tm.rank(); i < N; i += tm.size()) V.u[i] -= S.lam * V.Ru[i];
+        tm.sync();
+        write_trace(tm, V, nu, nRz, 2, 0, 0.0, 0.0);
+    }
+    // outputs: the candidate (u-bar with sigma = psi-bar - z_psi) or the certificate
+    const double tau = T.tau;
+    const double nan = NAN;
+    for (int j = tm.rank(); j < n; j += tm.size()) {
+        double x = nan;
+        if (status == ST_UNBOUNDED) x = V.ub[j] / (-T.cx);
+        else if (status != ST_INFEASIBLE && tau > 0.0) x = V.ub[j] / tau;
+        V.out_x[j] = x;
+    }
+    for (int i = tm.rank(); i < m; i += tm.size()) {
+        const double psi = V.ub[n + i];
+        const double sig = psi - V.u[n + i];
+        double y = nan, s = nan;
+        if (status == ST_INFEASIBLE) y = psi / (-T.by);
+        else if (status == ST_UNBOUNDED) s = sig / (-T.cx);
+        else if (tau > 0.0) { y = psi / tau; s = sig / tau; }
+        V.out_y[i] = y;
+        V.out_s[i] = s;
+    }
+    if (tm.rank() == 0) {
+        res->status = status;
+        res->err = tm.aborted() ? 1 : 0;
+        res->iters = nu;
+        res->k0 = 0; res->k1 = 0; res->k2 = nu; res->km = 0; res->bt = 0; res->cg = cgc;
+        res->pr = T.pr; res->dr = T.dr; res->gap = T.gap; res->ic = T.ic; res->uc = T.uc;
+        res->pobj = T.pobj; res->dobj = T.dobj; res->res = nRz;
+    }
+    tm.sync();
+}
+
+// Algorithm 1 or SCS's splitting, as the settings ask.
+template <typename TV, typename Team>
+__device__ void run_solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S, Result* res) {
+    if (S.direction == DIR_SCS) solve_scs<TV>(tm, sh, P, V, S, res);
+    else solve<TV>(tm, sh, P, V, S, res);
 }
 
 }  // namespace sscs

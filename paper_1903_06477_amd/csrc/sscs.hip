@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S,
     __syncthreads();
     GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
     grid_team_init(tm, d.P);
-    sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res);
+    sscs::run_solve<TV>(tm, sh, d.P, d.V, d.S, res);
 }
 
 template <bool LDS, typename TV, bool PT>
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         __syncthreads();
         block_team_init(tm, d.P, stage_doubles);
         setup_gdelta(tm, sh, d.P, d.V, const_cast<double*>(d.P.g), d.S.setup_tol, d.S.setup_max);
-        sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res + idx);
+        sscs::run_solve<TV>(tm, sh, d.P, d.V, d.S, res + idx);
     }
 }
 
@@ -192,7 +192,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     __syncthreads();
     BlockTeam tm;
     block_team_init(tm, d.P, stage_doubles);
-    sscs::solve<TV>(tm, sh, d.P, d.V, d.S, res);
+    sscs::run_solve<TV>(tm, sh, d.P, d.V, d.S, res);
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, long long n, float* __restrict__ b) {
@@ -485,7 +485,7 @@ int validate(const sscs_data* d, const sscs_cone* k, bool check_csr = true) {
 int validate_settings(const sscs_settings* st) {
     if (!st) return SSCS_E_INVALID;
     if (!(st->eps > 0)) return SSCS_E_INVALID;
-    if (st->direction < 0 || st->direction > 3) return SSCS_E_INVALID;
+    if (st->direction < 0 || st->direction > 4) return SSCS_E_INVALID;
     if (st->mem < 1 || st->mem > MEMMAX) return SSCS_E_INVALID;
     if (st->ls_max < 0 || st->max_iters < 0 || st->cg_max < 0) return SSCS_E_INVALID;
     if (!(st->lambda > 0 && st->lambda < 2)) return SSCS_E_INVALID;

@@ -262,9 +262,9 @@ def test_alg1_safeguards_golden(sscs):
 
 # ------------------------------------------------------------------ end to end
 
-def _compare_solve(sscs, prob, st_o, st_g, pobj_tol=1e-6):
+def _compare_solve(sscs, prob, st_o, st_g, pobj_tol=1e-6, scs=False):
     oracle, S = _oracle()
-    ref = S.solve(prob, st_o)
+    ref = S.solve_scs(prob, st_o) if scs else S.solve(prob, st_o)
     with sscs.Solver(prob, st_g) as s:
         x, y, sv, info = s.solve()
         res, kind, ls = s.trace()
@@ -336,6 +336,34 @@ def test_plain_relaxed_drs(sscs):
                                   sscs.Settings(direction="zero", c0=0.0, lam=1.5, max_iters=30000, cg_tol=1e-13,
                                                 cg_max=5000, record_trace=True))
     assert info["k2"] == info["iters"] and info["k0"] == 0
+
+
+@pytest.mark.parametrize("maker", ["lp", "socp2", "socp0"])
+def test_scs_splitting(sscs, maker):
+    """SCS's splitting (Douglas-Rachford on N_C + Q, relaxation 1.5) on the
+    device against the oracle's: trajectory of ||R z||, status, pr/dr/gap on
+    the host, objective within 1e-6 (both solved to 1e-8)."""
+    prob = {"lp": G.config1_lp, "socp2": lambda: G.small_socp(2), "socp0": lambda: G.small_socp(0)}[maker]()
+    _, S = _oracle()
+    info, ref, ncmp = _compare_solve(
+        sscs, prob, S.Settings(lam=1.5, eps=EPS_OBJ, max_iters=60000),
+        sscs.Settings(direction="scs", lam=1.5, eps=EPS_OBJ, max_iters=60000, cg_tol=1e-13, cg_max=5000,
+                      record_trace=True), scs=True)
+    print(f"SCS splitting {maker}: iters gpu {info['iters']} oracle {ref.iters}, trajectory equal for {ncmp}",
+          flush=True)
+    assert info["k2"] == info["iters"]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_scs_splitting_certificates(sscs, seed):
+    for prob, status in [(G.infeasible_lp(seed), sscs.INFEASIBLE), (G.unbounded_lp(seed), sscs.UNBOUNDED)]:
+        with sscs.Solver(prob, sscs.Settings(direction="scs", eps=1e-7, cg_tol=1e-13, max_iters=50000)) as s:
+            x, y, sv, info = s.solve()
+        assert info["status"] == status
+        if status == sscs.INFEASIBLE:
+            assert abs(prob.b @ y + 1) <= 1e-10 and y.min() >= -1e-12
+        else:
+            assert abs(prob.c @ x + 1) <= 1e-10 and sv.min() >= -1e-12
 
 
 @pytest.mark.parametrize("seed", [0, 1])

@@ -50,7 +50,8 @@ STATUS_NAMES = {1: "solved", 2: "infeasible", 3: "unbounded", 4: "max_iters",
 @dataclasses.dataclass
 class Settings:
     eps: float = 1e-6
-    direction: str = "aa"          # "rb" (Algorithm 2), "aa" (Anderson), "none" (d = -Ru), "zero" (d = 0)
+    direction: str = "aa"          # "rb" (Algorithm 2), "aa" (Anderson, normal equations), "aa_qr"
+                                   # (Anderson, updated QR), "none" (d = -Ru), "zero" (d = 0)
     mem: int = 5
     c0: Optional[float] = None     # default 0.1 for RB (Sec. IV-D-1), 0.99 for AA
     c1: float = 0.9999             # c1, q, lam: reading R17 (the paper leaves them open); with
@@ -156,6 +157,95 @@ class Anderson:
         return -r - (Z - Xi) @ t
 
 
+class AndersonQR:
+    """Anderson's acceleration with t from a QR factorisation of Xi that is
+    updated at every iteration (Sec. IV-D-2, the paper's alternative to the
+    normal equations): Xi = Q R with orthonormal Q (N x k) and upper
+    triangular R, columns oldest first.  A new pair appends a column by
+    classical Gram-Schmidt with one re-orthogonalisation; when the memory is
+    full the oldest column is dropped first and R's Hessenberg remainder is
+    restored to triangular form by Givens rotations, applied to Q's columns
+    alike.  t = R^{-1} Q^T R u; a non-finite t or a zero diagonal gives
+    d = -R u."""
+
+    def __init__(self, mem: int):
+        self.mem = mem
+        self.Z: List[np.ndarray] = []
+        self.Xi: List[np.ndarray] = []
+        self.Q = None                 # N x k
+        self.R = None                 # k x k
+
+    def _drop_oldest(self):
+        self.Z.pop(0)
+        self.Xi.pop(0)
+        H = self.R[:, 1:].copy()      # k x (k-1), upper Hessenberg
+        Q = self.Q.copy()
+        k = H.shape[0]
+        for i in range(k - 1):
+            a, b = H[i, i], H[i + 1, i]
+            r = math.hypot(a, b)
+            c, s = (1.0, 0.0) if r == 0.0 else (a / r, b / r)
+            Hi, Hj = H[i, :].copy(), H[i + 1, :].copy()
+            H[i, :], H[i + 1, :] = c * Hi + s * Hj, -s * Hi + c * Hj
+            H[i + 1, i] = 0.0                   # annihilated by construction
+            Qi, Qj = Q[:, i].copy(), Q[:, i + 1].copy()
+            Q[:, i], Q[:, i + 1] = c * Qi + s * Qj, -s * Qi + c * Qj
+        self.R = H[:k - 1, :]
+        self.Q = Q[:, :k - 1]
+
+    def push(self, z, xi):
+        if len(self.Z) == self.mem:
+            self._drop_oldest()
+        self.Z.append(z.copy())
+        self.Xi.append(xi.copy())
+        if self.Q is None or self.Q.shape[1] == 0:
+            r = float(np.linalg.norm(xi))
+            if not (r > 0.0):
+                self.Z.pop()
+                self.Xi.pop()
+                return
+            self.Q = (xi / r).reshape(-1, 1)
+            self.R = np.array([[r]])
+            return
+        c1 = self.Q.T @ xi
+        q = xi - self.Q @ c1
+        c2 = self.Q.T @ q                       # re-orthogonalisation
+        q = q - self.Q @ c2
+        r = float(np.linalg.norm(q))
+        if not (r > 0.0):                       # xi in the span of the memory: not stored
+            self.Z.pop()
+            self.Xi.pop()
+            return
+        k = self.R.shape[0]
+        R = np.zeros((k + 1, k + 1))
+        R[:k, :k] = self.R
+        R[:k, k] = c1 + c2
+        R[k, k] = r
+        self.R = R
+        self.Q = np.concatenate([self.Q, (q / r).reshape(-1, 1)], axis=1)
+
+    def coefficients(self, r):
+        with np.errstate(all="ignore"):
+            rhs = self.Q.T @ r
+            k = rhs.size
+            t = np.zeros(k)
+            for i in range(k - 1, -1, -1):             # back substitution
+                t[i] = (rhs[i] - self.R[i, i + 1:] @ t[i + 1:]) / self.R[i, i]
+        if not np.all(np.isfinite(t)):
+            return None
+        return t
+
+    def direction(self, r):
+        if not self.Z:
+            return -r.copy()
+        t = self.coefficients(r)
+        if t is None:
+            return -r.copy()
+        Z = np.stack(self.Z, axis=1)
+        Xi = np.stack(self.Xi, axis=1)
+        return -r - (Z - Xi) @ t
+
+
 # ----------------------------------------------------------------------------
 # T-oracle and termination
 # ----------------------------------------------------------------------------
@@ -245,7 +335,8 @@ def solve(prob, settings: Settings = Settings(), u0=None, lin: DirectLinSys = No
     if u0 is not None:
         u = np.asarray(u0, dtype=np.float64).copy()
     rb = RestartedBroyden(st.mem, st.thetabar) if st.direction == "rb" else None
-    aa = Anderson(st.mem, st.aa_reg) if st.direction == "aa" else None
+    aa = (Anderson(st.mem, st.aa_reg) if st.direction == "aa"
+          else AndersonQR(st.mem) if st.direction == "aa_qr" else None)
     counts = dict(k0=0, k1=0, k2=0, km=0, backtracks=0)
     history = []
     eta0 = eta = r_safe = None

@@ -512,3 +512,62 @@ def test_scs_splitting_certificates(seed):
     assert r1.status == S.INFEASIBLE
     r2 = S.solve_scs(G.unbounded_lp(seed), S.Settings(eps=1e-7, max_iters=50000))
     assert r2.status == S.UNBOUNDED
+
+
+# ------------------------------------------------------------ Anderson by an updated QR
+
+def test_anderson_qr_updates_keep_a_qr_factorisation():
+    """After more pushes than the memory holds (drops by Givens rotations),
+    Q stays orthonormal, Q R reproduces the stored Xi, R is upper triangular,
+    and t equals numpy's least-squares solution."""
+    r = np.random.default_rng(21)
+    N = 40
+    aa = S.AndersonQR(5)
+    for _ in range(12):
+        aa.push(r.standard_normal(N), r.standard_normal(N))
+    Xi = np.stack(aa.Xi, axis=1)
+    assert Xi.shape[1] == 5
+    np.testing.assert_allclose(aa.Q.T @ aa.Q, np.eye(5), atol=1e-13)
+    np.testing.assert_allclose(aa.Q @ aa.R, Xi, atol=1e-12 * np.abs(Xi).max())
+    assert np.all(np.tril(aa.R, -1) == 0.0)
+    res = r.standard_normal(N)
+    np.testing.assert_allclose(aa.coefficients(res), np.linalg.lstsq(Xi, res, rcond=None)[0], rtol=1e-10)
+    Z = np.stack(aa.Z, axis=1)
+    t = aa.coefficients(res)
+    np.testing.assert_allclose(aa.direction(res), -res - (Z - Xi) @ t, rtol=1e-12)
+
+
+def test_anderson_qr_robust_where_normal_equations_lose_accuracy():
+    """Xi with condition number ~1e7: the normal equations' t (cond ~1e14)
+    loses most digits, the QR solution keeps the least-squares one."""
+    r = np.random.default_rng(22)
+    N, k = 60, 4
+    U, _ = np.linalg.qr(r.standard_normal((N, k)))
+    V, _ = np.linalg.qr(r.standard_normal((k, k)))
+    Xi = U @ np.diag([1.0, 1e-2, 1e-5, 1e-7]) @ V.T
+    qr, ne = S.AndersonQR(k), S.Anderson(k, reg=0.0)
+    for j in range(k):
+        z = r.standard_normal(N)
+        qr.push(z, Xi[:, j])
+        ne.push(z, Xi[:, j])
+    res = Xi @ r.standard_normal(k) + 1e-3 * r.standard_normal(N)
+    ref = np.linalg.lstsq(Xi, res, rcond=None)[0]
+    e_qr = np.linalg.norm(qr.coefficients(res) - ref) / np.linalg.norm(ref)
+    t_ne = ne.coefficients(res)
+    e_ne = np.inf if t_ne is None else np.linalg.norm(t_ne - ref) / np.linalg.norm(ref)
+    assert e_qr <= 1e-6
+    assert e_ne > 100 * e_qr
+
+
+def test_anderson_qr_solves_like_the_normal_equations():
+    """Same problems, same answers: the QR form tracks the Gram form's
+    trajectory closely at first (different rounding only) and both solve."""
+    p = G.small_socp(2)
+    lin = DirectLinSys(p.A, p.b, p.c)
+    a = S.solve(p, S.Settings(direction="aa", mem=5, eps=1e-8), lin=lin)
+    b = S.solve(p, S.Settings(direction="aa_qr", mem=5, eps=1e-8), lin=lin)
+    assert a.status == b.status == S.SOLVED
+    ra = np.array([h["res"] for h in a.history[:20]])
+    rb = np.array([h["res"] for h in b.history[:20]])
+    np.testing.assert_allclose(rb, ra, rtol=1e-7)
+    assert abs(a.info["pobj"] - b.info["pobj"]) <= 1e-6 * (1 + abs(a.info["pobj"]))

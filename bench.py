@@ -492,7 +492,8 @@ DM_METHODS = [("SCS (DRS on N_C + Q)", dict(direction="scs")),
               ("RB (mem:10)", dict(direction="rb", mem=10)),
               ("RB (mem:16)", dict(direction="rb", mem=16)),
               ("AA (mem:5)", dict(direction="aa", mem=5)),
-              ("AA (mem:10)", dict(direction="aa", mem=10))]
+              ("AA (mem:10)", dict(direction="aa", mem=10)),
+              ("AA-QR (mem:5)", dict(direction="aa_qr", mem=5))]
 
 
 def dm_leg(sscs, G, seeds=1, eps=1e-4, max_time=5.0, log=None):
@@ -733,6 +734,19 @@ def main():
             isc = ss_.solve(out=(x, y, s))[3]
             torch.cuda.synchronize()
             wsc = time.perf_counter() - t0
+        # the same workload with Anderson's t from an updated QR factorisation
+        stq = bench_settings(sscs, args.max_iters)
+        stq.direction = "aa_qr"
+        with sscs.Solver(prob, stq, stream=stream.cuda_stream) as sq_:
+            sq_.solve(out=(x, y, s))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iq = sq_.solve(out=(x, y, s))[3]
+            torch.cuda.synchronize()
+            wq = time.perf_counter() - t0
+        out["aa_qr"] = {"solves_per_s": 1.0 / wq if iq["status"] == sscs.SOLVED else 0.0, "iters": iq["iters"],
+                        "cg_iters": iq["cg_iters"], "pr": iq["pr"], "dr": iq["dr"], "gap": iq["gap"],
+                        "method": "Anderson memory 5, t from an updated QR factorisation of Xi"}
         out["scs_splitting"] = {"solves_per_s": 1.0 / wsc if isc["status"] == sscs.SOLVED else 0.0,
                                 "iters": isc["iters"], "cg_iters": isc["cg_iters"], "pr": isc["pr"], "dr": isc["dr"],
                                 "gap": isc["gap"],

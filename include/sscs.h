@@ -64,6 +64,8 @@ extern "C" {
 #define SSCS_DIR_AA          1   /* Anderson's acceleration */
 #define SSCS_DIR_RESIDUAL    2   /* d = -R u (K0 with c0 = 1 gives plain DRS) */
 #define SSCS_DIR_ZERO        3   /* d = 0: every step is the hyperplane (K2) step */
+#define SSCS_DIR_AA_QR       5   /* Anderson's acceleration with t from an updated QR
+                                    factorisation of Xi (Sec. IV-D-2) */
 #define SSCS_DIR_SCS         4   /* not Algorithm 1: SCS's splitting, Douglas-Rachford on
                                     N_C + Q (Sec. IV-A) relaxed by lambda, no SuperMann
                                     steps; the state is z, the candidate Pi_C(z) */

@@ -200,7 +200,7 @@ class AndersonQR:
         self.Xi.append(xi.copy())
         if self.Q is None or self.Q.shape[1] == 0:
             r = float(np.linalg.norm(xi))
-            if not (r > 0.0):
+            if not (r > 0.0):                   # a zero xi: not stored
                 self.Z.pop()
                 self.Xi.pop()
                 return
@@ -212,7 +212,7 @@ class AndersonQR:
         c2 = self.Q.T @ q                       # re-orthogonalisation
         q = q - self.Q @ c2
         r = float(np.linalg.norm(q))
-        if not (r > 0.0):                       # xi in the span of the memory: not stored
+        if not (r > 1e-14 * float(np.linalg.norm(xi))):   # xi in the span of the memory: not stored
             self.Z.pop()
             self.Xi.pop()
             return

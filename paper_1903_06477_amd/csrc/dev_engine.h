@@ -23,7 +23,7 @@ namespace sscs {
 
 enum { ST_SOLVED = 1, ST_INFEASIBLE = 2, ST_UNBOUNDED = 3, ST_MAX_ITERS = 4, ST_TIME_LIMIT = 5,
        ST_NUMERICAL = 6 };
-enum { DIR_RB = 0, DIR_AA = 1, DIR_RES = 2, DIR_ZERO = 3, DIR_SCS = 4 };
+enum { DIR_RB = 0, DIR_AA = 1, DIR_RES = 2, DIR_ZERO = 3, DIR_SCS = 4, DIR_AA_QR = 5 };
 
 struct Prob {
     int n, m, N;
@@ -49,6 +49,7 @@ struct Vecs {
     double *cg_g[2];                                     // 4 n each: gathered (D r, D s, D w, -) per column
     double *cg_t;                                        // length m
     double *Zb, *Yb;                                     // mem x N memory buffers
+    double* Qb;                                          // mem x N: Q of Xi = Q R (Anderson by QR)
     const double* u0;                                    // warm start or null
     double *out_x, *out_y, *out_s;                       // results
     double* tr_res;                                      // trace (may be null)
@@ -579,6 +580,7 @@ struct DirState {
     int pend;       // 0: no pending pair; 1: (pz, pxi) complete; 2: pxi still needs + R u
     int aa_k, aa_head;
     int rb_m;
+    int aa_old;     // Anderson by QR: ring slot of the oldest pair (logical column 0)
 };
 
 // Anderson: push the pending pair into the ring, update the Gram matrix and
@@ -676,6 +678,212 @@ __device__ __noinline__ void termination_aa_pass(Team& tm, Shared& sh, const Pro
         if (k > 0) aa_gram(sh, S, k, slot, base);
     }
     __syncthreads();
+}
+
+// Anderson by an updated QR factorisation of Xi (Sec. IV-D-2): Xi = Q R with
+// Q (N x k, columns in logical order oldest first, in V.Qb) and R upper
+// triangular (k x k, in sh.G, replicated in every workgroup); Z and Xi stay in
+// the ring of V.Zb / V.Yb, logical column j in slot (aa_old + j) % mem.  Per
+// iteration: (1) with a full memory the oldest column is dropped: Givens
+// rotations restore R[:, 1:] to triangular form and are applied to Q's columns
+// element by element in the pass that also stores the new pair and forms
+// Q^T xi, Q^T R u, <xi, R u>, ||xi||^2 (one reduction, shared with the
+// termination check); (2) q1 = xi - Q c1 and its re-orthogonalisation
+// coefficients c2 = Q^T q1 and ||q1||^2 (one reduction); (3) R gains the column
+// (c1 + c2, r) with r^2 = ||q1||^2 - ||c2||^2 (q1 - Q c2 is orthogonal to Q),
+// unless r <= 1e-14 ||xi|| (xi in the span: the pair is not stored), and
+// t = R^{-1} Q^T R u, where the new column's entry of Q^T R u is
+// (<xi, R u> - (c1 + c2)^T Q^T R u) / r; (4) the new Q column
+// (q1 - Q c2) / r is written in the pass that forms d = -R u - (Z - Xi) t.
+
+// Thread 0: Givens rotations dropping logical column 0 from R (k x k) into
+// sh.L (c_i, s_i pairs), R replaced by the k-1 x k-1 triangular result.
+__device__ inline void aaqr_drop_rotations(Shared& sh, int k) {
+    double* R = sh.G;
+    for (int i = 0; i < k; ++i)                 // H = R[:, 1:] (k x k-1), in place
+        for (int j = 0; j < k - 1; ++j) R[i * MEMMAX + j] = R[i * MEMMAX + j + 1];
+    for (int i = 0; i < k - 1; ++i) {
+        const double a = R[i * MEMMAX + i], b = R[(i + 1) * MEMMAX + i];
+        const double r = hypot(a, b);
+        const double c = r == 0.0 ? 1.0 : a / r, s = r == 0.0 ? 0.0 : b / r;
+        sh.L[2 * i] = c;
+        sh.L[2 * i + 1] = s;
+        for (int j = i; j < k - 1; ++j) {
+            const double hi = R[i * MEMMAX + j], hj = R[(i + 1) * MEMMAX + j];
+            R[i * MEMMAX + j] = c * hi + s * hj;
+            R[(i + 1) * MEMMAX + j] = -s * hi + c * hj;
+        }
+        R[(i + 1) * MEMMAX + i] = 0.0;
+    }
+}
+
+// (1): the termination partials (when check) and the Anderson-QR dot
+// products in one reduction; slots base.. : c1 (k), Q^T R u (k), <xi, R u>,
+// ||xi||^2.  Returns the number of kept columns k.
+template <typename Team>
+__device__ __noinline__ int termination_aaqr_pass(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                                                  DirState& ds, bool timed_out, bool check) {
+    const int N = P.N, mem = S.mem;
+    const int base = check ? 7 : 0;
+    const double tau = check ? term_partials(tm, sh, P, V, timed_out) : 0.0;
+    const bool push = ds.pend != 0;
+    const bool drop = push && ds.aa_k == mem;
+    if (drop) {
+        if (threadIdx.x == 0) aaqr_drop_rotations(sh, mem);
+        __syncthreads();
+        ds.aa_old = (ds.aa_old + 1) % mem;
+        ds.aa_k -= 1;
+    }
+    const int k = ds.aa_k;
+    const int slot = (ds.aa_old + k) % mem;
+    const bool fix = ds.pend == 2;
+    double a1[MEMMAX], aR[MEMMAX];
+    for (int j = 0; j < k; ++j) { a1[j] = 0.0; aR[j] = 0.0; }
+    double axr = 0.0, axx = 0.0;
+    for (int e = tm.rank(); e < N; e += tm.size()) {
+        double q[MEMMAX];
+        const int kq = drop ? k + 1 : k;
+        for (int j = 0; j < kq; ++j) q[j] = V.Qb[(size_t)j * N + e];
+        if (drop) {
+            for (int i = 0; i < k; ++i) {
+                const double c = sh.L[2 * i], s = sh.L[2 * i + 1];
+                const double qi = q[i], qj = q[i + 1];
+                q[i] = c * qi + s * qj;
+                q[i + 1] = -s * qi + c * qj;
+            }
+            for (int j = 0; j < k; ++j) V.Qb[(size_t)j * N + e] = q[j];
+        }
+        const double ru = V.Ru[e];
+        double xi = 0.0;
+        if (push) {
+            xi = V.pxi[e] + (fix ? ru : 0.0);
+            V.Zb[(size_t)slot * N + e] = V.pz[e];
+            V.Yb[(size_t)slot * N + e] = xi;
+            axr += xi * ru;
+            axx += xi * xi;
+        }
+        for (int j = 0; j < k; ++j) {
+            a1[j] += q[j] * xi;
+            aR[j] += q[j] * ru;
+        }
+    }
+    for (int j = 0; j < k; ++j) {
+        put(sh, base + j, a1[j]);
+        put(sh, base + k + j, aR[j]);
+    }
+    put(sh, base + 2 * k, axr);
+    put(sh, base + 2 * k + 1, axx);
+    tm.reduce(sh, base + 2 * k + 2);
+    if (threadIdx.x == 0 && check) term_finish(sh, P, S, tau);
+    __syncthreads();
+    // keep the reduced values the next steps need (sh.out is reused)
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 2 * k + 2; ++j) sh.coef[2 * MEMMAX + j] = sh.out[base + j];
+    __syncthreads();
+    return k;
+}
+
+// (2) and (3): re-orthogonalisation sums, then (thread 0) R's new column and t
+// into sh.coef[slot]; returns the number of stored columns after the step.
+// sh.coef layout: [0, mem) t by ring slot; [2 MEMMAX, ..) c1, Q^T R u, <xi, R u>,
+// ||xi||^2 from (1); sh.L[0, MEMMAX) c2, sh.L[MEMMAX] r, sh.L[MEMMAX + 1] 1 if
+// the column was stored.
+template <typename Team>
+__device__ __noinline__ int aaqr_solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S,
+                                       DirState& ds, int k) {
+    const int N = P.N, mem = S.mem;
+    const bool push = ds.pend != 0;
+    const double* c1 = sh.coef + 2 * MEMMAX;
+    if (push) {
+        const int slot = (ds.aa_old + k) % mem;
+        double a2[MEMMAX];
+        for (int j = 0; j < k; ++j) a2[j] = 0.0;
+        double an = 0.0;
+        for (int e = tm.rank(); e < N; e += tm.size()) {
+            double q1 = V.Yb[(size_t)slot * N + e];
+            double qv[MEMMAX];
+            for (int j = 0; j < k; ++j) {
+                qv[j] = V.Qb[(size_t)j * N + e];
+                q1 -= qv[j] * c1[j];
+            }
+            V.Qb[(size_t)k * N + e] = q1;
+            for (int j = 0; j < k; ++j) a2[j] += qv[j] * q1;
+            an += q1 * q1;
+        }
+        for (int j = 0; j < k; ++j) put(sh, j, a2[j]);
+        put(sh, k, an);
+        tm.reduce(sh, k + 1);
+    }
+    if (threadIdx.x == 0) {
+        double* R = sh.G;
+        const double* qru = c1 + k;
+        double rhs[MEMMAX];
+        for (int j = 0; j < k; ++j) rhs[j] = qru[j];
+        int kn = k;
+        sh.L[MEMMAX + 1] = 0.0;
+        if (push) {
+            double c2n = 0.0;
+            for (int j = 0; j < k; ++j) {
+                sh.L[j] = sh.out[j];
+                c2n += sh.out[j] * sh.out[j];
+            }
+            const double r2 = sh.out[k] - c2n;
+            const double xr = c1[2 * k], xx = c1[2 * k + 1];
+            if (r2 > 1e-28 * xx && isfinite(r2)) {
+                const double r = sqrt(r2);
+                double proj = 0.0;
+                for (int j = 0; j < k; ++j) {
+                    const double col = c1[j] + sh.L[j];
+                    R[j * MEMMAX + k] = col;
+                    proj += col * qru[j];
+                }
+                for (int j = 0; j < k; ++j) R[k * MEMMAX + j] = 0.0;
+                R[k * MEMMAX + k] = r;
+                rhs[k] = (xr - proj) / r;
+                sh.L[MEMMAX] = r;
+                sh.L[MEMMAX + 1] = 1.0;
+                kn = k + 1;
+            }
+        }
+        double t[MEMMAX];
+        bool ok = true;
+        for (int i = kn - 1; i >= 0; --i) {
+            double v = rhs[i];
+            for (int j = i + 1; j < kn; ++j) v -= R[i * MEMMAX + j] * t[j];
+            t[i] = v / R[i * MEMMAX + i];
+            ok = ok && isfinite(t[i]);
+        }
+        for (int j = 0; j < MEMMAX; ++j) sh.coef[j] = 0.0;
+        if (ok)
+            for (int j = 0; j < kn; ++j) sh.coef[(ds.aa_old + j) % mem] = t[j];
+    }
+    __syncthreads();
+    return sh.L[MEMMAX + 1] > 0.0 ? k + 1 : k;
+}
+
+// (4) d = -Ru - (Z - Xi) t over the stored slots, the new Q column finished
+// in the same pass; a K0 step applies d at once.
+template <typename Team>
+__device__ __noinline__ void aaqr_apply(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const Params& S, int k,
+                                        bool stored, bool k0) {
+    const int N = P.N, mem = S.mem;
+    const double r = sh.L[MEMMAX];
+    const int kq = stored ? k - 1 : k;      // columns of Q before the new one
+    for (int e = tm.rank(); e < N; e += tm.size()) {
+        if (stored) {
+            double q = V.Qb[(size_t)kq * N + e];
+            for (int j = 0; j < kq; ++j) q -= V.Qb[(size_t)j * N + e] * sh.L[j];
+            V.Qb[(size_t)kq * N + e] = q / r;
+        }
+        double d = -V.Ru[e];
+        for (int i = 0; i < mem; ++i) {
+            const double t = sh.coef[i];
+            if (t != 0.0) d -= (V.Zb[(size_t)i * N + e] - V.Yb[(size_t)i * N + e]) * t;
+        }
+        V.d[e] = d;
+        if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
+    }
+    tm.sync();
 }
 
 // Restarted Broyden (Algorithm 2).  H = (I + zt_m z_m^T) ... (I + zt_1 z_1^T);
@@ -872,7 +1080,7 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     double* const qu = V.q_u;
     double* const qd = V.q_d;
     tm.sync();
-    DirState ds = {0, 0, 0, 0};
+    DirState ds = {0, 0, 0, 0, 0};
     double eta0 = 0.0, eta = 0.0, r_safe = 0.0;
     long long k0c = 0, k1c = 0, k2c = 0, kmc = 0, btc = 0, cgc = 0;
     const Term& T = *reinterpret_cast<const Term*>(sh.term);
@@ -895,7 +1103,9 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         // termination test (Sec. IV-C) every check_every-th iteration and at the
         // iteration cap; the candidate returned is always that of a tested iteration
         const bool check = S.check_every <= 1 || nu % S.check_every == 0 || nu >= S.max_iters;
+        int qr_k = 0;
         if (S.direction == DIR_AA) termination_aa_pass(tm, sh, P, V, S, ds, late, check);
+        else if (S.direction == DIR_AA_QR) qr_k = termination_aaqr_pass(tm, sh, P, V, S, ds, late, check);
         else if (check) termination_pass(tm, sh, P, V, S, late);
         if (nu == 0) eta0 = eta = r_safe = nRu;
         status = check ? T.status : 0;
@@ -907,6 +1117,10 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
         const bool k0 = nRu <= S.c0 * eta;
         if (S.direction == DIR_AA) {
             aa_apply(tm, sh, P, V, ds.aa_k, k0);            // its dot products went with the termination check
+        } else if (S.direction == DIR_AA_QR) {
+            const int kn = aaqr_solve(tm, sh, P, V, S, ds, qr_k);
+            ds.aa_k = kn;
+            aaqr_apply(tm, sh, P, V, S, kn, kn > qr_k, k0);
         } else if (S.direction == DIR_RB) {
             direction_rb(tm, sh, P, V, S, ds, k0);
         } else {

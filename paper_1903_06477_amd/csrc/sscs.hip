@@ -485,7 +485,7 @@ int validate(const sscs_data* d, const sscs_cone* k, bool check_csr = true) {
 int validate_settings(const sscs_settings* st) {
     if (!st) return SSCS_E_INVALID;
     if (!(st->eps > 0)) return SSCS_E_INVALID;
-    if (st->direction < 0 || st->direction > 4) return SSCS_E_INVALID;
+    if (st->direction < 0 || st->direction > 5) return SSCS_E_INVALID;
     if (st->mem < 1 || st->mem > MEMMAX) return SSCS_E_INVALID;
     if (st->ls_max < 0 || st->max_iters < 0 || st->cg_max < 0) return SSCS_E_INVALID;
     if (!(st->lambda > 0 && st->lambda < 2)) return SSCS_E_INVALID;
@@ -698,7 +698,7 @@ Prob make_prob(const Inst& I) {
 
 size_t vec_doubles(int n, int m, int mem) {
     const size_t N = (size_t)n + m + 1;
-    return 9 * N + 18 * (size_t)n + (size_t)m + 2 * (size_t)mem * N + 8;
+    return 9 * N + 18 * (size_t)n + (size_t)m + 3 * (size_t)mem * N + 8;
 }
 
 // Carves the Vecs of one instance from a contiguous device buffer.
@@ -716,7 +716,7 @@ Vecs carve(double* base, int n, int m, int mem) {
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 31) & ~uintptr_t(31));   // 32-byte records
     V.cg_g[0] = take(4 * (size_t)n); V.cg_g[1] = take(4 * (size_t)n);
     V.cg_t = take(m);
-    V.Zb = take((size_t)mem * N); V.Yb = take((size_t)mem * N);
+    V.Zb = take((size_t)mem * N); V.Yb = take((size_t)mem * N); V.Qb = take((size_t)mem * N);
     return V;
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsscs.so"
 SOLVED, INFEASIBLE, UNBOUNDED, MAX_ITERS, TIME_LIMIT, NUMERICAL = 1, 2, 3, 4, 5, 6
 STATUS_NAMES = {1: "solved", 2: "infeasible", 3: "unbounded", 4: "max_iters", 5: "time_limit",
                 6: "numerical"}
-DIRECTIONS = {"rb": 0, "aa": 1, "residual": 2, "none": 2, "zero": 3, "scs": 4}
+DIRECTIONS = {"rb": 0, "aa": 1, "residual": 2, "none": 2, "zero": 3, "scs": 4, "aa_qr": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int32)

@@ -312,7 +312,8 @@ def test_config1_lp_rb(sscs):
 
 
 @pytest.mark.parametrize("seed", [0, 2])
-@pytest.mark.parametrize("direction,mem", [("aa", 5), ("aa", 10), ("rb", 10), ("none", 5)])
+@pytest.mark.parametrize("direction,mem", [("aa", 5), ("aa", 10), ("rb", 10), ("none", 5), ("aa_qr", 5),
+                                           ("aa_qr", 10)])
 def test_small_socp_directions(sscs, direction, mem, seed):
     """Default settings (lambda 1.5, c1 0.9999, q 0.999).  Seed 0 is the SOCP on
     which c1 = q = 0.99, lambda = 1 stall: Anderson in K2 steps with ||Ru||

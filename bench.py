@@ -496,15 +496,25 @@ DM_METHODS = [("SCS (DRS on N_C + Q)", dict(direction="scs")),
               ("AA-QR (mem:5)", dict(direction="aa_qr", mem=5))]
 
 
-def dm_leg(sscs, G, seeds=1, eps=1e-4, max_time=5.0, log=None):
-    """The LASSO family of Sec. V-C (48 (n, kappa, mu) combinations x `seeds`)
-    solved by each method to eps on the GPU, one problem at a time (data on
-    the device, setup not timed), with a time limit per solve standing for
-    the paper's failure rule.  Returns per-method success, sgm and the
-    Dolan-More profile.  RB memories above 16 are outside the engine's
-    limit, so 10 and 16 stand in for the paper's 50 and 100."""
+DM_FAMILIES = {
+    "lasso": ("LASSO family of Sec. V-C: n in (631, 1000, 1585, 2512), m = ceil(n/5), kappa_A in (10, 215, 4600, 1e5), "
+              "mu in (0.01, 0.1, 1)", "lasso_dm_family"),
+    "sdp": ("l1-regularised sparse PCA of Sec. V-B: d in (50, 120, 140, 180), lambda in (0.1, 2, 5)", "sdp_pca_dm_family"),
+    "logreg": ("l1-regularised logistic regression of Sec. V-D: p in (80, 100), q in (50, 100, 120), "
+               "lambda in (10, 20, 50)", "logreg_dm_family"),
+}
+
+
+def dm_leg(sscs, G, seeds=1, eps=1e-4, max_time=5.0, log=None, family="lasso"):
+    """A benchmark family of Sec. V (`seeds` problems per parameter
+    combination) solved by each method to eps on the GPU, one problem at a
+    time (data on the device, setup not timed), with a time limit per solve
+    standing for the paper's failure rule.  Returns per-method success, sgm
+    and the Dolan-More profile.  RB memories above 16 are outside the
+    engine's limit, so 10 and 16 stand in for the paper's 50 and 100."""
     import torch
-    probs = G.lasso_dm_family(seeds)
+    desc, fn = DM_FAMILIES[family]
+    probs = getattr(G, fn)(seeds)
     T = np.full((len(probs), len(DM_METHODS)), np.inf)
     iters = np.zeros_like(T)
     for ip, p in enumerate(probs):
@@ -528,10 +538,8 @@ def dm_leg(sscs, G, seeds=1, eps=1e-4, max_time=5.0, log=None):
     R = performance_ratios(T)
     taus = [1.0, 1.25, 1.5, 2.0, 4.0, 10.0, 100.0]
     rho = performance_profile(R, taus)
-    out = {"workload": f"LASSO family of Sec. V-C: n in (631, 1000, 1585, 2512), m = ceil(n/5), kappa_A in "
-                       f"(10, 215, 4600, 1e5), mu in (0.01, 0.1, 1); {len(probs)} problems, eps {eps:g}, "
-                       f"time limit {max_time:g} s per solve",
-           "time_unit": "ms", "sgm_shift_ms": 10.0, "methods": {}}
+    out = {"workload": f"{desc}; {len(probs)} problems, eps {eps:g}, time limit {max_time:g} s per solve",
+           "family": family, "time_unit": "ms", "sgm_shift_ms": 10.0, "methods": {}}
     for js, (name, _) in enumerate(DM_METHODS):
         out["methods"][name] = {
             "success": float(np.isfinite(T[:, js]).mean()),
@@ -595,8 +603,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--dm", type=int, default=0, metavar="SEEDS",
-                    help="only run the Dolan-More / sgm comparison on the LASSO family (SEEDS problems per "
-                         "(n, kappa, mu) combination)")
+                    help="only run the Dolan-More / sgm comparison on a benchmark family (SEEDS problems per "
+                         "parameter combination)")
+    ap.add_argument("--dm-family", default="lasso", choices=sorted(DM_FAMILIES),
+                    help="the family of the Dolan-More comparison")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -604,7 +614,8 @@ def main():
     if args.dm > 0:
         from paper_1903_06477_amd import generators as G
         from paper_1903_06477_amd import sscs
-        res = dm_leg(sscs, G, seeds=args.dm, log=lambda s: print(s, file=sys.stderr, flush=True))
+        res = dm_leg(sscs, G, seeds=args.dm, log=lambda s: print(s, file=sys.stderr, flush=True),
+                     family=args.dm_family)
         print(json.dumps(res))
         return
     if args.gpus != 1:

@@ -455,3 +455,104 @@ def config3_sdp_exp(instance: int = 0, nblk: int = 64, k: int = 64, kbig: int = 
 def small_sdp_exp(seed: int = 0) -> Problem:
     """The mixed SDP / exp instance at a size the oracle solves in seconds."""
     return config3_sdp_exp(instance=1000 + seed, nblk=2, k=4, kbig=7, q=30, p=6, density=0.3)
+
+
+# ---------------------------------------------------------------------------
+# Benchmark families of Sec. V-B (l1-regularised sparse PCA SDP) and Sec. V-D
+# (l1-regularised logistic regression), one problem per call
+
+def sdp_pca_instance(d: int, lam: float, seed: int = 0) -> Problem:
+    """max tr(S Z) - lam ||Z||_1 s.t. tr Z = 1, Z PSD (problem (rpca), Sec.
+    V-B) with S = (G + G^T) / 2, G of N(0,1) entries, as a cone program in
+    (svec Z, svec T): min -<svec S, svec Z> + lam <w, svec T> with rows
+    tr Z = 1 (zero), T - Z >= 0 and T + Z >= 0 (R+), svec Z in the PSD cone
+    (w = 1 on the diagonal, sqrt 2 off it, so <w, svec T> = sum |Z_ij| at the
+    optimum).  The paper does not publish its generator; this one takes the
+    stated sizes d and weights lam."""
+    rng = rng_for(8, seed)
+    Gm = rng.standard_normal((d, d))
+    S = 0.5 * (Gm + Gm.T)
+    ii, jj, sc = _svec_pairs(d)
+    D = d * (d + 1) // 2
+    c = np.concatenate([-(S[ii, jj] * sc), lam * np.where(ii == jj, 1.0, math.sqrt(2.0))])
+    diag = np.nonzero(ii == jj)[0]
+    e = np.arange(D)
+    rows = [np.zeros(d, np.int64), 1 + e, 1 + e, 1 + D + e, 1 + D + e, 1 + 2 * D + e]
+    cols = [diag, D + e, e, D + e, e, e]
+    vals = [np.ones(d), -np.ones(D), np.ones(D), -np.ones(D), -np.ones(D), -np.ones(D)]
+    m = 1 + 3 * D
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m, 2 * D))
+    b = np.concatenate([[1.0], np.zeros(3 * D)])
+    return Problem(A=_csr(A), b=b, c=c, cone=Cone(z=1, l=2 * D, s=[d]), name=f"sdp_pca_d{d}_lam{lam:g}_{seed}",
+                   meta=dict(S=S, lam=lam))
+
+
+def sdp_pca_dm_family(seeds: int = 1) -> List[Problem]:
+    """The sparse-PCA family of Sec. V-B: d in {50, 120, 140, 180}, lam in
+    {0.1, 2, 5}, `seeds` problems per combination."""
+    return [sdp_pca_instance(d, lam, 100 * i + s)
+            for i, (d, lam) in enumerate((d, lam) for d in (50, 120, 140, 180) for lam in (0.1, 2.0, 5.0))
+            for s in range(seeds)]
+
+
+def logreg_instance(p: int, q: int, lam: float, seed: int = 0, density: float = 1.0) -> Problem:
+    """min lam ||w||_1 + sum_i log(1 + exp(-y_i (a_i^T w + beta))) (problem
+    (logreg) of Sec. V-D, read with labels y_i in {-1, 1} and intercept beta)
+    over q samples a_i in R^p with N(0,1) entries (at `density`), labels
+    +-1.  Each loss term through two exponential cones: t_i >=
+    log(1 + exp(z_i)) iff u1 + u2 <= 1, (u1, 1, -t_i) and (u2, 1, z_i - t_i) in
+    K_exp, with z_i = -y_i (a_i^T w + beta); |w| <= r by 2p R+ rows.
+    Variables [w | beta | r | t | u1 | u2]."""
+    rng = rng_for(9, seed)
+    F = sprandn(q, p, density, rng) if density < 1.0 else sp.csr_matrix(rng.standard_normal((q, p)))
+    y = np.where(rng.random(q) < 0.5, -1.0, 1.0)
+    ow, obeta = 0, p
+    orr = obeta + 1
+    ot = orr + p
+    ou1 = ot + q
+    ou2 = ou1 + q
+    n = ou2 + q
+    c = np.zeros(n)
+    c[orr:orr + p] = lam
+    c[ot:ot + q] = 1.0
+    rows, cols, vals, bvec = [], [], [], []
+
+    def add(rr, cc, vv):
+        rows.append(np.asarray(rr, np.int64))
+        cols.append(np.asarray(cc, np.int64))
+        vals.append(np.asarray(vv, np.float64))
+
+    r0 = 0
+    eq = np.arange(q)
+    add(r0 + eq, ou1 + eq, np.ones(q)); add(r0 + eq, ou2 + eq, np.ones(q)); r0 += q    # 1 - u1 - u2 >= 0
+    bvec.append(np.ones(q))
+    ep_ = np.arange(p)
+    add(r0 + ep_, orr + ep_, -np.ones(p)); add(r0 + ep_, ow + ep_, np.ones(p)); r0 += p      # r - w >= 0
+    add(r0 + ep_, orr + ep_, -np.ones(p)); add(r0 + ep_, ow + ep_, -np.ones(p)); r0 += p     # r + w >= 0
+    bvec.append(np.zeros(2 * p))
+    nl = q + 2 * p
+    eb = np.zeros(6 * q)
+    base = r0 + 6 * eq
+    add(base, ou1 + eq, -np.ones(q))
+    eb[6 * eq + 1] = 1.0
+    add(base + 2, ot + eq, np.ones(q))
+    add(base + 3, ou2 + eq, -np.ones(q))
+    eb[6 * eq + 4] = 1.0
+    Fc = F.tocoo()
+    add(base[Fc.row] + 5, ow + Fc.col, y[Fc.row] * Fc.data)
+    add(base + 5, np.full(q, obeta), y)
+    add(base + 5, ot + eq, np.ones(q))
+    bvec.append(eb)
+    m = r0 + 6 * q
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m, n))
+    return Problem(A=_csr(A), b=np.concatenate(bvec), c=c, cone=Cone(l=nl, ep=2 * q),
+                   name=f"logreg_p{p}_q{q}_lam{lam:g}_{seed}", meta=dict(F=F, labels=y, lam=lam, p=p, q=q))
+
+
+def logreg_dm_family(seeds: int = 1) -> List[Problem]:
+    """The logistic-regression family of Sec. V-D: p in {80, 100}, q in {50,
+    100, 120}, lam in {10, 20, 50}, `seeds` problems per combination."""
+    return [logreg_instance(p, q, lam, 100 * i + s)
+            for i, (p, q, lam) in enumerate((p, q, lam) for p in (80, 100) for q in (50, 100, 120)
+                                            for lam in (10.0, 20.0, 50.0))
+            for s in range(seeds)]

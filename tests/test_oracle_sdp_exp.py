@@ -120,3 +120,64 @@ def test_objective_is_sum_of_subproblem_optima(solved):
     # pobj = <c, x> = -(sum of SPCA values) + logistic optimum (to the tolerance)
     assert abs(r.info["pobj"] - (f_star - spca)) <= 1e-4 * (1 + abs(r.info["pobj"]))
     assert math.isfinite(r.info["dobj"])
+
+
+# ------------------------------------------------------------ benchmark families of Sec. V-B / V-D
+
+def _svec_to_mat(v, d):
+    import math
+    M = np.zeros((d, d))
+    jj, ii = np.triu_indices(d)
+    sc = np.where(ii == jj, 1.0, 1.0 / math.sqrt(2.0))
+    M[ii, jj] = v * sc
+    M[jj, ii] = v * sc
+    return M
+
+
+def test_sdp_pca_family_instance_closed_form():
+    """lam = 0: max tr(S Z) over tr Z = 1, Z PSD is the largest eigenvalue of
+    S (closed form); lam > 0: the optimum lies between the value of the top
+    eigenvector's rank-one Z and lam_max(S), and the returned Z is feasible."""
+    from oracle import superscs as S
+    p = G.sdp_pca_instance(6, 0.0, 1)
+    r = S.solve(p, S.Settings(eps=1e-9, max_iters=50000))
+    lmax = np.linalg.eigvalsh(p.meta["S"]).max()
+    assert r.status == S.SOLVED and abs(-r.info["pobj"] - lmax) <= 1e-7 * (1 + lmax)
+    d, lam = 8, 0.5
+    p = G.sdp_pca_instance(d, lam, 2)
+    r = S.solve(p, S.Settings(eps=1e-9, max_iters=50000))
+    Smat = p.meta["S"]
+    w, V = np.linalg.eigh(Smat)
+    v = V[:, -1]
+    lower = v @ Smat @ v - lam * np.abs(np.outer(v, v)).sum()
+    val = -r.info["pobj"]
+    assert r.status == S.SOLVED and lower - 1e-7 <= val <= w[-1] + 1e-7
+    D = d * (d + 1) // 2
+    Z = _svec_to_mat(r.x[:D], d)
+    assert abs(np.trace(Z) - 1) <= 1e-7 and np.linalg.eigvalsh(Z).min() >= -1e-7
+    assert abs((np.trace(Smat @ Z) - lam * np.abs(Z).sum()) - val) <= 1e-6
+
+
+def test_logreg_family_instance_matches_smooth_minimiser():
+    """The cone program's optimum equals the minimum of the l1-regularised
+    logistic loss found by L-BFGS-B on the split form w = w+ - w-."""
+    import scipy.optimize as so
+    from oracle import superscs as S
+    p = G.logreg_instance(10, 20, 1.0, 3)
+    r = S.solve(p, S.Settings(eps=1e-9, max_iters=50000))
+    F, y, lam = p.meta["F"].toarray(), p.meta["labels"], p.meta["lam"]
+    k = F.shape[1]
+
+    def f(z):
+        wp, wm, beta = z[:k], z[k:2 * k], z[-1]
+        mrg = -y * (F @ (wp - wm) + beta)
+        val = lam * (wp.sum() + wm.sum()) + np.logaddexp(0.0, mrg).sum()
+        sgm = 1.0 / (1.0 + np.exp(-mrg))
+        g_w = F.T @ (-y * sgm)
+        return val, np.concatenate([lam + g_w, lam - g_w, [np.sum(-y * sgm)]])
+
+    bounds = [(0, None)] * (2 * k) + [(None, None)]
+    res = so.minimize(f, np.zeros(2 * k + 1), jac=True, method="L-BFGS-B", bounds=bounds,
+                      options=dict(ftol=1e-15, gtol=1e-12, maxiter=10000))
+    assert r.status == S.SOLVED
+    assert abs(r.info["pobj"] - res.fun) <= 1e-6 * (1 + abs(res.fun))

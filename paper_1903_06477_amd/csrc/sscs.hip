@@ -216,22 +216,23 @@ __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __re
 // Stand-alone SpMV, column-panel form, for operators that stream from HBM:
 // the input vector is cut into panels of at most kPanelCols entries, and a
 // workgroup of 1024 threads (one per CU: the panel fills the LDS) stages its
-// panel of x in LDS once and then runs the row-segmented product over a chunk
-// of rows, gathering from LDS instead of the cache hierarchy (measured: with
-// x in L2 each 8-byte gather costs a cache-line transfer and caps the product
-// far below the streaming rate of the operator).  Work item i is (panel p,
-// share c, shares C) in items[3 i .. 3 i + 2]: the C workgroups of panel p
-// interleave its rows segment by segment (at any moment the grid streams
-// through one region of the operator).  With one panel the sums go to
-// y; with several, row r's entries of panel p are the contiguous range
-// [cut[r (P+1) + p], cut[r (P+1) + p + 1]) of the CSR arrays (columns are
-// sorted) and its partial sum goes to part[p rows + r], summed over the
-// panels in order by k_panel_sum.
+// panel of x in LDS once and then runs the row-segmented product over its
+// share of the rows, gathering from LDS instead of the cache hierarchy
+// (measured: with x in L2 each 8-byte gather costs a cache-line transfer and
+// caps the product far below the streaming rate of the operator).  Work item
+// i is (panel p, share c, shares C) in items[3 i .. 3 i + 2]: the C workgroups
+// of panel p interleave its rows segment by segment (at any moment the grid
+// streams through one region of the operator).  The operator is given panel
+// by panel: rows r of panel p are [rp[p rows + r], rp[p rows + r + 1]) of
+// (ci, v), column indices relative to the panel (one panel: the CSR itself).
+// With one panel the sums go to y; with several, row r's partial sum of panel
+// p goes to part[p rows + r], summed over the panels in order by k_panel_sum.
 constexpr int kPanelCols = 20480;      // 160 KB of FP64 entries per panel
 constexpr int kPanelThreads = 1024;
 template <int S>
-__global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(Csr<double> M, const int* __restrict__ items, int nitems,
-                                                              int P, int pc, const int* __restrict__ cut,
+__global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                              const double* __restrict__ v, int rows, int cols,
+                                                              const int* __restrict__ items, int nitems, int P, int pc,
                                                               const double* __restrict__ x, double* __restrict__ y,
                                                               double* __restrict__ part) {
     double* xs = sscs_dyn_lds;
@@ -239,30 +240,23 @@ __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(Csr<double> M, con
     const int seg = threadIdx.x / S, nseg = blockDim.x / S, ls = threadIdx.x & (S - 1);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int p = items[3 * it], c = items[3 * it + 1], C = items[3 * it + 2];
-        const int c0 = p * pc;
         if (p != cur) {
             __syncthreads();
-            const int len = min(pc, M.cols - c0);
+            const int c0 = p * pc, len = min(pc, cols - c0);
             for (int i = threadIdx.x; i < len; i += blockDim.x) xs[i] = x[c0 + i];
             __syncthreads();
             cur = p;
         }
-        for (int r = c * nseg + seg; r < M.rows; r += C * nseg) {
-            int kb, ke;
-            if (P == 1) {
-                kb = M.rp[r];
-                ke = M.rp[r + 1];
-            } else {
-                kb = cut[(size_t)r * (P + 1) + p];
-                ke = cut[(size_t)r * (P + 1) + p + 1];
-            }
+        const int* prp = rp + (size_t)p * rows;
+        for (int r = c * nseg + seg; r < rows; r += C * nseg) {
+            const int kb = prp[r], ke = prp[r + 1];
             double acc = 0.0;
-            for (int k = kb + ls; k < ke; k += S) acc += M.v[k] * xs[M.ci[k] - c0];
+            for (int k = kb + ls; k < ke; k += S) acc += v[k] * xs[ci[k]];
 #pragma unroll
             for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
             if (ls == 0) {
                 if (P == 1) y[r] = acc;
-                else part[(size_t)p * M.rows + r] = acc;
+                else part[(size_t)p * rows + r] = acc;
             }
         }
     }
@@ -276,22 +270,44 @@ __global__ void k_panel_sum(const double* __restrict__ part, int P, int rows, do
     }
 }
 
-// Split points of every row at the panel boundaries (first entry with column
-// >= p pc, by binary search over the row's sorted columns).
-__global__ void k_panel_cuts(const int* __restrict__ rp, const int* __restrict__ ci, int rows, int P, int pc,
-                             int* __restrict__ cut) {
-    const long long total = (long long)rows * (P + 1);
+// First entry of row r with column >= key (columns sorted).
+__device__ inline int row_lower(const int* __restrict__ rp, const int* __restrict__ ci, int r, int key) {
+    int lo = rp[r], hi = rp[r + 1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ci[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Panel-major copy of a CSR matrix with sorted columns: (1) the entry count of
+// every (panel p, row r) into len[p rows + r]; (2) an exclusive scan of len
+// (k_scan) gives the panel-major row pointers; (3) every (p, r) segment is
+// copied with panel-relative columns.
+__global__ void k_panel_lens(const int* __restrict__ rp, const int* __restrict__ ci, int rows, int P, int pc,
+                             int* __restrict__ len) {
+    const long long total = (long long)rows * P;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
          t += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(t / (P + 1)), p = (int)(t % (P + 1));
-        int lo = rp[r], hi = rp[r + 1];
-        if (p == P) { cut[t] = hi; continue; }
+        const int p = (int)(t / rows), r = (int)(t % rows);
+        len[t] = row_lower(rp, ci, r, (p + 1) * pc) - row_lower(rp, ci, r, p * pc);
+    }
+}
+
+__global__ void k_panel_scatter(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                                int rows, int P, int pc, const int* __restrict__ off, int* __restrict__ pci,
+                                double* __restrict__ pv) {
+    const long long total = (long long)rows * P;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int p = (int)(t / rows), r = (int)(t % rows);
         const int key = p * pc;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ci[mid] < key) lo = mid + 1; else hi = mid;
+        const int lo = row_lower(rp, ci, r, key);
+        const int o = off[t], cnt = off[t + 1] - o;
+        for (int e = 0; e < cnt; ++e) {
+            pci[o + e] = ci[lo + e] - key;
+            pv[o + e] = v[lo + e];
         }
-        cut[t] = lo;
     }
 }
 
@@ -730,8 +746,10 @@ struct PanelPlan {
     bool built = false, use = false;
     int P = 1, pc = 0, S = 8, nitems = 0;
     int* items = nullptr;
-    int* cut = nullptr;
-    double* part = nullptr;
+    int* prp = nullptr;          // panel-major row pointers (P rows + 1), several panels
+    int* pci = nullptr;          // panel-major column indices (panel-relative)
+    double* pv = nullptr;        // panel-major values
+    double* part = nullptr;      // P x rows partial sums
 };
 
 struct sscs_work {
@@ -832,7 +850,7 @@ int panel_plan(sscs_work* w, int which) {
     if (!pl.use) return SSCS_OK;
     const double mean = (double)nnz / std::max(1.0, (double)rows * pl.P);
     pl.S = 1;
-    while (pl.S < 64 && pl.S < mean / 2.5) pl.S <<= 1;
+    while (pl.S < 64 && pl.S < mean / 3.0) pl.S <<= 1;
     std::vector<int> items;
     for (int p = 0; p < pl.P; ++p)
         for (int c = 0; c < chunks; ++c) items.insert(items.end(), {p, c, chunks});
@@ -840,14 +858,24 @@ int panel_plan(sscs_work* w, int which) {
     TRY(dmalloc(&pl.items, items.size()));
     HIP_TRY(hipMemcpy(pl.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
     if (pl.P > 1) {
-        TRY(dmalloc(&pl.cut, (size_t)rows * (pl.P + 1)));
-        TRY(dmalloc(&pl.part, (size_t)rows * pl.P));
         const int* drp = which ? I.At_rp : I.A_rp;
         const int* dci = which ? I.At_ci : I.A_ci;
-        const long long total = (long long)rows * (pl.P + 1);
-        k_panel_cuts<<<(int)std::min<long long>(65535, (total + 255) / 256), 256, 0, w->stream>>>(drp, dci, rows, pl.P,
-                                                                                              pl.pc, pl.cut);
+        const double* dv = which ? I.At_v : I.A_v;
+        const long long total = (long long)rows * pl.P;
+        if (total >= (1ll << 31) - 1) { pl.use = false; return SSCS_OK; }
+        int* len = nullptr;
+        TRY(dmalloc(&len, total));
+        TRY(dmalloc(&pl.prp, total + 1));
+        TRY(dmalloc(&pl.pci, (size_t)nnz));
+        TRY(dmalloc(&pl.pv, (size_t)nnz));
+        TRY(dmalloc(&pl.part, (size_t)rows * pl.P));
+        const int g = (int)std::min<long long>(65535, (total + 255) / 256);
+        k_panel_lens<<<g, 256, 0, w->stream>>>(drp, dci, rows, pl.P, pl.pc, len);
+        k_scan<<<1, 1024, 0, w->stream>>>(len, (int)total, pl.prp);
+        k_panel_scatter<<<g, 256, 0, w->stream>>>(drp, dci, dv, rows, pl.P, pl.pc, pl.prp, pl.pci, pl.pv);
         HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        hipFree(len);
     }
     static const bool attr = [] {
         bool ok = true;
@@ -871,12 +899,14 @@ int launch_spmv(sscs_work* w, int transpose, const double* dx, double* dy) {
     const Csr<double>& M = transpose ? P.At : P.A;
     if (pl.use) {
         const int grid = std::max(1, std::min(pl.nitems, w->ncu));
-        Csr<double> Mv = M;
+        const int* rp = pl.P > 1 ? pl.prp : M.rp;
+        const int* ci = pl.P > 1 ? pl.pci : M.ci;
+        const double* v = pl.P > 1 ? pl.pv : M.v;
+        int rows = M.rows, cols = M.cols;
         const int* items = pl.items;
         int nitems = pl.nitems, np = pl.P, pc = pl.pc;
-        const int* cut = pl.cut;
         double* part = pl.part;
-        void* args[] = {&Mv, &items, &nitems, &np, &pc, &cut, &dx, &dy, &part};
+        void* args[] = {&rp, &ci, &v, &rows, &cols, &items, &nitems, &np, &pc, &dx, &dy, &part};
         HIP_TRY(hipLaunchKernel(panel_kernel(pl.S), dim3(grid), dim3(kPanelThreads), args,
                                 (size_t)pl.pc * sizeof(double), w->stream));
         if (pl.P > 1)
@@ -1162,7 +1192,9 @@ int sscs_destroy(sscs_work* w) {
     hipFree(w->vecbuf); hipFree(w->io); hipFree(w->scal); hipFree(w->res);
     hipFree(w->bar); hipFree(w->abort_flag); hipFree(w->part);
     hipFree(w->tr_res); hipFree(w->tr_kind); hipFree(w->tr_ls); hipFree(w->tr_eta); hipFree(w->tr_rsafe);
-    for (auto& pl : w->panel) { hipFree(pl.items); hipFree(pl.cut); hipFree(pl.part); }
+    for (auto& pl : w->panel) {
+        hipFree(pl.items); hipFree(pl.prp); hipFree(pl.pci); hipFree(pl.pv); hipFree(pl.part);
+    }
     delete w;
     return SSCS_OK;
 }

@@ -274,6 +274,17 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
     constexpr bool kQ = std::is_same<TV, double>::value;
     if constexpr (!kQ) q = nullptr;
     const bool use_q = q != nullptr && !refresh;
+    // FP64 solves end one pass early: the reduction that gives alpha and beta
+    // also gives <r,w>, <r,s>, <w,w>, <w,s> and <s,s>, from which the
+    // recurrence residual after the step, ||r - alpha (w + beta s)||^2,
+    // follows without the step's products.  When it meets the threshold the
+    // step is left pending and the closing pass applies it (x + alpha (u +
+    // beta p), formed where it is gathered): the last pass's two products and
+    // two barriers are saved.  The iterates are the same as without it.
+    constexpr bool kPred = kQ;
+    constexpr int KD = kPred ? 8 : 3;             // dot products per CG reduction
+    bool pend = false;
+    double fa = 0.0, fb = 0.0;
     int cur = 0;
     auto start = [&](int j, double rj) {          // r0 = rj; u = w = p = s = 0; record (D r0, 0, 0)
         V.cg_r[j] = rj;
@@ -317,13 +328,15 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
                 const double sj = V.cg_w[j] + beta * V.cg_s[j];
                 const double rj = V.cg_r[j] - alpha * sj;
                 const double dj = P.dinv[j];
-                xw[j] += alpha * pj;
+                const double xj = xw[j] + alpha * pj;
+                xw[j] = xj;
                 V.cg_p[j] = pj;
                 V.cg_s[j] = sj;
                 V.cg_r[j] = rj;
                 V.cg_u[j] = dj * rj;
                 gn[4 * (size_t)j] = dj * rj;
                 gn[4 * (size_t)j + 1] = dj * sj;
+                if constexpr (kPred) gn[4 * (size_t)j + 3] = xj;   // read by a closing pass with a pending step
             }
             spmv_part<4>(tm, KA, 0,
                          [&](int c) {
@@ -336,6 +349,7 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
             cur ^= 1;
             // ---- phase Y
             double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
+            double a_rw = 0.0, a_rs = 0.0, a_ww = 0.0, a_ws = 0.0, a_ss = 0.0;
             spmv_part<4>(tm, KAt, 1, [&](int c) { return V.cg_t[c]; }, [&](int j, double s) {
                 const double uj = V.cg_u[j];
                 const double rj = V.cg_r[j];
@@ -345,15 +359,30 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
                 a_g += rj * uj;
                 a_d += wj * uj;
                 a_rr += rj * rj;
+                if constexpr (kPred) {
+                    const double sj = V.cg_s[j];
+                    a_rw += rj * wj;
+                    a_rs += rj * sj;
+                    a_ww += wj * wj;
+                    a_ws += wj * sj;
+                    a_ss += sj * sj;
+                }
             });
             put(sh, 0, a_g);
             put(sh, 1, a_d);
             put(sh, 2, a_rr);
-            if (round == 0 && pass == 0) put(sh, 3, a_bb);
-            tm.reduce(sh, (round == 0 && pass == 0) ? 4 : 3);
+            if constexpr (kPred) {
+                put(sh, 3, a_rw);
+                put(sh, 4, a_rs);
+                put(sh, 5, a_ww);
+                put(sh, 6, a_ws);
+                put(sh, 7, a_ss);
+            }
+            if (round == 0 && pass == 0) put(sh, KD, a_bb);
+            tm.reduce(sh, (round == 0 && pass == 0) ? KD + 1 : KD);
             const double gamma = sh.out[0], delta = sh.out[1], rr = sh.out[2];
             if (round == 0 && pass == 0) {
-                thr = thr_abs > 0.0 ? thr_abs : tol * tol * sh.out[3];
+                thr = thr_abs > 0.0 ? thr_abs : tol * tol * sh.out[KD];
                 if (thr_used) *thr_used = thr;
             }
             if (!(rr > thr) && (it > 0 || round > 0)) {   // at least one step, as in solve_M_staged
@@ -376,20 +405,50 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
             gamma_old = gamma;
             alpha_old = alpha;
             ++it;
+            if constexpr (kPred) {
+                // ||r - alpha s'||^2 with s' = w + beta s
+                const double rs1 = sh.out[3] + beta * sh.out[4];
+                const double ss1 = sh.out[5] + beta * (2.0 * sh.out[6] + beta * sh.out[7]);
+                const double rr1 = rr - 2.0 * alpha * rs1 + alpha * alpha * ss1;
+                if (!(rr1 > thr)) {
+                    pend = true;
+                    fa = alpha;
+                    fb = beta;
+                    done = true;
+                    break;
+                }
+            }
         }
         if (done) break;
     }
-    // py = ry + A px ; h^T p
+    // py = ry + A px ; h^T p.  With a pending step, x + alpha p' (p' = u +
+    // beta p) is formed where it is read: gathers take x and u from the
+    // column records (the owners overwrite x in this pass), p from its vector.
     double a_hp = 0.0;
-    spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) {
+    const double* gf = V.cg_g[cur];
+    spmv_part<1>(tm, P.A, 0, [&](int c_) {
+        if (pend) {
+            const double* g = gf + 4 * (size_t)c_;
+            return g[3] + fa * (g[0] + fb * V.cg_p[c_]);
+        }
+        return xw[c_];
+    }, [&](int i, double s) {
         const double py = r[n + i] + s;
         out[n + i] = py;
         a_hp += P.b[i] * py;
     });
     for (int j = tm.rank(); j < n; j += tm.size()) {
-        out[j] = xw[j];
-        a_hp += P.c[j] * xw[j];
-        if (q) q[j] = V.cg_b[j] - V.cg_r[j];
+        double xj = xw[j], rj = V.cg_r[j];
+        if (pend) {
+            const double pj = V.cg_u[j] + fb * V.cg_p[j];
+            const double sj = V.cg_w[j] + fb * V.cg_s[j];
+            rj = rj - fa * sj;
+            xj = xj + fa * pj;
+            xw[j] = xj;
+        }
+        out[j] = xj;
+        a_hp += P.c[j] * xj;
+        if (q) q[j] = V.cg_b[j] - rj;
     }
     put(sh, 0, a_hp);
     tm.reduce(sh, 1);

@@ -58,6 +58,7 @@ __device__ inline void grid_team_init(GridTeam<LDS, TL, PT>& tm, const Prob& P) 
     load_part(tm.mp[0], op_mat<TL>(P, 0), P.partA, blockIdx.x, LDS, &off);
     load_part(tm.mp[1], op_mat<TL>(P, 1), P.partAt, blockIdx.x, LDS, &off);
     __syncthreads();
+    tm.set_up();
 }
 
 // stage_doubles: dynamic LDS of the launch (in doubles) for the CG's gathered
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(kBlock) k_solve_grid(Prob P, Vecs V, Params S,
         d.S = S;
     }
     __syncthreads();
-    GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0, 0u, 1u, 1ull};
     grid_team_init(tm, d.P);
     sscs::run_solve<TV>(tm, sh, d.P, d.V, d.S, res);
 }
@@ -101,7 +102,7 @@ template <bool LDS, typename TV, bool PT>
 __global__ void __launch_bounds__(kBlock) k_op_grid(Prob P, Vecs V, OpArgs a, unsigned long long* bar,
                                                     int* abort_flag, double* part, long long timeout_ticks) {
     __shared__ Shared sh;
-    GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0};
+    GridTeam<LDS, TV, PT> tm{{}, bar, abort_flag, part, 0ull, timeout_ticks, 0, 0u, 1u, 1ull};
     grid_team_init(tm, P);
     const int n = P.n, m = P.m, N = P.N;
     if (a.op == OP_LINEAR) {

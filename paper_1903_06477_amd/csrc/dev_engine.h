@@ -281,7 +281,7 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
     // step is left pending and the closing pass applies it (x + alpha (u +
     // beta p), formed where it is gathered): the last pass's two products and
     // two barriers are saved.  The iterates are the same as without it.
-    constexpr bool kPred = kQ;
+    constexpr bool kPred = kQ && !Team::kBlock;   // grid teams (the one-workgroup kernel has no registers to spare)
     constexpr int KD = kPred ? 8 : 3;             // dot products per CG reduction
     bool pend = false;
     double fa = 0.0, fb = 0.0;
@@ -542,23 +542,28 @@ struct Term {
 template <typename Team>
 __device__ __forceinline__ double term_partials(Team& tm, Shared& sh, const Prob& P, const Vecs& V, bool timed_out,
                                                 bool scs = false) {
-    const int n = P.n, m = P.m;
+    const int n = P.n;
     const double tau = V.ub[P.N - 1];
     double a_p = 0.0, a_u = 0.0, a_d = 0.0, a_i = 0.0, a_cx = 0.0, a_by = 0.0;
+    // <b, y> and <c, x> ride along with the products: every row of A and of
+    // A^T is reported exactly once
     spmv_part<1>(tm, P.A, 0, [&](int c_) { return V.ub[c_]; }, [&](int i, double s) {
-        const double sig = scs ? V.ub[n + i] - V.u[n + i] : V.ub[n + i] - 2.0 * V.ut[n + i] + V.u[n + i];
+        const double yb = V.ub[n + i];
+        const double sig = scs ? yb - V.u[n + i] : yb - 2.0 * V.ut[n + i] + V.u[n + i];
         const double v = s + sig;
         a_u += v * v;
-        const double w = v - P.b[i] * tau;
+        const double bi = P.b[i];
+        const double w = v - bi * tau;
         a_p += w * w;
+        a_by += bi * yb;
     });
     spmv_part<1>(tm, P.At, 1, [&](int c_) { return V.ub[n + c_]; }, [&](int j, double s) {
         a_i += s * s;
-        const double w = s + P.c[j] * tau;
+        const double cj = P.c[j];
+        const double w = s + cj * tau;
         a_d += w * w;
+        a_cx += cj * V.ub[j];
     });
-    for (int j = tm.rank(); j < n; j += tm.size()) a_cx += P.c[j] * V.ub[j];
-    for (int i = tm.rank(); i < m; i += tm.size()) a_by += P.b[i] * V.ub[n + i];
     put(sh, 0, a_p);
     put(sh, 1, a_u);
     put(sh, 2, a_d);
@@ -642,6 +647,11 @@ struct DirState {
     int aa_old;     // Anderson by QR: ring slot of the oldest pair (logical column 0)
 };
 
+// Memory columns whose loads one pass keeps in flight together (fewer in the
+// one-workgroup engine, whose register budget is smaller).
+template <typename Team>
+constexpr int aa_chunk() { return Team::kBlock ? 2 : 8; }
+
 // Anderson: push the pending pair into the ring, update the Gram matrix and
 // solve for t; then d = -Ru - (Z - Xi) t, fused with the K0 update of u.
 // Anderson (Sec. IV-D-2), in three parts so that the dot products can share
@@ -656,7 +666,7 @@ __device__ __forceinline__ int aa_push_dots(Team& tm, Shared& sh, const Vecs& V,
     int slot = -1;
     if (ds.pend) {
         slot = ds.aa_head;
-        const bool fix = ds.pend == 2;
+        const bool fix = ds.pend == 2;   // a K0 pair: xi from the next R u
         double* Zs = V.Zb + (size_t)slot * N;
         double* Ys = V.Yb + (size_t)slot * N;
         for (int e = tm.rank(); e < N; e += tm.size()) {
@@ -668,19 +678,34 @@ __device__ __forceinline__ int aa_push_dots(Team& tm, Shared& sh, const Vecs& V,
     }
     const int k = ds.aa_k;
     if (k == 0) return slot;
-    for (int i = 0; i < k; ++i) {
-        const double* Yi = V.Yb + (size_t)i * N;
-        double acc = 0.0;
-        for (int e = tm.rank(); e < N; e += tm.size()) acc += Yi[e] * V.Ru[e];
-        put(sh, base + i, acc);
-    }
-    if (slot >= 0) {
-        const double* Ys = V.Yb + (size_t)slot * N;
-        for (int i = 0; i < k; ++i) {
-            const double* Yi = V.Yb + (size_t)i * N;
-            double acc = 0.0;
-            for (int e = tm.rank(); e < N; e += tm.size()) acc += Yi[e] * Ys[e];
-            put(sh, base + k + i, acc);
+    // memory columns in chunks of AA_CHUNK, each chunk one pass whose loads
+    // are all in flight together (a loop over the columns with a run-time
+    // bound would wait for each column's loads in turn)
+    const bool nc = slot >= 0;
+    const bool fix = ds.pend == 2;
+    constexpr int AA_CHUNK = aa_chunk<Team>();
+    for (int i0 = 0; i0 < k; i0 += AA_CHUNK) {
+        double a_r[AA_CHUNK], a_n[AA_CHUNK];
+#pragma unroll
+        for (int q = 0; q < AA_CHUNK; ++q) { a_r[q] = 0.0; a_n[q] = 0.0; }
+        for (int e = tm.rank(); e < N; e += tm.size()) {
+            const double ru = V.Ru[e];
+            const double ys = nc ? V.pxi[e] + (fix ? ru : 0.0) : 0.0;   // the new column, as stored above
+#pragma unroll
+            for (int q = 0; q < AA_CHUNK; ++q) {
+                if (i0 + q < k) {
+                    const double yi = V.Yb[(size_t)(i0 + q) * N + e];
+                    a_r[q] += yi * ru;
+                    if (nc) a_n[q] += yi * ys;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < AA_CHUNK; ++q) {
+            if (i0 + q < k) {
+                put(sh, base + i0 + q, a_r[q]);
+                if (nc) put(sh, base + k + i0 + q, a_n[q]);
+            }
         }
     }
     return slot;
@@ -709,9 +734,15 @@ __device__ __forceinline__ void aa_gram(Shared& sh, const Params& S, int k, int 
 template <typename Team>
 __device__ __noinline__ void aa_apply(Team& tm, Shared& sh, const Prob& P, const Vecs& V, int k, bool k0) {
     const int N = P.N;
+    constexpr int AA_CHUNK = aa_chunk<Team>();
     for (int e = tm.rank(); e < N; e += tm.size()) {
         double d = -V.Ru[e];
-        for (int i = 0; i < k; ++i) d -= (V.Zb[(size_t)i * N + e] - V.Yb[(size_t)i * N + e]) * sh.coef[i];
+        for (int i0 = 0; i0 < k; i0 += AA_CHUNK) {      // loads of a chunk in flight together
+#pragma unroll
+            for (int q = 0; q < AA_CHUNK; ++q)
+                if (i0 + q < k)
+                    d -= (V.Zb[(size_t)(i0 + q) * N + e] - V.Yb[(size_t)(i0 + q) * N + e]) * sh.coef[i0 + q];
+        }
         V.d[e] = d;
         if (k0) { V.u[e] += d; V.pz[e] = d; V.pxi[e] = -V.Ru[e]; }
     }

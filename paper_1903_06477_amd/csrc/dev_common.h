@@ -39,16 +39,43 @@ struct Shared {
     int    qhead;               // batched engine: instance popped from the queue
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+// v of another lane by a data-parallel-primitive move (both halves with the
+// same control); lanes of rows outside ROWM receive 0.
+template <int CTRL, int ROWM>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWM, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of S lanes (S a power of two, uniform over the
+// wave), by moves within quads, half-rows and rows, then the broadcasts of a
+// row's last lane into the next row: the group's total is in its last lane
+// (S - 1), and in all of its lanes for S <= 16.  Moves that stay inside the
+// group keep groups independent, so a group whose lanes are all active may sum
+// while others of the wave are not.
+__device__ __forceinline__ double group_sum(double v, int S) {
+    if (S >= 2) v += dpp_f64<0xB1, 0xf>(v);      // quad_perm [1,0,3,2]
+    if (S >= 4) v += dpp_f64<0x4E, 0xf>(v);      // quad_perm [2,3,0,1]
+    if (S >= 8) v += dpp_f64<0x141, 0xf>(v);     // row_half_mirror
+    if (S >= 16) v += dpp_f64<0x140, 0xf>(v);    // row_mirror
+    if (S >= 32) v += dpp_f64<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    if (S >= 64) v += dpp_f64<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+// Sum over the wave, returned to every lane (all lanes must be active).
+__device__ __forceinline__ double wave_sum(double v) {
+    v = group_sum(v, WAVE);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
+    return __hiloint2double(hi, lo);
 }
 
 // Writes the wave-sum of v into slot k of the per-wave partials.
 __device__ __forceinline__ void put(Shared& sh, int k, double v) {
-    v = wave_sum(v);
-    if ((threadIdx.x & (WAVE - 1)) == 0) sh.red[k * NWMAX + (threadIdx.x / WAVE)] = v;
+    v = group_sum(v, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) sh.red[k * NWMAX + (threadIdx.x / WAVE)] = v;
 }
 
 // Sums the per-wave partials of slot k in wave order.
@@ -70,12 +97,27 @@ struct MatPart {
 
 extern __shared__ __attribute__((aligned(16))) double sscs_dyn_lds[];
 
-struct BlockTeam {
-    static constexpr bool kLds = false;
+// Vectors a kernel holds in LDS but reaches through generic pointers (shared
+// descriptors) are cast back to LDS pointers where the code knows they live
+// there: LDS instructions then replace flat ones, which take the longer
+// vector-memory path even for LDS addresses.
+typedef __attribute__((address_space(3))) double lds_f64;
+template <bool L> struct VecPtr { using type = double*; };
+template <> struct VecPtr<true> { using type = lds_f64*; };
+template <bool L>
+__device__ __forceinline__ typename VecPtr<L>::type vec_at(const double* p) {
+    if constexpr (L) return (lds_f64*)const_cast<double*>(p);
+    else return const_cast<double*>(p);
+}
+
+// One workgroup; LDS: the operator (A and A^T, FP64) is held in LDS.
+template <bool LDS>
+struct BlockTeamT {
+    static constexpr bool kLds = LDS;
     static constexpr bool kBlock = true;
     static constexpr bool kPsdTeam = false;
     using lds_t = double;
-    MatPart mp[2];    // A, A^T: all rows, global memory
+    MatPart mp[2];    // A, A^T: all rows (global memory, or LDS)
     double* lu = nullptr;   // LDS copies of the CG's gathered vectors (n and m
     double* lt = nullptr;   // entries), or null when they do not fit
     __device__ int rank() const { return threadIdx.x; }
@@ -92,6 +134,7 @@ struct BlockTeam {
         __syncthreads();
     }
 };
+using BlockTeam = BlockTeamT<false>;
 
 // Words of the grid barrier, each on its own 128-byte line: the global
 // arrival counter, one arrival counter and one release word per group, one
@@ -261,12 +304,12 @@ struct Csr {
 };
 
 // Row-segmented SpMV over the team: for every row r, f(r, sum_k v[k] gx(ci[k]))
-// is called by the first lane of the segment that owns r.  Segments of `seg`
+// is called by the last lane of the segment that owns r.  Segments of `seg`
 // consecutive lanes stride a row's nonzeros, so loads of ci and v coalesce;
 // each segment keeps ROWS rows in flight at once (independent load chains,
 // which is what hides the memory latency of a persistent kernel; the CG's
 // products use four, the other passes one), and each
-// row's sum is a butterfly over the segment's lanes.  gx(c) returns the
+// row's sum is a group sum over the segment's lanes (reported by its last lane).  gx(c) returns the
 // input vector's entry c, so callers can gather values formed on the fly.
 template <int ROWS, typename Team, typename T, typename Gx, typename F>
 __device__ __forceinline__ void spmv_gather(Team& tm, const Csr<T>& M, Gx&& gx, F&& f) {
@@ -300,15 +343,15 @@ __device__ __forceinline__ void spmv_gather(Team& tm, const Csr<T>& M, Gx&& gx, 
 #pragma unroll
         for (int q = 0; q < ROWS; ++q) {
             double a = acc[q];
-            for (int off = S >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, WAVE);
+            a = group_sum(a, S);
             const int r = r0 + q * nseg;
-            if (ls == 0 && r < M.rows) f(r, a);
+            if (ls == S - 1 && r < M.rows) f(r, a);
         }
     }
 }
 
 // Team SpMV over the rows a workgroup owns (MatPart): for every owned row r,
-// f(r, sum_k v[k] gx(ci[k])) is called by the first lane of the segment that
+// f(r, sum_k v[k] gx(ci[k])) is called by the last lane of the segment that
 // owns r.  Same segment scheme and ROWS-way batching as spmv_gather, with the
 // row range local to the workgroup and the operator read from LDS when cached.
 template <int ROWS, bool LDS, typename T, typename Gx, typename F>
@@ -359,9 +402,9 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
 #pragma unroll
         for (int q = 0; q < ROWS; ++q) {
             double a = acc[q];
-            for (int off = S >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, WAVE);
+            a = group_sum(a, S);
             const int l = l0 + q * nseg;
-            if (ls == 0 && own[q]) f(mp.r0 + l, a);
+            if (ls == S - 1 && own[q]) f(mp.r0 + l, a);
         }
     }
     if (M.nlong > 0) {

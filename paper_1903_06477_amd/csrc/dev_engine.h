@@ -131,19 +131,32 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
                               double* xw, double tol, int maxit, double thr_abs, double* thr_used, double* q,
                               bool refresh) {
     const int n = P.n, m = P.m;
-    double* __restrict__ ul = tm.lu;
-    double* __restrict__ tl = tm.lt;
+    // the small-instance kernel holds the staging, the CG's vectors, the warm
+    // start and K xw, and D, b, c in LDS (Team::kLds)
+    constexpr bool L = Team::kLds;
+    const auto ul = vec_at<L>(tm.lu);
+    const auto tl = vec_at<L>(tm.lt);
+    const auto cr = vec_at<L>(V.cg_r);
+    const auto cs = vec_at<L>(V.cg_s);
+    const auto cu = vec_at<L>(V.cg_u);
+    const auto cw = vec_at<L>(V.cg_w);
+    const auto cp = vec_at<L>(V.cg_p);
+    const auto cb = vec_at<L>(V.cg_b);
+    const auto xl = vec_at<L>(xw);
+    const auto dv = vec_at<L>(P.dinv);
+    const auto bv = vec_at<L>(P.b);
+    const auto cv = vec_at<L>(P.c);
     const Csr<TV>& KA = op_mat<TV>(P, 0);
     const Csr<TV>& KAt = op_mat<TV>(P, 1);
     constexpr bool kQ = std::is_same<TV, double>::value;
     if constexpr (!kQ) q = nullptr;
     const bool use_q = q != nullptr && !refresh;
     auto start = [&](int j, double rj) {          // r0 = rj; p = s = w = 0
-        V.cg_r[j] = rj;
-        V.cg_s[j] = 0.0;
-        V.cg_u[j] = 0.0;
-        V.cg_w[j] = 0.0;
-        V.cg_p[j] = 0.0;
+        cr[j] = rj;
+        cs[j] = 0.0;
+        cu[j] = 0.0;
+        cw[j] = 0.0;
+        cp[j] = 0.0;
     };
     for (int i = tm.rank(); i < m; i += tm.size()) tl[i] = r[n + i];
     tm.sync();
@@ -151,9 +164,9 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
     double a_bb = 0.0;
     spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; }, [&](int j, double s) {
         const double bj = r[j] - s;
-        V.cg_b[j] = bj;
+        cb[j] = bj;
         a_bb += bj * bj;
-        if (use_q) start(j, bj - q[j]);
+        if (use_q) start(j, bj - vec_at<L>(q)[j]);
     });
     double thr = 0.0;
     int it = 0;
@@ -161,12 +174,12 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
     for (int round = 0; round < rounds; ++round) {
         if (!(use_q && round == 0)) {
             // r0 = rhs - (xw + A^T A xw) in FP64
-            for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
+            for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xl[j];
             tm.sync();
             spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) { tl[i] = s; });
             tm.sync();
             spmv_part<1>(tm, P.At, 1, [&](int c_) { return tl[c_]; },
-                         [&](int j, double s) { start(j, V.cg_b[j] - (xw[j] + s)); });
+                         [&](int j, double s) { start(j, cb[j] - (xl[j] + s)); });
         }
         tm.sync();
         double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0;
@@ -174,15 +187,15 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
         for (int pass = 0;; ++pass) {
             double a_rr = 0.0;
             for (int j = tm.rank(); j < n; j += tm.size()) {
-                const double pj = V.cg_u[j] + beta * V.cg_p[j];
-                const double sj = V.cg_w[j] + beta * V.cg_s[j];
-                const double rj = V.cg_r[j] - alpha * sj;
-                const double uj = P.dinv[j] * rj;
-                xw[j] += alpha * pj;
-                V.cg_p[j] = pj;
-                V.cg_s[j] = sj;
-                V.cg_r[j] = rj;
-                V.cg_u[j] = uj;
+                const double pj = cu[j] + beta * cp[j];
+                const double sj = cw[j] + beta * cs[j];
+                const double rj = cr[j] - alpha * sj;
+                const double uj = dv[j] * rj;
+                xl[j] += alpha * pj;
+                cp[j] = pj;
+                cs[j] = sj;
+                cr[j] = rj;
+                cu[j] = uj;
                 ul[j] = uj;
                 a_rr += rj * rj;
             }
@@ -209,10 +222,10 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
             tm.sync();
             double a_g = 0.0, a_d = 0.0;
             spmv_part<4>(tm, KAt, 1, [&](int c) { return tl[c]; }, [&](int j, double s) {
-                const double uj = V.cg_u[j];
-                const double rj = V.cg_r[j];
+                const double uj = cu[j];
+                const double rj = cr[j];
                 const double wj = uj + s;
-                V.cg_w[j] = wj;
+                cw[j] = wj;
                 a_g += rj * uj;
                 a_d += wj * uj;
             });
@@ -236,18 +249,18 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
         if (done) break;
     }
     // py = ry + A px ; h^T p
-    for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xw[j];
+    for (int j = tm.rank(); j < n; j += tm.size()) ul[j] = xl[j];
     tm.sync();
     double a_hp = 0.0;
     spmv_part<1>(tm, P.A, 0, [&](int c_) { return ul[c_]; }, [&](int i, double s) {
         const double py = r[n + i] + s;
         out[n + i] = py;
-        a_hp += P.b[i] * py;
+        a_hp += bv[i] * py;
     });
     for (int j = tm.rank(); j < n; j += tm.size()) {
-        out[j] = xw[j];
-        a_hp += P.c[j] * xw[j];
-        if (q) q[j] = V.cg_b[j] - V.cg_r[j];
+        out[j] = xl[j];
+        a_hp += cv[j] * xl[j];
+        if (q) vec_at<L>(q)[j] = cb[j] - cr[j];
     }
     put(sh, 0, a_hp);
     tm.reduce(sh, 1);

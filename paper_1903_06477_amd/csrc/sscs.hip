@@ -63,7 +63,8 @@ __device__ inline void grid_team_init(GridTeam<LDS, TL, PT>& tm, const Prob& P) 
 
 // stage_doubles: dynamic LDS of the launch (in doubles) for the CG's gathered
 // vectors; an instance uses it when its n + m entries fit.
-__device__ inline void block_team_init(BlockTeam& tm, const Prob& P, int stage_doubles) {
+template <bool LDS>
+__device__ inline void block_team_init(BlockTeamT<LDS>& tm, const Prob& P, int stage_doubles) {
     tm.mp[0] = MatPart{0, P.A.rows, 0, 0, 0, 0};
     tm.mp[1] = MatPart{0, P.At.rows, 0, 0, 0, 0};
     const bool fit = P.n + P.m <= stage_doubles;
@@ -194,6 +195,98 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     BlockTeam tm;
     block_team_init(tm, d.P, stage_doubles);
     sscs::run_solve<TV>(tm, sh, d.P, d.V, d.S, res);
+}
+
+// LDS plan of the small-instance kernel: after the CG's staging region, the
+// operator (A, then A^T: values, column indices, row pointers), then groups
+// of vectors, each group placed only when it fits, in this order: the
+// problem's vectors (D, b, c, g), the CG's n- and m-vectors, the N-vectors of
+// Algorithm 1, the quasi-Newton memory.  The host computes the plan with the
+// same function, so the kernel's carving and the launch's size agree.
+enum : int { SP_OP = 1, SP_PROB = 2, SP_CG = 4, SP_ITER = 8, SP_MEM = 16 };
+__host__ __device__ inline int sp_align(long long b) { return (int)((b + 15) & ~15ll); }
+__host__ __device__ inline long long sp_op_bytes(int rows, long long nnz) {
+    return sp_align(8 * nnz + 4 * nnz + 4 * (long long)(rows + 1));
+}
+__host__ __device__ inline long long sp_group_bytes(int g, int n, int m, int N, int mem, bool qr) {
+    switch (g) {
+        case SP_PROB: return sp_align(8ll * n) * 2 + sp_align(8ll * m) + sp_align(8ll * (n + m));
+        case SP_CG: return sp_align(8ll * n) * 10 + sp_align(8ll * m);
+        case SP_ITER: return sp_align(8ll * N) * 9;
+        case SP_MEM: return sp_align(8ll * N) * (long long)mem * (qr ? 3 : 2);
+        default: return 0;
+    }
+}
+
+// Algorithm 1 for one small instance in a single workgroup with its working
+// set in LDS (plan `mask`, above): every pass then reads and writes LDS
+// instead of waiting on the memory hierarchy.  Vectors are reached through
+// the same descriptors as in global memory (generic addresses), so the engine
+// code is shared; the outputs, the trace and the PSD buffers stay global.
+// OPL (launched only when the plan holds the operator, the problem's vectors
+// and the CG's vectors): the CG addresses those through LDS pointers.
+template <bool OPL>
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) k_solve_small(
+    Prob P, Vecs V, Params S, Result* res, int stage_doubles, int mask) {
+    __shared__ Shared sh;
+    __shared__ Desc d;
+    if (threadIdx.x == 0) {
+        d.P = P;
+        d.V = V;
+        d.S = S;
+    }
+    __syncthreads();
+    BlockTeamT<OPL> tm;
+    block_team_init(tm, d.P, stage_doubles);
+    const int n = P.n, m = P.m, N = P.N, mem = S.mem;
+    int off = sp_align(8ll * stage_doubles);
+    if constexpr (OPL) {
+        const int pa[2] = {0, m}, pt[2] = {0, n};
+        load_part(tm.mp[0], P.A, pa, 0, true, &off);
+        load_part(tm.mp[1], P.At, pt, 0, true, &off);
+    }
+    char* lds = reinterpret_cast<char*>(sscs_dyn_lds);
+    auto take = [&](long long cnt) {
+        double* q = reinterpret_cast<double*>(lds + off);
+        off += sp_align(8 * cnt);
+        return q;
+    };
+    auto copy_in = [&](double* dst, const double* src, long long cnt) {
+        for (long long i = threadIdx.x; i < cnt; i += blockDim.x) dst[i] = src[i];
+    };
+    Prob& Q = d.P;
+    Vecs& W = d.V;
+    __syncthreads();                  // every thread has read d.P / d.V before thread 0 rewires them
+    if (mask & SP_PROB) {
+        double* dinv = take(n); double* c = take(n); double* b = take(m); double* g = take(n + m);
+        copy_in(dinv, P.dinv, n); copy_in(c, P.c, n); copy_in(b, P.b, m); copy_in(g, P.g, n + m);
+        if (threadIdx.x == 0) { Q.dinv = dinv; Q.c = c; Q.b = b; Q.g = g; }
+    }
+    if (mask & SP_CG) {
+        double* v[10];
+        for (int i = 0; i < 10; ++i) v[i] = take(n);
+        double* t = take(m);
+        if (threadIdx.x == 0) {
+            W.xw_u = v[0]; W.xw_d = v[1]; W.q_u = v[2]; W.q_d = v[3]; W.cg_b = v[4];
+            W.cg_u = v[5]; W.cg_w = v[6]; W.cg_p = v[7]; W.cg_r = v[8]; W.cg_s = v[9]; W.cg_t = t;
+        }
+    }
+    if (mask & SP_ITER) {
+        double* v[9];
+        for (int i = 0; i < 9; ++i) v[i] = take(N);
+        if (threadIdx.x == 0) {
+            W.u = v[0]; W.ut = v[1]; W.ub = v[2]; W.Ru = v[3]; W.d = v[4]; W.dt = v[5]; W.Rw = v[6];
+            W.pz = v[7]; W.pxi = v[8];
+        }
+    }
+    if (mask & SP_MEM) {
+        double* z = take((long long)mem * N);
+        double* y = take((long long)mem * N);
+        double* qb = S.direction == DIR_AA_QR ? take((long long)mem * N) : nullptr;
+        if (threadIdx.x == 0) { W.Zb = z; W.Yb = y; if (qb) W.Qb = qb; }
+    }
+    __syncthreads();
+    sscs::run_solve<double>(tm, sh, d.P, d.V, d.S, res);
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, long long n, float* __restrict__ b) {
@@ -434,6 +527,28 @@ int stage_doubles(long long entries) {
     return attr ? (int)entries : 0;
 }
 
+// Dynamic LDS the small-instance kernel may take (its static LDS and a margin
+// subtracted from the device's per-workgroup limit); the limit is raised on
+// both instantiations once.
+int small_lds_budget() {
+    static const int budget = [] {
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+        long long stat = 0;
+        for (const void* f : {(const void*)k_solve_small<true>, (const void*)k_solve_small<false>}) {
+            hipFuncAttributes fa{};
+            if (hipFuncGetAttributes(&fa, f) != hipSuccess) return 0;
+            stat = std::max<long long>(stat, (long long)fa.sharedSizeBytes);
+        }
+        const int b = (int)std::max<long long>(0, (long long)lds_max - stat - 256);
+        for (const void* f : {(const void*)k_solve_small<true>, (const void*)k_solve_small<false>})
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess) return 0;
+        return b;
+    }();
+    return budget;
+}
+
 int pow2_seg(double avg) {
     const double div = 4.0;
     int s = 1;
@@ -466,6 +581,35 @@ struct Inst {
     int *partA = nullptr, *partAt = nullptr;
     int lds_bytes = 0;                     // dynamic LDS of the grid kernels (0: operator in HBM)
 };
+
+// The small kernel's plan for an FP64 instance: mask of what goes to LDS (see
+// k_solve_small) and the dynamic LDS bytes; mask 0 when the CG's staging
+// region itself does not fit.
+int small_plan(const Inst& I, const sscs_settings& st, int* bytes) {
+    *bytes = 0;
+    const long long stage = I.n + (long long)I.m;
+    const int budget = small_lds_budget();
+    if (I.mixed || stage > kStageMax || budget <= 0) return 0;
+    long long off = sp_align(8 * stage);
+    if (off > budget) return 0;
+    int mask = 0;
+    const long long op = sp_op_bytes(I.m, I.nnz) + sp_op_bytes(I.n, I.nnz);
+    if (off + op <= budget) { off += op; mask |= SP_OP; }
+    for (int g : {(int)SP_PROB, (int)SP_CG, (int)SP_ITER, (int)SP_MEM}) {
+        const long long gb = sp_group_bytes(g, I.n, I.m, I.N, st.mem, st.direction == SSCS_DIR_AA_QR);
+        if (off + gb <= budget) { off += gb; mask |= g; }
+    }
+    *bytes = (int)off;
+    return mask;
+}
+
+// A single instance runs on the small kernel (one workgroup, working set in
+// LDS) when its operator, problem vectors, CG vectors and iterates all fit.
+bool small_fits(const Inst& I, const sscs_settings& st) {
+    int bytes = 0;
+    const int need = SP_OP | SP_PROB | SP_CG | SP_ITER;
+    return (small_plan(I, st, &bytes) & need) == need;
+}
 
 // check_csr = false skips the walk over A (an instance that shares instance
 // 0's arrays, already checked).
@@ -987,6 +1131,7 @@ int choose_grid(sscs_work* w) {
     const long long want = std::max<long long>((w->I.nnz + 2ll * kBlock - 1) / (2ll * kBlock),
                                                ((long long)w->I.N + kBlock - 1) / kBlock);
     w->grid = (int)std::max<long long>(1, std::min<long long>(want, w->max_grid));
+    if (small_fits(w->I, w->st)) w->grid = 1;     // one workgroup with its working set in LDS
     if (w->st.workgroups >= 1) w->grid = std::min(w->st.workgroups, w->max_grid);
     int rate_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
@@ -1220,8 +1365,14 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
     if (w->grid == 1) {
         HIP_TRY(hipMemsetAsync(w->abort_flag, 0, sizeof(int), w->stream));
         const int sd = stage_doubles(w->I.n + w->I.m);
+        int bytes = 0;
+        const int mask = small_plan(w->I, w->st, &bytes);
         if (w->I.mixed)
             k_solve_block<float><<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
+        else if ((mask & (SP_OP | SP_PROB | SP_CG)) == (SP_OP | SP_PROB | SP_CG))
+            k_solve_small<true><<<1, kBatchBlock, bytes, w->stream>>>(P, V, S, w->res, (int)(w->I.n + w->I.m), mask);
+        else if (mask)
+            k_solve_small<false><<<1, kBatchBlock, bytes, w->stream>>>(P, V, S, w->res, (int)(w->I.n + w->I.m), mask);
         else
             k_solve_block<double><<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
     } else {

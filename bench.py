@@ -1,22 +1,25 @@
 """Throughput of the SuperSCS hot path on one MI355X.
 
-A step is one complete solve (Algorithm 1 to pr, dr, gap <= 1e-6) of the
-sparse SOCP workload: n = 20000, m = 50000, A at density 1e-3 with N(0,1)
-values, K = zero 1000 + R+ 20000 + second-order cones of sizes uniform in
-[3, 50], planted primal-dual optimum, Anderson memory 5, FP64.  The instance
-is resident in HBM before timing; outputs go to device buffers.
+A step solves five seeded instances (0..4) of the sparse SOCP workload, each
+to pr, dr, gap <= 1e-6 by Algorithm 1: n = 20000, m = 50000, A at density
+1e-3 with N(0,1) values, K = zero 1000 + R+ 20000 + second-order cones of
+sizes uniform in [3, 50], planted primal-dual optimum, Anderson memory 5,
+FP64.  One instance's iteration count moves with the rounding order of its
+reductions, so the workload is the family's, over five seeds.  The
+instances are resident in HBM before timing; outputs go to device buffers.
 
-Prints one JSON line with the metric, the roofline of the dominant kernel
-(the persistent solve kernel) and the CPU oracle timed on a bounded sample.
-Further fields measure the other workloads on the same GPU: the same SOCP
-with the mixed-precision linear step, by plain relaxed DRS (no SuperMann
-steps) and on further seeded instances; the stand-alone SpMV of the CG on
-the SOCP's matrix and on a 1e8-nonzero matrix past the on-package cache; the
-LP (single and 1024 seeds batched); the mixed PSD / exponential-cone
-instance solved to 1e-6; 4096 batched LASSO instances in one launch; the
-learned warm start (90000 training / 10000 held-out instances) against the
-cold-started method and against a training-mean start; and the oracle timed
-on the host for every workload.
+Prints one JSON line with the metric (solves per second over the five), the
+roofline of the dominant kernel (the persistent solve kernel, averaged over
+its launches) and the CPU oracle timed on a bounded sample.  Further fields
+measure the other workloads on the same GPU: the SOCP with the
+mixed-precision linear step, by plain relaxed DRS, SCS's splitting and
+Anderson by QR; the stand-alone SpMV of the CG on the SOCP's matrix and on a
+1e8-nonzero matrix past the on-package cache; the LP (single and 1024 seeds
+batched); the mixed PSD / exponential-cone instance solved to 1e-6; 4096
+batched LASSO instances in one launch; the learned warm start (90000
+training / 10000 held-out instances) against the cold-started method and
+against a training-mean start; and the oracle timed on the host for every
+workload.
 """
 from __future__ import annotations
 
@@ -35,6 +38,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "solves/s to 1e-6 residual; CG SpMV HBM GB/s; learned+batched vs plain"
 
+HEADLINE_INSTANCES = 5       # seeded instances of the sparse SOCP family in the headline workload
 
 def spmv_bytes(nnz, rows, cols, bval=8):
     """Algorithmic bytes of one CSR SpMV: values + column indices, row
@@ -379,35 +383,6 @@ def config1_leg(sscs, G, reps=20, batch=1024):
                         "note": "solves/s counts the instances solved to 1e-6 within the 20000-iteration cap"}}
 
 
-def config2_instances_leg(sscs, G, instances=(1, 2, 3, 4)):
-    """The SOCP workload over further seeded instances (one warm-up and one
-    timed solve each): iteration counts and solves/s vary with the instance,
-    since the trajectory of Algorithm 1 does."""
-    import torch
-    rows = []
-    dev = torch.device("cuda:0")
-    for i in instances:
-        p = G.config2_socp(i)
-        st = bench_settings(sscs, 20000)
-        x = torch.empty(p.n, dtype=torch.float64, device=dev)
-        y = torch.empty(p.m, dtype=torch.float64, device=dev)
-        sv = torch.empty(p.m, dtype=torch.float64, device=dev)
-        with sscs.Solver(p, st) as s:
-            s.solve(out=(x, y, sv))
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            info = s.solve(out=(x, y, sv))[3]
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-        pr, dr, gap = host_kkt(p, x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy())
-        ok = info["status"] == sscs.SOLVED and max(pr, dr, gap) <= 1e-6 * 1.0001
-        rows.append({"instance": i, "iters": info["iters"], "solve_s": wall, "solves_per_s": 1.0 / wall if ok else 0.0,
-                     "pr_host": pr, "dr_host": dr})
-    v = np.array([r["solves_per_s"] for r in rows])
-    return {"instances": rows, "solves_per_s_mean": float(v.mean()), "solves_per_s_min": float(v.min()),
-            "solves_per_s_max": float(v.max())}
-
-
 def spmv_large_leg(sscs, G, reps=20):
     """The CG's SpMV on the SOCP workload's matrix shape scaled to 5e6 x 2e4
     with 1e8 nonzeros (1.2 GB of values and indices, past the 256 MB
@@ -596,7 +571,6 @@ def main():
     ap.add_argument("--sdp-iters", type=int, default=20000,
                     help="iteration cap of the PSD / exponential-cone leg (the default solves it to 1e-6)")
     ap.add_argument("--no-config1", action="store_true", help="skip the LP leg")
-    ap.add_argument("--no-instances", action="store_true", help="skip the further SOCP instances")
     ap.add_argument("--no-spmv-large", action="store_true", help="skip the cache-exceeding SpMV leg")
     ap.add_argument("--learned-train", type=int, default=90000, help="training instances of the learned leg")
     ap.add_argument("--learned-test", type=int, default=10000, help="held-out instances of the learned leg")
@@ -629,52 +603,66 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
-    prob = G.config2_socp()
+    # the workload: HEADLINE_INSTANCES seeded instances of the sparse SOCP
+    # family, each solved once per step (one instance's trajectory, and so its
+    # iteration count, moves with rounding order; their mean does not)
+    probs = [G.config2_socp(i) for i in range(HEADLINE_INSTANCES)]
+    prob = probs[0]
     n, m, nnz = prob.n, prob.m, prob.A.nnz
     stream = torch.cuda.current_stream()
     st = bench_settings(sscs, args.max_iters)
-    solver = sscs.Solver(prob, st, stream=stream.cuda_stream)
-    x = torch.empty(n, dtype=torch.float64, device=dev)
-    y = torch.empty(m, dtype=torch.float64, device=dev)
-    s = torch.empty(m, dtype=torch.float64, device=dev)
+    solvers = [sscs.Solver(p, st, stream=stream.cuda_stream) for p in probs]
+    outs = [(torch.empty(p.n, dtype=torch.float64, device=dev), torch.empty(p.m, dtype=torch.float64, device=dev),
+             torch.empty(p.m, dtype=torch.float64, device=dev)) for p in probs]
 
     for _ in range(args.warmup):
-        solver.solve(out=(x, y, s))
+        for sv_, o in zip(solvers, outs):
+            sv_.solve(out=o)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    infos = []
+    ni = len(probs)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps * ni + 1)]
+    infos = [[] for _ in range(ni)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        infos.append(solver.solve(out=(x, y, s))[3])
-    ev1.record(stream)
+    evs[0].record(stream)
+    for k in range(args.steps):
+        for i, (sv_, o) in enumerate(zip(solvers, outs)):
+            infos[i].append(sv_.solve(out=o)[3])
+            evs[k * ni + i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
+    per_ms = np.array([[evs[k * ni + i].elapsed_time(evs[k * ni + i + 1]) for i in range(ni)]
+                       for k in range(args.steps)])             # steps x instances, ms per solve
 
-    solved = all(i["status"] == sscs.SOLVED for i in infos)
+    solved = all(f["status"] == sscs.SOLVED for inf in infos for f in inf)
     ms_per_step = wall * 1e3 / args.steps
-    value = args.steps / wall if solved else 0.0
+    value = args.steps * ni / wall if solved else 0.0
     # roofline of the solve kernel: CG-operator equivalents x bytes per operator,
-    # plus the vector passes of the outer iterations
-    units = np.mean([op_units(i) for i in infos])
-    vec_bytes = float(np.mean([outer_vector_bytes(i, n + m + 1) for i in infos]))
-    bytes_per_launch = units * cg_op_bytes(nnz, m, n) + vec_bytes
-    kernel_ms = ev_ms / args.steps
-    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    # plus the vector passes of the outer iterations, averaged over the launches
+    op_b = cg_op_bytes(nnz, m, n)
+    launch_bytes = [op_units(f) * op_b + outer_vector_bytes(f, n + m + 1) for inf in infos for f in inf]
+    bytes_per_launch = float(np.mean(launch_bytes))
+    units = float(np.mean([op_units(f) for inf in infos for f in inf]))
+    vec_bytes = float(np.mean([outer_vector_bytes(f, n + m + 1) for inf in infos for f in inf]))
+    kernel_ms = float(per_ms.mean())
+    achieved = float(np.sum(launch_bytes)) / (per_ms.sum() * 1e-3) / 1e9
     # stand-alone SpMV of the CG (same kernel code), device-resident, event-timed
     reps = 200
-    ms_a = solver.spmv_bench(False, reps) / reps
-    ms_t = solver.spmv_bench(True, reps) / reps
+    ms_a = solvers[0].spmv_bench(False, reps) / reps
+    ms_t = solvers[0].spmv_bench(True, reps) / reps
     gbs_a = spmv_bytes(nnz, m, n) / (ms_a * 1e-3) / 1e9
     gbs_t = spmv_bytes(nnz, n, m) / (ms_t * 1e-3) / 1e9
-    # accuracy of the timed solve, recomputed on the host in FP64
-    xh, yh, sh = x.cpu().numpy(), y.cpu().numpy(), s.cpu().numpy()
-    pr = float(np.linalg.norm(prob.A @ xh + sh - prob.b) / (1 + np.linalg.norm(prob.b)))
-    dr = float(np.linalg.norm(prob.A.T @ yh + prob.c) / (1 + np.linalg.norm(prob.c)))
-    pstar = float(prob.c @ prob.x_star)
-    obj_err = abs(float(prob.c @ xh) - pstar) / (1 + abs(pstar))
-    last = infos[-1]
+    # accuracy of every instance's last timed solve, recomputed on the host in FP64
+    rows = []
+    for i, (p, o) in enumerate(zip(probs, outs)):
+        xh, yh, sh = (t.cpu().numpy() for t in o)
+        pr, dr, gap = host_kkt(p, xh, yh, sh)
+        pstar = float(p.c @ p.x_star)
+        f = infos[i][-1]
+        rows.append({"instance": i, "iters": f["iters"], "cg_iters": f["cg_iters"], "k0": f["k0"], "k1": f["k1"],
+                     "k2": f["k2"], "km": f["km"], "backtracks": f["backtracks"],
+                     "solve_ms": float(per_ms[:, i].mean()), "pr_host": pr, "dr_host": dr, "gap_host": gap,
+                     "obj_err_vs_planted": abs(float(p.c @ xh) - pstar) / (1 + abs(pstar))})
+    iters_mean = float(np.mean([r["iters"] for r in rows]))
     out = {
         "metric": METRIC,
         "value": value,
@@ -688,24 +676,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "sparse SOCP n=20000 m=50000 density 1e-3, zero 1000 + R+ 20000 + "
-                               f"{len(prob.cone.q)} SOC (sizes 3..50), planted optimum, AA mem 5, eps 1e-6",
+        "config": {"workload": f"sparse SOCP n=20000 m=50000 density 1e-3, zero 1000 + R+ 20000 + SOC (sizes 3..50), "
+                               f"planted optimum, AA mem 5, eps 1e-6; seeded instances 0..{ni - 1}, each solved "
+                               f"once per step",
                    "settings": {"lambda": 1.5, "c1": 0.9999, "q": 0.999, "sigma": 0.01, "c0": 0.99,
                                 "cg_adapt": 0.2, "cg_tol": 1e-12},
-                   "n": n, "m": m, "nnz": int(nnz), "parallelism": "single GPU"},
-        "iterations_per_s": last["iters"] * value,
-        "solve": {"iters": last["iters"], "cg_iters": last["cg_iters"], "k0": last["k0"], "k1": last["k1"],
-                  "k2": last["k2"], "km": last["km"], "backtracks": last["backtracks"],
-                  "pr": pr, "dr": dr, "gap": last["gap"], "obj_err_vs_planted": obj_err},
+                   "n": n, "m": m, "nnz": int(nnz), "instances": ni, "parallelism": "single GPU"},
+        "iterations_per_s": iters_mean * value,
+        "solves": rows,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_solve_grid", "kernel_ms": kernel_ms,
                      "bytes_per_launch": bytes_per_launch, "cg_op_units": units,
-                     "cg_op_bytes": cg_op_bytes(nnz, m, n), "outer_vector_bytes": vec_bytes},
+                     "cg_op_bytes": op_b, "outer_vector_bytes": vec_bytes},
         "spmv": {"A_us": ms_a * 1e3, "A_GBs": gbs_a, "At_us": ms_t * 1e3, "At_GBs": gbs_t,
                  "frac_of_hbm": max(gbs_a, gbs_t) / HBM_PEAK_GBS},
     }
-    solver.close()
+    x, y, s = outs[0]
+    for sv_ in solvers:
+        sv_.close()
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
     if not args.no_host_io:
         out["host_io"] = host_io_leg(sscs, prob, stream)
@@ -763,9 +752,6 @@ def main():
                                 "gap": isc["gap"],
                                 "method": "SCS's splitting: Douglas-Rachford on N_C + Q (lambda 1.5), no SuperMann steps"}
     del x, y, s
-    if not args.no_instances:
-        log("bench: further SOCP instances")
-        out["socp_instances"] = config2_instances_leg(sscs, G)
     if not args.no_config1:
         log("bench: LP leg")
         out["config1_lp"] = config1_leg(sscs, G)
@@ -786,7 +772,7 @@ def main():
         out["learned_vs_plain"] = learned_leg(args.learned_train, args.learned_test)
     if not args.no_cpu:
         log("bench: CPU oracle legs")
-        out["cpu_baseline"] = cpu_baseline(prob, last["iters"])
+        out["cpu_baseline"] = cpu_baseline(prob, iters_mean)
         others = {}
         if not args.no_config1:
             others["config1_lp"] = cpu_config1(G.config1_lp())

@@ -383,6 +383,38 @@ def config1_leg(sscs, G, reps=20, batch=1024):
                         "note": "solves/s counts the instances solved to 1e-6 within the 20000-iteration cap"}}
 
 
+def direct_leg(sscs, G):
+    """The direct linear step (dense Cholesky of I + A^T A factored on the
+    device, Sec. IV-A) against the CG on one held-out instance of the
+    shared-A LASSO family (conic n 2001, m 4002): create time (which includes
+    the factorisation), solve time of a second solve, iterations, host KKT."""
+    import torch
+    A = G.config5_shared_A()
+    p = G.config5_family([90000], A)[0]
+    out = {"workload": f"shared-A LASSO instance 90000, conic n {p.n}, m {p.m}, nnz {int(p.A.nnz)}, AA mem 5, eps 1e-6"}
+    for ls in ("cg", "direct"):
+        st = bench_settings(sscs, 20000)
+        st.linsys = ls
+        st.data_on_device = False
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = sscs.Solver(p, st)
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t0
+        s.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, y, sv, info = s.solve()
+        wall = time.perf_counter() - t0
+        s.close()
+        pr, dr, gap = host_kkt(p, x, y, sv)
+        ok = info["status"] == sscs.SOLVED and max(pr, dr, gap) <= 1e-6 * 1.0001
+        out[ls] = {"create_s": t_create, "solve_s": wall, "solves_per_s": 1.0 / wall if ok else 0.0,
+                   "iters": info["iters"], "cg_iters": info["cg_iters"], "us_per_iteration": wall * 1e6 / max(1, info["iters"]),
+                   "pr_host": pr, "dr_host": dr, "gap_host": gap}
+    return out
+
+
 def spmv_large_leg(sscs, G, reps=20):
     """The CG's SpMV on the SOCP workload's matrix shape scaled to 5e6 x 2e4
     with 1e8 nonzeros (1.2 GB of values and indices, past the 256 MB
@@ -572,6 +604,7 @@ def main():
                     help="iteration cap of the PSD / exponential-cone leg (the default solves it to 1e-6)")
     ap.add_argument("--no-config1", action="store_true", help="skip the LP leg")
     ap.add_argument("--no-spmv-large", action="store_true", help="skip the cache-exceeding SpMV leg")
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-linear-step leg")
     ap.add_argument("--learned-train", type=int, default=90000, help="training instances of the learned leg")
     ap.add_argument("--learned-test", type=int, default=10000, help="held-out instances of the learned leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -764,6 +797,9 @@ def main():
         log("bench: batched leg")
         probs4 = [G.config4_instance(i) for i in range(4096)]
         out["batched"] = batched_leg(sscs, G, probs=probs4)
+    if not args.no_direct:
+        log("bench: direct linear step leg")
+        out["direct_linear_step"] = direct_leg(sscs, G)
     if not args.no_spmv_large:
         log("bench: cache-exceeding SpMV leg")
         out["spmv_large"] = spmv_large_leg(sscs, G)

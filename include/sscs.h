@@ -71,6 +71,15 @@ extern "C" {
                                     steps; the state is z, the candidate Pi_C(z) */
 
 /* Precision of the linear step (Sec. IV-A, indirect solve). */
+/* Linear step (I + Q)^{-1} (Sec. IV-A): the reduced system I + A^T A of the
+ * HSDE solved iteratively or directly. */
+#define SSCS_LINSYS_CG       0   /* conjugate gradients, Jacobi preconditioned, warm-started */
+#define SSCS_LINSYS_DIRECT   1   /* dense Cholesky factor L L^T = I + A^T A formed and factored
+                                    once on the device at create (n <= SSCS_DIRECT_NMAX, FP64,
+                                    single-instance solves on one workgroup); each linear step
+                                    is a forward and a backward substitution with it */
+#define SSCS_DIRECT_NMAX  4096
+
 #define SSCS_PREC_FP64       0   /* FP64 everywhere */
 #define SSCS_PREC_MIXED      1   /* the CG iterations apply I + A^T A with FP32 copies of
                                     A's values (FP64 vectors, accumulation and scalar
@@ -133,6 +142,11 @@ typedef struct {
                                      solves run on k workgroups (1: the one-workgroup
                                      kernel), capped by what stays co-resident.  Read at
                                      create; update_settings may not change it. */
+    int32_t linsys;               /* SSCS_LINSYS_*; read at create, update_settings may not
+                                     change it.  DIRECT: SSCS_E_UNSUPPORTED when n exceeds
+                                     SSCS_DIRECT_NMAX, with SSCS_PREC_MIXED, for batches and
+                                     for sscs_solve_noalloc; cg_* settings are then unused
+                                     and cg_iters reports 0 */
 } sscs_settings;
 
 /* Result of a solve. */
@@ -156,7 +170,7 @@ typedef struct sscs_batch sscs_batch;
 /* Fills *st with defaults: eps 1e-6, AA mem 5, c0 0.99 (0.1 is the paper's
  * advice for RB, Sec. IV-D-1), c1 0.9999, q 0.999, sigma 0.01, lambda 1.5,
  * thetabar 0.1, ls_max 10, FP64, cg_tol 1e-10, cg_max 500, aa_reg 1e-12,
- * cg_adapt 0, cg_d_match 1, check_every 1, workgroups 0.  Algorithm 1 leaves
+ * cg_adapt 0, cg_d_match 1, check_every 1, workgroups 0, linsys CG.  Algorithm 1 leaves
  * c1, q and lambda open; with c1 = q = 0.99 and lambda = 1 Anderson can stall
  * in K2 steps and restarted Broyden in steps at the backtracking cap. */
 int sscs_default_settings(sscs_settings *st);

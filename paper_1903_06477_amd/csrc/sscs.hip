@@ -289,6 +289,151 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     sscs::run_solve<double>(tm, sh, d.P, d.V, d.S, res);
 }
 
+// ------------------------------------------------------------ direct linear step
+// Dense Cholesky of the reduced system M = I + A^T A (Sec. IV-A), column-major
+// and in place, by blocks of DIRECT_B: the diagonal block factored (and
+// inverted) by one workgroup in LDS, the panel below it by triangular solves
+// against that inverse, the trailing lower triangle updated tile by tile.
+
+// M = I + A^T A: entry (i, j) is 1[i = j] + <A e_i, A e_j>, the sorted rows i and
+// j of A^T merged; one thread per entry of the lower triangle, both halves written.
+__global__ void k_form_normal(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                              int n, double* __restrict__ M) {
+    const int i = blockIdx.y * blockDim.y + threadIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || j > i) return;
+    int a = rp[i], ae = rp[i + 1], b = rp[j], be = rp[j + 1];
+    double s = (i == j) ? 1.0 : 0.0;
+    while (a < ae && b < be) {
+        const int ca = ci[a], cb = ci[b];
+        if (ca == cb) { s += v[a] * v[b]; ++a; ++b; }
+        else if (ca < cb) ++a;
+        else ++b;
+    }
+    M[(size_t)j * n + i] = s;
+    M[(size_t)i * n + j] = s;
+}
+
+// Factors the diagonal block at k0 (order kn) in LDS, writes L_bb into M and
+// L_bb^{-1} (row-major, zero-padded to DIRECT_B) into Li.  *err = 1 on a
+// non-positive pivot.
+__global__ void __launch_bounds__(256) k_chol_diag(double* __restrict__ M, int n, int k0, int kn,
+                                                   double* __restrict__ Li, int* err) {
+    __shared__ double A[DIRECT_B][DIRECT_B + 1];
+    __shared__ double X[DIRECT_B][DIRECT_B + 1];
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int i = e / DIRECT_B, j = e % DIRECT_B;
+        A[i][j] = (i < kn && j < kn) ? M[(size_t)(k0 + j) * n + (k0 + i)] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < kn; ++k) {
+        if (t == 0) {
+            const double d = A[k][k];
+            if (!(d > 0.0)) *err = 1;
+            A[k][k] = sqrt(fmax(d, 1e-300));
+        }
+        __syncthreads();
+        const double d = A[k][k];
+        for (int i = k + 1 + t; i < kn; i += nt) A[i][k] /= d;
+        __syncthreads();
+        const int w = kn - k - 1;
+        for (int e = t; e < w * w; e += nt) {
+            const int i = k + 1 + e / w, j = k + 1 + e % w;
+            if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+        }
+        __syncthreads();
+    }
+    // X = L^{-1}, column c by thread c: forward substitution of L X e_c = e_c
+    for (int c = t; c < DIRECT_B; c += nt) {
+        for (int i = 0; i < DIRECT_B; ++i) X[i][c] = 0.0;
+        if (c < kn) {
+            for (int i = c; i < kn; ++i) {
+                double s = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) s -= A[i][k] * X[k][c];
+                X[i][c] = s / A[i][i];
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int i = e / DIRECT_B, j = e % DIRECT_B;
+        Li[e] = X[i][j];
+        if (i < kn && j < kn && j <= i) M[(size_t)(k0 + j) * n + (k0 + i)] = A[i][j];
+    }
+}
+
+// The panel below the diagonal block: L[i, k0 + c] = sum_k M[i, k0 + k] Li[c][k]
+// for the DIRECT_B rows of this workgroup (i >= k0 + kn).
+__global__ void __launch_bounds__(256) k_chol_panel(double* __restrict__ M, int n, int k0, int kn,
+                                                    const double* __restrict__ Li) {
+    __shared__ double R[DIRECT_B][DIRECT_B + 1];   // rows of this workgroup, panel columns
+    __shared__ double I_[DIRECT_B][DIRECT_B + 1];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int r0 = k0 + kn + blockIdx.x * DIRECT_B;
+    const int rn = min(DIRECT_B, n - r0);
+    if (rn <= 0) return;
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, k = e / DIRECT_B;   // consecutive threads: consecutive rows
+        R[a][k] = (a < rn && k < kn) ? M[(size_t)(k0 + k) * n + (r0 + a)] : 0.0;
+        I_[k][a] = Li[(size_t)k * DIRECT_B + a];
+    }
+    __syncthreads();
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, c = e / DIRECT_B;
+        if (a >= rn || c >= kn) continue;
+        double s = 0.0;
+        for (int k = 0; k <= c; ++k) s += R[a][k] * I_[c][k];
+        M[(size_t)(k0 + c) * n + (r0 + a)] = s;
+    }
+}
+
+// Trailing update of the lower triangle below and right of the panel:
+// M[i, j] -= sum_k L[i, k0 + k] L[j, k0 + k], one DIRECT_B x DIRECT_B tile per
+// workgroup (tiles above the diagonal return at once).
+__global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ M, int n, int k0, int kn) {
+    const int ti = blockIdx.y, tj = blockIdx.x;
+    if (tj > ti) return;
+    __shared__ double Pi[DIRECT_B][DIRECT_B + 1];
+    __shared__ double Pj[DIRECT_B][DIRECT_B + 1];
+    const int base = k0 + kn;
+    const int i0 = base + ti * DIRECT_B, j0 = base + tj * DIRECT_B;
+    const int in_ = min(DIRECT_B, n - i0), jn = min(DIRECT_B, n - j0);
+    if (in_ <= 0 || jn <= 0) return;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, k = e / DIRECT_B;
+        Pi[a][k] = (a < in_ && k < kn) ? M[(size_t)(k0 + k) * n + (i0 + a)] : 0.0;
+        Pj[a][k] = (a < jn && k < kn) ? M[(size_t)(k0 + k) * n + (j0 + a)] : 0.0;
+    }
+    __syncthreads();
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, b = e / DIRECT_B;      // row i0 + a, column j0 + b
+        if (a >= in_ || b >= jn) continue;
+        if (ti == tj && b > a) continue;
+        double s = 0.0;
+        for (int k = 0; k < kn; ++k) s += Pi[a][k] * Pj[b][k];
+        M[(size_t)(j0 + b) * n + (i0 + a)] -= s;
+    }
+}
+
+// B = A^T for n x n column-major arrays (tiles through LDS).
+__global__ void __launch_bounds__(256) k_transpose_sq(const double* __restrict__ A, int n, double* __restrict__ B) {
+    __shared__ double T[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+        const int a = e % 32, b = e / 32;
+        const int r = by + a, c = bx + b;
+        T[b][a] = (r < n && c < n) ? A[(size_t)c * n + r] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+        const int a = e % 32, b = e / 32;
+        const int r = bx + a, c = by + b;                 // B[r, c] = A[c, r]
+        if (r < n && c < n) B[(size_t)c * n + r] = T[a][b];
+    }
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, long long n, float* __restrict__ b) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         b[i] = (float)a[i];
@@ -580,6 +725,7 @@ struct Inst {
     std::vector<int> h_rpA, h_rpAt;        // host row pointers (partitioning)
     int *partA = nullptr, *partAt = nullptr;
     int lds_bytes = 0;                     // dynamic LDS of the grid kernels (0: operator in HBM)
+    double *Lc = nullptr, *Lt = nullptr, *Linv = nullptr;   // direct linear step (factor of I + A^T A)
 };
 
 // The small kernel's plan for an FP64 instance: mask of what goes to LDS (see
@@ -657,6 +803,7 @@ int validate_settings(const sscs_settings* st) {
     if (st->cg_d_match != 0 && st->cg_d_match != 1) return SSCS_E_INVALID;
     if (st->precision != SSCS_PREC_FP64 && st->precision != SSCS_PREC_MIXED) return SSCS_E_INVALID;
     if (st->check_every < 0 || st->workgroups < 0) return SSCS_E_INVALID;
+    if (st->linsys != SSCS_LINSYS_CG && st->linsys != SSCS_LINSYS_DIRECT) return SSCS_E_INVALID;
     return SSCS_OK;
 }
 
@@ -840,6 +987,7 @@ void free_instance(Inst& I) {
     hipFree(I.K.psd_team);
     hipFree(I.K.psd_warm);
     hipFree(I.partA); hipFree(I.partAt);
+    hipFree(I.Lc); hipFree(I.Lt); hipFree(I.Linv);
     I = Inst{};
 }
 
@@ -854,6 +1002,7 @@ Prob make_prob(const Inst& I) {
     P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.lds_bytes > 0 ? 1 : 0;
     P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
     P.K = I.K;
+    P.Lc = I.Lc; P.Lt = I.Lt; P.Linv = I.Linv;
     return P;
 }
 
@@ -1133,6 +1282,7 @@ int choose_grid(sscs_work* w) {
     w->grid = (int)std::max<long long>(1, std::min<long long>(want, w->max_grid));
     if (small_fits(w->I, w->st)) w->grid = 1;     // one workgroup with its working set in LDS
     if (w->st.workgroups >= 1) w->grid = std::min(w->st.workgroups, w->max_grid);
+    if (w->st.linsys == SSCS_LINSYS_DIRECT) w->grid = 1;   // the substitutions run in one workgroup
     int rate_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
     w->ticks_per_s = rate_khz > 0 ? rate_khz * 1000.0 : 1e8;
@@ -1210,6 +1360,52 @@ int alloc_work_vectors(sscs_work* w) {
     return SSCS_OK;
 }
 
+// The factor of the direct linear step, on the device: M = I + A^T A formed
+// from the rows of A^T, then the blocked Cholesky in place, then L^T.
+int build_direct(sscs_work* w) {
+    Inst& I = w->I;
+    const int n = I.n;
+    if (n > SSCS_DIRECT_NMAX || I.mixed) {
+        g_unsupported = n > SSCS_DIRECT_NMAX ? "the direct linear step takes n <= SSCS_DIRECT_NMAX"
+                                             : "the direct linear step is FP64 only";
+        return SSCS_E_UNSUPPORTED;
+    }
+    const int nb = (n + DIRECT_B - 1) / DIRECT_B;
+    TRY(dmalloc(&I.Lc, (size_t)n * n));
+    TRY(dmalloc(&I.Lt, (size_t)n * n));
+    TRY(dmalloc(&I.Linv, (size_t)nb * DIRECT_B * DIRECT_B));
+    int* err = nullptr;
+    TRY(dmalloc(&err, 1));
+    const hipStream_t st = w->stream;
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
+    k_form_normal<<<dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, st>>>(I.At_rp, I.At_ci, I.At_v, n, I.Lc);
+    for (int b = 0; b < nb; ++b) {
+        const int k0 = b * DIRECT_B, kn = std::min(DIRECT_B, n - k0);
+        k_chol_diag<<<1, 256, 0, st>>>(I.Lc, n, k0, kn, I.Linv + (size_t)b * DIRECT_B * DIRECT_B, err);
+        const int rest = n - k0 - kn;
+        if (rest > 0) {
+            const int nt = (rest + DIRECT_B - 1) / DIRECT_B;
+            k_chol_panel<<<nt, 256, 0, st>>>(I.Lc, n, k0, kn, I.Linv + (size_t)b * DIRECT_B * DIRECT_B);
+            k_chol_update<<<dim3(nt, nt), 256, 0, st>>>(I.Lc, n, k0, kn);
+        }
+    }
+    k_transpose_sq<<<dim3((n + 31) / 32, (n + 31) / 32), 256, 0, st>>>(I.Lc, n, I.Lt);
+    int h = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(err);
+    if (e != hipSuccess) {
+        g_last_hip = hipGetErrorString(e);
+        return SSCS_E_HIP;
+    }
+    if (h) {
+        g_last_hip = "the Cholesky factor of I + A^T A met a non-positive pivot";
+        return SSCS_E_DEVICE;
+    }
+    return SSCS_OK;
+}
+
 int setup_linear(sscs_work* w) {
     // g = M^{-1} (c, b) and delta = 1 + (c, b)^T g, solved tightly once
     double* h = w->io;
@@ -1283,12 +1479,14 @@ int sscs_default_settings(sscs_settings* st) {
     st->cg_d_match = 1;
     st->check_every = 1;
     st->workgroups = 0;
+    st->linsys = SSCS_LINSYS_CG;
     return SSCS_OK;
 }
 
 int sscs_create(const sscs_data* data, const sscs_cone* cone, const sscs_settings* st, void* hip_stream,
                 sscs_work** out) {
     try {
+        g_unsupported = nullptr;
         if (!out) return SSCS_E_INVALID;
         *out = nullptr;
         TRY(validate(data, cone));
@@ -1302,6 +1500,7 @@ int sscs_create(const sscs_data* data, const sscs_cone* cone, const sscs_setting
         if (r == SSCS_OK) r = choose_grid(w);
         if (r == SSCS_OK) r = alloc_work_vectors(w);
         if (r == SSCS_OK) r = alloc_trace(w);
+        if (r == SSCS_OK && st->linsys == SSCS_LINSYS_DIRECT) r = build_direct(w);
         if (r == SSCS_OK) r = setup_linear(w);
         if (r != SSCS_OK) { sscs_destroy(w); return r; }
         w->setup_s = now_s() - t0;
@@ -1315,7 +1514,8 @@ int sscs_create(const sscs_data* data, const sscs_cone* cone, const sscs_setting
 int sscs_update_settings(sscs_work* w, const sscs_settings* st) {
     if (!w) return SSCS_E_INVALID;
     TRY(validate_settings(st));
-    if (st->precision != w->st.precision || st->workgroups != w->st.workgroups) return SSCS_E_INVALID;
+    if (st->precision != w->st.precision || st->workgroups != w->st.workgroups || st->linsys != w->st.linsys)
+        return SSCS_E_INVALID;
     const bool retrace = st->record_trace != w->st.record_trace || st->max_iters != w->st.max_iters;
     w->st = *st;
     if (retrace) TRY(alloc_trace(w));
@@ -1533,12 +1733,17 @@ int sscs_batch_destroy(sscs_batch* bt) {
 int sscs_batch_create(int32_t count, const sscs_data* data, const sscs_cone* cones, const sscs_settings* st,
                       void* hip_stream, sscs_batch** out) {
     try {
+        g_unsupported = nullptr;
         if (!out || count < 1 || !data || !cones) return SSCS_E_INVALID;
         *out = nullptr;
         TRY(validate_settings(st));
         // the batched engine runs the FP64 operator only: its mixed-precision
         // form ran without finishing in a test whose cause has not been shown
         if (st->precision != SSCS_PREC_FP64) return SSCS_E_UNSUPPORTED;
+        if (st->linsys != SSCS_LINSYS_CG) {
+            g_unsupported = "batches run the CG linear step only";
+            return SSCS_E_UNSUPPORTED;
+        }
         for (int i = 0; i < count; ++i) {
             const bool shared = i > 0 && data[i].rowptr == data[0].rowptr && data[i].colind == data[0].colind &&
                                 data[i].val == data[0].val && data[i].m == data[0].m && data[i].n == data[0].n &&
@@ -1816,6 +2021,10 @@ int sscs_solve_noalloc(const sscs_data* data, const sscs_cone* cone, const sscs_
         TRY(validate_settings(st));
         if (st->precision != SSCS_PREC_FP64) {                      // as the batched engine
             g_unsupported = "sscs_solve_noalloc runs the FP64 operator only";
+            return SSCS_E_UNSUPPORTED;
+        }
+        if (st->linsys != SSCS_LINSYS_CG) {
+            g_unsupported = "sscs_solve_noalloc runs the CG linear step only";
             return SSCS_E_UNSUPPORTED;
         }
         int kmax = 0;

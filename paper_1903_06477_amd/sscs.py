@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsscs.so"
 SOLVED, INFEASIBLE, UNBOUNDED, MAX_ITERS, TIME_LIMIT, NUMERICAL = 1, 2, 3, 4, 5, 6
 STATUS_NAMES = {1: "solved", 2: "infeasible", 3: "unbounded", 4: "max_iters", 5: "time_limit",
                 6: "numerical"}
+LINSYS = {"cg": 0, "direct": 1}
 DIRECTIONS = {"rb": 0, "aa": 1, "residual": 2, "none": 2, "zero": 3, "scs": 4, "aa_qr": 5}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 
@@ -45,7 +46,7 @@ class _Settings(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double), ("cg_max", ctypes.c_int32),
                 ("data_on_device", ctypes.c_int32), ("record_trace", ctypes.c_int32),
                 ("aa_reg", ctypes.c_double), ("cg_adapt", ctypes.c_double), ("cg_d_match", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("workgroups", ctypes.c_int32), ("linsys", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -136,6 +137,7 @@ class Settings:
     cg_d_match: bool = True
     check_every: int = 1
     workgroups: int = 0
+    linsys: str = "cg"             # "cg" (iterative) or "direct" (dense Cholesky of I + A^T A)
 
     def to_c(self) -> _Settings:
         st = _Settings()
@@ -157,6 +159,7 @@ class Settings:
         st.cg_d_match = int(self.cg_d_match)
         st.check_every = int(self.check_every)
         st.workgroups = int(self.workgroups)
+        st.linsys = LINSYS[self.linsys]
         return st
 
 

@@ -89,6 +89,13 @@ def test_create_rejects_bad_input_before_touching_the_device():
         sscs.Solver(bad2)
     with pytest.raises(sscs.SSCSError, match="invalid"):
         sscs.Solver(Problem(A=A, b=np.ones(3), c=np.ones(2), cone=Cone(l=3)), sscs.Settings(mem=0))
+    st = sscs.Settings()
+    c = st.to_c()
+    c.linsys = 7                                                             # no such linear step
+    h = ctypes.c_void_p()
+    mm = sscs._Marshal(A, np.ones(3), np.ones(2), Cone(l=3))
+    assert sscs.lib().sscs_create(ctypes.byref(mm.data), ctypes.byref(mm.cone), ctypes.byref(c), None,
+                                  ctypes.byref(h)) == -1
 
 
 def test_noalloc_rejects_instances_beyond_its_scratch():
@@ -102,3 +109,5 @@ def test_noalloc_rejects_instances_beyond_its_scratch():
     bad = G.config1_lp()
     with pytest.raises(sscs.SSCSError, match="unsupported"):
         sscs.solve_noalloc(bad, sscs.Settings(precision="mixed"))
+    with pytest.raises(sscs.SSCSError, match="unsupported"):
+        sscs.solve_noalloc(bad, sscs.Settings(linsys="direct"))

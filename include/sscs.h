@@ -74,10 +74,11 @@ extern "C" {
 /* Linear step (I + Q)^{-1} (Sec. IV-A): the reduced system I + A^T A of the
  * HSDE solved iteratively or directly. */
 #define SSCS_LINSYS_CG       0   /* conjugate gradients, Jacobi preconditioned, warm-started */
-#define SSCS_LINSYS_DIRECT   1   /* dense Cholesky factor L L^T = I + A^T A formed and factored
-                                    once on the device at create (n <= SSCS_DIRECT_NMAX, FP64,
-                                    single-instance solves on one workgroup); each linear step
-                                    is a forward and a backward substitution with it */
+#define SSCS_LINSYS_DIRECT   1   /* I + A^T A formed and factored (dense Cholesky L L^T) once
+                                    on the device at create, and its inverse L^{-T} L^{-1}
+                                    formed from the factor (n <= SSCS_DIRECT_NMAX, FP64,
+                                    single instances); each linear step is then one dense
+                                    product with it */
 #define SSCS_DIRECT_NMAX  4096
 
 #define SSCS_PREC_FP64       0   /* FP64 everywhere */

@@ -36,12 +36,9 @@ struct Prob {
     const int* partA;       // row partition of A over the workgroups of a grid (G + 1)
     const int* partAt;      // row partition of A^T
     int lds_cache;          // grid kernels keep their rows of A and A^T in LDS
-    // direct linear step: L L^T = I + A^T A (column-major L and L^T, n x n) and
-    // the inverses of L's diagonal blocks of order DIRECT_B (row-major, the
-    // last block padded with the identity); null for the CG
-    const double* Lc;
-    const double* Lt;
-    const double* Linv;
+    // direct linear step: (I + A^T A)^{-1}, n x n and symmetric (row j is
+    // contiguous); null for the CG
+    const double* Minv;
     double delta;           // 1 + (c, b)^T g
     double nb, nc;          // ||b||, ||c||
     ConeDev K;
@@ -275,92 +272,44 @@ __device__ int solve_M_staged(Team& tm, Shared& sh, const Prob& P, const Vecs& V
 
 // Out of line: the CG loop then gets a register allocation of its own,
 // independent of the rest of the solve kernel it is called from.
-// Direct form of solve_M (Sec. IV-A, the reduced system solved by its
-// factor): rhs = r_x - A^T r_y, then L z = rhs by blocks of DIRECT_B (each
-// block's unknowns by the stored inverse of L's diagonal block, then the
-// rows below updated column block by column block, reading L column-major so
-// the threads' loads coalesce), then L^T x = z from the last block back in the
-// same way, then (x, r_y + A x) and h^T p.  For one workgroup (the host runs
-// instances with a factor on one).  xw and q are set to x and K x = rhs, so
-// the CG's bookkeeping stays consistent.  Returns 0 (no CG iterations).
-constexpr int DIRECT_B = 64;
-
-// sum_k col[k * ld] blk[k] over k < kn: four partial sums and an unrolled loop
-// keep many of the strided loads in flight at once.
-__device__ __forceinline__ double direct_dot(const double* col, int ld, const double* blk, int kn) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = 0;
-    if (kn == DIRECT_B) {
-#pragma unroll
-        for (; k < DIRECT_B; k += 4) {
-            s0 += col[(size_t)k * ld] * blk[k];
-            s1 += col[(size_t)(k + 1) * ld] * blk[k + 1];
-            s2 += col[(size_t)(k + 2) * ld] * blk[k + 2];
-            s3 += col[(size_t)(k + 3) * ld] * blk[k + 3];
-        }
-    } else {
-        for (; k < kn; ++k) s0 += col[(size_t)k * ld] * blk[k];
-    }
-    return (s0 + s1) + (s2 + s3);
-}
-
+// Direct form of solve_M (Sec. IV-A, the reduced system solved directly):
+// rhs = r_x - A^T r_y, then x = M^{-1} rhs with the inverse formed once from
+// the Cholesky factor (a dense symmetric product: one wavefront per row,
+// coalesced, over the whole team, so the step is bound by reading M^{-1}
+// rather than by the substitutions' chain of dependent blocks), then
+// (x, r_y + A x) and h^T p.  xw and q are set to x and K x = rhs, so the
+// CG's bookkeeping stays consistent.  Returns 0 (no CG iterations).
 template <typename Team>
 __device__ __noinline__ int solve_direct(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r,
                                          double* out, double* xw, double* q) {
     const int n = P.n;
-    const int nb = (n + DIRECT_B - 1) / DIRECT_B;
-    double* zb = V.cg_b;                       // rhs, then z, then x in place
-    double* rh = V.cg_r;                       // the rhs kept for q
-    __shared__ double blk[DIRECT_B];
-    spmv_part<1>(tm, P.At, 1, [&](int c_) { return r[n + c_]; }, [&](int j, double s) {
-        const double bj = r[j] - s;
-        zb[j] = bj;
-        rh[j] = bj;
-    });
+    double* rh = V.cg_b;
+    double* xs = V.cg_r;
+    spmv_part<1>(tm, P.At, 1, [&](int c_) { return r[n + c_]; }, [&](int j, double s) { rh[j] = r[j] - s; });
     tm.sync();
-    const int t = threadIdx.x, nt = blockDim.x;
-    // forward: L z = rhs
-    for (int b = 0; b < nb; ++b) {
-        const int k0 = b * DIRECT_B, kn = min(DIRECT_B, n - k0);
-        if (t < DIRECT_B) blk[t] = t < kn ? zb[k0 + t] : 0.0;
-        __syncthreads();
-        const double* Li = P.Linv + (size_t)b * DIRECT_B * DIRECT_B;
-        if (t < kn) zb[k0 + t] = direct_dot(Li + t * DIRECT_B, 1, blk, DIRECT_B);   // L_bb^{-1} is zero above
-        __syncthreads();
-        if (t < DIRECT_B) blk[t] = t < kn ? zb[k0 + t] : 0.0;
-        __syncthreads();
-        for (int i = k0 + kn + t; i < n; i += nt) {
-            const double* col = P.Lc + (size_t)k0 * n + i;
-            zb[i] -= direct_dot(col, n, blk, kn);
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (int j = tm.wave(); j < n; j += tm.nwaves()) {
+        const double* row = P.Minv + (size_t)j * n;
+        double a0 = 0.0, a1 = 0.0;
+        int k = lane;
+        for (; k + WAVE < n; k += 2 * WAVE) {
+            a0 += row[k] * rh[k];
+            a1 += row[k + WAVE] * rh[k + WAVE];
         }
-        __syncthreads();
-    }
-    // backward: L^T x = z
-    for (int b = nb - 1; b >= 0; --b) {
-        const int k0 = b * DIRECT_B, kn = min(DIRECT_B, n - k0);
-        if (t < DIRECT_B) blk[t] = t < kn ? zb[k0 + t] : 0.0;
-        __syncthreads();
-        const double* Li = P.Linv + (size_t)b * DIRECT_B * DIRECT_B;
-        if (t < kn) zb[k0 + t] = direct_dot(Li + t, DIRECT_B, blk, DIRECT_B);   // (L_bb^{-1})^T, zero below
-        __syncthreads();
-        if (t < DIRECT_B) blk[t] = t < kn ? zb[k0 + t] : 0.0;
-        __syncthreads();
-        for (int i = t; i < k0; i += nt) {
-            const double* col = P.Lt + (size_t)k0 * n + i;
-            zb[i] -= direct_dot(col, n, blk, kn);
-        }
-        __syncthreads();
+        if (k < n) a0 += row[k] * rh[k];
+        const double x = group_sum(a0 + a1, WAVE);
+        if (lane == WAVE - 1) xs[j] = x;
     }
     tm.sync();
     // py = ry + A x ; h^T p
     double a_hp = 0.0;
-    spmv_part<1>(tm, P.A, 0, [&](int c_) { return zb[c_]; }, [&](int i, double s) {
+    spmv_part<1>(tm, P.A, 0, [&](int c_) { return xs[c_]; }, [&](int i, double s) {
         const double py = r[n + i] + s;
         out[n + i] = py;
         a_hp += P.b[i] * py;
     });
     for (int j = tm.rank(); j < n; j += tm.size()) {
-        const double xj = zb[j];
+        const double xj = xs[j];
         out[j] = xj;
         a_hp += P.c[j] * xj;
         xw[j] = xj;
@@ -375,7 +324,7 @@ template <typename TV, typename Team>
 __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr,
                        double* q = nullptr, bool refresh = true) {
-    if (P.Lc) return solve_direct(tm, sh, P, V, r, out, xw, q);
+    if (P.Minv) return solve_direct(tm, sh, P, V, r, out, xw, q);
     if constexpr (Team::kBlock) {
         if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used, q, refresh);
     }

@@ -295,6 +295,8 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
 // inverted) by one workgroup in LDS, the panel below it by triangular solves
 // against that inverse, the trailing lower triangle updated tile by tile.
 
+constexpr int DIRECT_B = 64;    // block order of the factorisation
+
 // M = I + A^T A: entry (i, j) is 1[i = j] + <A e_i, A e_j>, the sorted rows i and
 // j of A^T merged; one thread per entry of the lower triangle, both halves written.
 __global__ void k_form_normal(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
@@ -417,21 +419,72 @@ __global__ void __launch_bounds__(256) k_chol_update(double* __restrict__ M, int
     }
 }
 
-// B = A^T for n x n column-major arrays (tiles through LDS).
-__global__ void __launch_bounds__(256) k_transpose_sq(const double* __restrict__ A, int n, double* __restrict__ B) {
-    __shared__ double T[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
-        const int a = e % 32, b = e / 32;
-        const int r = by + a, c = bx + b;
-        T[b][a] = (r < n && c < n) ? A[(size_t)c * n + r] : 0.0;
+// M^{-1} = L^{-T} L^{-1} from the factor, by substitution with the n columns of
+// the identity as right-hand sides (W, column-major, starts as I): forward,
+// for each block b, the rows of b are multiplied by L_bb^{-1} and the rows
+// below lose L[rows, b] times them; backward the same with L^T from the last
+// block up.  Each step is one launch over 64 x 64 tiles of W.
+
+// W[k0 .. k0+kn, c0 .. c0+64] = Li (or Li^T) times itself, one column tile per workgroup.
+__global__ void __launch_bounds__(256) k_inv_apply(double* __restrict__ W, int n, int k0, int kn,
+                                                   const double* __restrict__ Li, int transpose) {
+    __shared__ double B[DIRECT_B][DIRECT_B + 1];
+    __shared__ double I_[DIRECT_B][DIRECT_B + 1];
+    const int c0 = blockIdx.x * DIRECT_B;
+    const int cn = min(DIRECT_B, n - c0);
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, c = e / DIRECT_B;          // row k0 + a, column c0 + c
+        B[a][c] = (a < kn && c < cn) ? W[(size_t)(c0 + c) * n + (k0 + a)] : 0.0;
+        const int r = e / DIRECT_B, q = e % DIRECT_B;
+        I_[r][q] = transpose ? Li[(size_t)q * DIRECT_B + r] : Li[(size_t)r * DIRECT_B + q];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
-        const int a = e % 32, b = e / 32;
-        const int r = bx + a, c = by + b;                 // B[r, c] = A[c, r]
-        if (r < n && c < n) B[(size_t)c * n + r] = T[a][b];
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, c = e / DIRECT_B;
+        if (a >= kn || c >= cn) continue;
+        double s = 0.0;
+        for (int k = 0; k < kn; ++k) s += I_[a][k] * B[k][c];
+        W[(size_t)(c0 + c) * n + (k0 + a)] = s;
     }
+}
+
+// W[i, c] -= sum_k F[i, k0 + k] W[k0 + k, c] for the row tile of this
+// workgroup (blockIdx.y) and column tile (blockIdx.x); F = L (forward, rows
+// below the block) or L^T (backward, rows above it), L column-major in Lc.
+__global__ void __launch_bounds__(256) k_inv_update(double* __restrict__ W, const double* __restrict__ Lc, int n,
+                                                    int k0, int kn, int forward) {
+    __shared__ double F[DIRECT_B][DIRECT_B + 1];
+    __shared__ double B[DIRECT_B][DIRECT_B + 1];
+    const int base = forward ? k0 + kn : 0;
+    const int lim = forward ? n : k0;
+    const int i0 = base + blockIdx.y * DIRECT_B, c0 = blockIdx.x * DIRECT_B;
+    const int in_ = min(DIRECT_B, lim - i0), cn = min(DIRECT_B, n - c0);
+    if (in_ <= 0 || cn <= 0) return;
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, k = e / DIRECT_B;
+        double f = 0.0;
+        if (a < in_ && k < kn)
+            f = forward ? Lc[(size_t)(k0 + k) * n + (i0 + a)]      // L[i, k0 + k]
+                        : Lc[(size_t)(i0 + a) * n + (k0 + k)];     // L^T[i, k0 + k] = L[k0 + k, i]
+        F[a][k] = f;
+        B[a][k] = (a < kn && k < cn) ? W[(size_t)(c0 + k) * n + (k0 + a)] : 0.0;   // B[row k0 + a][col c0 + k]
+    }
+    __syncthreads();
+    for (int e = t; e < DIRECT_B * DIRECT_B; e += nt) {
+        const int a = e % DIRECT_B, c = e / DIRECT_B;
+        if (a >= in_ || c >= cn) continue;
+        double s = 0.0;
+        for (int k = 0; k < kn; ++k) s += F[a][k] * B[k][c];
+        W[(size_t)(c0 + c) * n + (i0 + a)] -= s;
+    }
+}
+
+__global__ void k_identity(double* __restrict__ W, int n) {
+    const long long nn = (long long)n * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x)
+        W[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, long long n, float* __restrict__ b) {
@@ -725,7 +778,7 @@ struct Inst {
     std::vector<int> h_rpA, h_rpAt;        // host row pointers (partitioning)
     int *partA = nullptr, *partAt = nullptr;
     int lds_bytes = 0;                     // dynamic LDS of the grid kernels (0: operator in HBM)
-    double *Lc = nullptr, *Lt = nullptr, *Linv = nullptr;   // direct linear step (factor of I + A^T A)
+    double *Minv = nullptr;                // direct linear step: (I + A^T A)^{-1}, n x n
 };
 
 // The small kernel's plan for an FP64 instance: mask of what goes to LDS (see
@@ -987,7 +1040,7 @@ void free_instance(Inst& I) {
     hipFree(I.K.psd_team);
     hipFree(I.K.psd_warm);
     hipFree(I.partA); hipFree(I.partAt);
-    hipFree(I.Lc); hipFree(I.Lt); hipFree(I.Linv);
+    hipFree(I.Minv);
     I = Inst{};
 }
 
@@ -1002,7 +1055,7 @@ Prob make_prob(const Inst& I) {
     P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.lds_bytes > 0 ? 1 : 0;
     P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
     P.K = I.K;
-    P.Lc = I.Lc; P.Lt = I.Lt; P.Linv = I.Linv;
+    P.Minv = I.Minv;
     return P;
 }
 
@@ -1282,7 +1335,6 @@ int choose_grid(sscs_work* w) {
     w->grid = (int)std::max<long long>(1, std::min<long long>(want, w->max_grid));
     if (small_fits(w->I, w->st)) w->grid = 1;     // one workgroup with its working set in LDS
     if (w->st.workgroups >= 1) w->grid = std::min(w->st.workgroups, w->max_grid);
-    if (w->st.linsys == SSCS_LINSYS_DIRECT) w->grid = 1;   // the substitutions run in one workgroup
     int rate_khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
     w->ticks_per_s = rate_khz > 0 ? rate_khz * 1000.0 : 1e8;
@@ -1360,8 +1412,10 @@ int alloc_work_vectors(sscs_work* w) {
     return SSCS_OK;
 }
 
-// The factor of the direct linear step, on the device: M = I + A^T A formed
-// from the rows of A^T, then the blocked Cholesky in place, then L^T.
+// The direct linear step's operator, on the device: M = I + A^T A formed
+// from the rows of A^T, its blocked Cholesky factor in place, then
+// M^{-1} = L^{-T} L^{-1} by substitution with the identity; the factor is
+// freed once the inverse is formed.
 int build_direct(sscs_work* w) {
     Inst& I = w->I;
     const int n = I.n;
@@ -1371,30 +1425,46 @@ int build_direct(sscs_work* w) {
         return SSCS_E_UNSUPPORTED;
     }
     const int nb = (n + DIRECT_B - 1) / DIRECT_B;
-    TRY(dmalloc(&I.Lc, (size_t)n * n));
-    TRY(dmalloc(&I.Lt, (size_t)n * n));
-    TRY(dmalloc(&I.Linv, (size_t)nb * DIRECT_B * DIRECT_B));
+    double *Lc = nullptr, *Li = nullptr;
     int* err = nullptr;
-    TRY(dmalloc(&err, 1));
+    int r = dmalloc(&Lc, (size_t)n * n);
+    if (r == SSCS_OK) r = dmalloc(&Li, (size_t)nb * DIRECT_B * DIRECT_B);
+    if (r == SSCS_OK) r = dmalloc(&I.Minv, (size_t)n * n);
+    if (r == SSCS_OK) r = dmalloc(&err, 1);
+    auto release = [&] { hipFree(Lc); hipFree(Li); hipFree(err); };
+    if (r != SSCS_OK) { release(); return r; }
     const hipStream_t st = w->stream;
-    HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
-    k_form_normal<<<dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, st>>>(I.At_rp, I.At_ci, I.At_v, n, I.Lc);
+    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), st);
+    k_form_normal<<<dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, st>>>(I.At_rp, I.At_ci, I.At_v, n, Lc);
     for (int b = 0; b < nb; ++b) {
         const int k0 = b * DIRECT_B, kn = std::min(DIRECT_B, n - k0);
-        k_chol_diag<<<1, 256, 0, st>>>(I.Lc, n, k0, kn, I.Linv + (size_t)b * DIRECT_B * DIRECT_B, err);
+        double* Lib = Li + (size_t)b * DIRECT_B * DIRECT_B;
+        k_chol_diag<<<1, 256, 0, st>>>(Lc, n, k0, kn, Lib, err);
         const int rest = n - k0 - kn;
         if (rest > 0) {
             const int nt = (rest + DIRECT_B - 1) / DIRECT_B;
-            k_chol_panel<<<nt, 256, 0, st>>>(I.Lc, n, k0, kn, I.Linv + (size_t)b * DIRECT_B * DIRECT_B);
-            k_chol_update<<<dim3(nt, nt), 256, 0, st>>>(I.Lc, n, k0, kn);
+            k_chol_panel<<<nt, 256, 0, st>>>(Lc, n, k0, kn, Lib);
+            k_chol_update<<<dim3(nt, nt), 256, 0, st>>>(Lc, n, k0, kn);
         }
     }
-    k_transpose_sq<<<dim3((n + 31) / 32, (n + 31) / 32), 256, 0, st>>>(I.Lc, n, I.Lt);
+    double* W = I.Minv;
+    k_identity<<<1024, 256, 0, st>>>(W, n);
+    for (int b = 0; b < nb; ++b) {                                   // L Y = I
+        const int k0 = b * DIRECT_B, kn = std::min(DIRECT_B, n - k0);
+        k_inv_apply<<<nb, 256, 0, st>>>(W, n, k0, kn, Li + (size_t)b * DIRECT_B * DIRECT_B, 0);
+        const int rest = n - k0 - kn;
+        if (rest > 0) k_inv_update<<<dim3(nb, (rest + DIRECT_B - 1) / DIRECT_B), 256, 0, st>>>(W, Lc, n, k0, kn, 1);
+    }
+    for (int b = nb - 1; b >= 0; --b) {                              // L^T X = Y
+        const int k0 = b * DIRECT_B, kn = std::min(DIRECT_B, n - k0);
+        k_inv_apply<<<nb, 256, 0, st>>>(W, n, k0, kn, Li + (size_t)b * DIRECT_B * DIRECT_B, 1);
+        if (k0 > 0) k_inv_update<<<dim3(nb, (k0 + DIRECT_B - 1) / DIRECT_B), 256, 0, st>>>(W, Lc, n, k0, kn, 0);
+    }
     int h = 0;
-    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(err);
+    release();
     if (e != hipSuccess) {
         g_last_hip = hipGetErrorString(e);
         return SSCS_E_HIP;

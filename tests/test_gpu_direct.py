@@ -1,5 +1,6 @@
-"""The direct linear step (dense Cholesky of I + A^T A, factored on the device)
-against the oracle's direct solve (Sec. IV-A).
+"""The direct linear step (I + A^T A factored by a dense Cholesky on the device,
+its inverse formed from the factor, one dense product per step) against the
+oracle's direct solve (Sec. IV-A).
 
 Parity: (I + Q)^{-1} r within 1e-12 relative (both sides direct; I + A^T A is
 well conditioned on these instances, so the bar is a small multiple of the

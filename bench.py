@@ -339,8 +339,9 @@ def host_kkt(p, x, y, s):
 def config1_leg(sscs, G, reps=20, batch=1024):
     """The LP workload (300 x 100, 10% density, planted optimum, RB memory 10,
     eps 1e-6): one instance solved `reps` times on the one-workgroup kernel
-    (latency: microseconds per iteration), and `batch` seeded instances of the
-    same family in one batched launch (throughput)."""
+    (latency: microseconds per iteration), with the CG and with the direct
+    linear step, and `batch` seeded instances of the same family in one
+    batched launch (throughput)."""
     import torch
     p = G.config1_lp()
     st = sscs.Settings(direction="rb", mem=10, eps=1e-6, cg_tol=1e-12, cg_adapt=0.2, cg_max=500,
@@ -358,6 +359,18 @@ def config1_leg(sscs, G, reps=20, batch=1024):
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / reps
     pr, dr, gap = host_kkt(p, x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy())
+    # the same single solve with the direct linear step
+    std = sscs.Settings(direction="rb", mem=10, eps=1e-6, max_iters=20000, data_on_device=True, linsys="direct")
+    with sscs.Solver(p, std) as s:
+        s.solve(out=(x, y, sv))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            info_d = s.solve(out=(x, y, sv))[3]
+        torch.cuda.synchronize()
+        wall_d = (time.perf_counter() - t0) / reps
+    prd, drd, gapd = host_kkt(p, x.cpu().numpy(), y.cpu().numpy(), sv.cpu().numpy())
+    ok_d = info_d["status"] == sscs.SOLVED and max(prd, drd, gapd) <= 1e-6 * 1.0001
     probs = [G.config1_lp(i) for i in range(batch)]
     bs = sscs.BatchSolver(probs, st)
     out = (torch.empty(batch * p.n, dtype=torch.float64, device=dev),
@@ -375,6 +388,9 @@ def config1_leg(sscs, G, reps=20, batch=1024):
     return {"workload": "LP 300 x 100 at 10%, K = R+^300, planted optimum, RB memory 10, eps 1e-6",
             "solves_per_s": 1.0 / wall if info["status"] == sscs.SOLVED else 0.0, "iters": info["iters"],
             "us_per_iteration": wall * 1e6 / max(1, info["iters"]), "pr_host": pr, "dr_host": dr, "gap_host": gap,
+            "direct_linear_step": {"solves_per_s": 1.0 / wall_d if ok_d else 0.0, "iters": info_d["iters"],
+                                   "us_per_iteration": wall_d * 1e6 / max(1, info_d["iters"]),
+                                   "pr_host": prd, "dr_host": drd, "gap_host": gapd},
             "batched": {"instances": batch, "solves_per_s": int(np.sum(solved)) / bwall,
                         "solved_frac": float(np.mean(solved)),
                         "unsolved": [{"instance": k, "status": infos[k]["status_name"], "iters": infos[k]["iters"]}

@@ -49,6 +49,7 @@ struct Vecs {
     double *xw_u, *xw_d;                                 // CG warm starts, length n
     double *q_u, *q_d;                                   // K xw_u, K xw_d as the CG left them, length n
     double *cg_b, *cg_u, *cg_w, *cg_p, *cg_r, *cg_s;     // length n
+    double* rhs_u;                                       // the u~ solve's right-hand side (grid teams), length n
     double *cg_g[2];                                     // 4 n each: gathered (D r, D s, D w, -) per column
     double *cg_t;                                        // length m
     double *Zb, *Yb;                                     // mem x N memory buffers
@@ -323,7 +324,8 @@ __device__ __noinline__ int solve_direct(Team& tm, Shared& sh, const Prob& P, co
 template <typename TV, typename Team>
 __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr,
-                       double* q = nullptr, bool refresh = true) {
+                       double* q = nullptr, bool refresh = true, double* rb = nullptr, bool prestarted = false,
+                       double bb_part = 0.0) {
     if (P.Minv) return solve_direct(tm, sh, P, V, r, out, xw, q);
     if constexpr (Team::kBlock) {
         if (tm.lu) return solve_M_staged<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used, q, refresh);
@@ -362,14 +364,19 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
         g[1] = 0.0;
         g[2] = 0.0;
     };
-    // rhs = rx - A^T ry
-    double a_bb = 0.0;
-    spmv_part<1>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; }, [&](int j, double s) {
-        const double bj = r[j] - s;
-        V.cg_b[j] = bj;
-        a_bb += bj * bj;
-        if (use_q) start(j, bj - q[j]);
-    });
+    // rhs = rx - A^T ry, into rb (default the CG's own buffer).  prestarted:
+    // the caller has already formed the rhs in rb and, with use_q, started
+    // the CG from it (r0 = rhs - q, as start() below) in a pass that ended
+    // with a team barrier; bb_part is this thread's part of ||rhs||^2.
+    double* const B = rb ? rb : V.cg_b;
+    double a_bb = bb_part;
+    if (!prestarted)
+        spmv_part<1>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; }, [&](int j, double s) {
+            const double bj = r[j] - s;
+            B[j] = bj;
+            a_bb += bj * bj;
+            if (use_q) start(j, bj - q[j]);
+        });
     double thr = 0.0;
     int it = 0;
     const int rounds = cg_rounds<TV>();
@@ -379,9 +386,9 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
             spmv_part<1>(tm, P.A, 0, [&](int c_) { return (xw)[c_]; }, [&](int i, double s) { V.cg_t[i] = s; });
             tm.sync();
             spmv_part<1>(tm, P.At, 1, [&](int c_) { return (V.cg_t)[c_]; },
-                         [&](int j, double s) { start(j, V.cg_b[j] - (xw[j] + s)); });
+                         [&](int j, double s) { start(j, B[j] - (xw[j] + s)); });
         }
-        tm.sync();
+        if (!(prestarted && use_q && round == 0)) tm.sync();
         double alpha = 0.0, beta = 0.0, gamma_old = 1.0, alpha_old = 1.0;
         bool done = false;
         for (int pass = 0;; ++pass) {
@@ -513,7 +520,7 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
         }
         out[j] = xj;
         a_hp += P.c[j] * xj;
-        if (q) q[j] = V.cg_b[j] - rj;
+        if (q) q[j] = B[j] - rj;
     }
     put(sh, 0, a_hp);
     tm.reduce(sh, 1);
@@ -527,8 +534,10 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
 template <typename TV, typename Team>
 __device__ double linear_step(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                               double* xw, double tol, int maxit, long long* cg_iters, double thr_abs = 0.0,
-                              double* thr_used = nullptr, double* q = nullptr, bool refresh = true) {
-    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used, q, refresh);
+                              double* thr_used = nullptr, double* q = nullptr, bool refresh = true,
+                              double* rb = nullptr, bool prestarted = false, double bb_part = 0.0) {
+    *cg_iters += solve_M<TV>(tm, sh, P, V, r, out, xw, tol, maxit, thr_abs, thr_used, q, refresh, rb, prestarted,
+                             bb_part);
     return (r[P.N - 1] + sh.out[0]) / P.delta;
 }
 
@@ -1244,10 +1253,21 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
     long long nu = 0;
     double tol = S.cg_adapt > 0.0 ? 1e-6 : S.cg_tol;
     double thr_u = 0.0;                                // the u step's CG threshold (absolute)
+    // After a K1 step u+ = u + a d, the next u~ solve's right-hand side is
+    // rhs_u + a rhs_d by linearity (the one of Sec. IV-B), and its CG starts
+    // from x_u + a x_d with r0 = rhs - q: both are formed in the step's own
+    // pass, so that solve needs neither the product with A^T nor its barrier
+    // (grid teams, FP64 operator, iterative linear step).
+    constexpr bool kPre = !Team::kBlock && std::is_same<TV, double>::value;
+    const bool pre_ok = kPre && P.Minv == nullptr;
+    bool pre = false;            // the next u~ solve is prestarted
+    double bb_part = 0.0;        // this thread's part of that solve's ||rhs||^2
     for (nu = 0;; ++nu) {
         const bool refresh = !(S.cg_adapt > 0.0) || nu % 64 == 0;
         const double tau_u = linear_step<TV>(tm, sh, P, V, V.u, V.ut, V.xw_u, tol, S.cg_max, &cgc, 0.0, &thr_u, qu,
-                                             refresh);
+                                             refresh, pre_ok ? V.rhs_u : nullptr, pre, bb_part);
+        pre = false;
+        bb_part = 0.0;
         nRu = sqrt(residual_pass(tm, sh, P, V, tau_u));
         if (S.cg_adapt > 0.0) {
             // inexact linear steps: accuracy relative to the current fixed-point residual
@@ -1349,10 +1369,31 @@ __device__ void solve(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const 
             // the next linear step solves for u + a d: by linearity (the same
             // property the line search uses, Sec. IV-B) its CG starts from the
             // sum of the two solutions already at hand
+            const bool use_q = S.cg_adapt > 0.0 && (nu + 1) % 64 != 0;   // the next solve's refresh rule
             for (int j = tm.rank(); j < n; j += tm.size()) {
                 V.xw_u[j] += a * V.xw_d[j];
-                qu[j] += a * qd[j];
+                const double qj = qu[j] + a * qd[j];
+                qu[j] = qj;
+                if (pre_ok) {
+                    // rhs_d is in the CG's buffer (d~ was the last solve)
+                    const double bj = V.rhs_u[j] + a * V.cg_b[j];
+                    V.rhs_u[j] = bj;
+                    bb_part += bj * bj;
+                    if (use_q) {                       // start(j, bj - q_j) of solve_M
+                        const double rj = bj - qj;
+                        V.cg_r[j] = rj;
+                        V.cg_s[j] = 0.0;
+                        V.cg_u[j] = 0.0;
+                        V.cg_w[j] = 0.0;
+                        V.cg_p[j] = 0.0;
+                        double* g = V.cg_g[0] + 4 * (size_t)j;
+                        g[0] = P.dinv[j] * rj;
+                        g[1] = 0.0;
+                        g[2] = 0.0;
+                    }
+                }
             }
+            pre = pre_ok;
             ds.pend = 1;
             ++k1c;
         } else if (kind == 2) {

@@ -1061,7 +1061,7 @@ Prob make_prob(const Inst& I) {
 
 size_t vec_doubles(int n, int m, int mem) {
     const size_t N = (size_t)n + m + 1;
-    return 9 * N + 18 * (size_t)n + (size_t)m + 3 * (size_t)mem * N + 8;
+    return 9 * N + 19 * (size_t)n + (size_t)m + 3 * (size_t)mem * N + 8;
 }
 
 // Carves the Vecs of one instance from a contiguous device buffer.
@@ -1075,7 +1075,7 @@ Vecs carve(double* base, int n, int m, int mem) {
     V.xw_u = take(n); V.xw_d = take(n);
     V.q_u = take(n); V.q_d = take(n);
     V.cg_b = take(n); V.cg_u = take(n); V.cg_w = take(n); V.cg_p = take(n);
-    V.cg_r = take(n); V.cg_s = take(n);
+    V.cg_r = take(n); V.cg_s = take(n); V.rhs_u = take(n);
     p = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(p) + 31) & ~uintptr_t(31));   // 32-byte records
     V.cg_g[0] = take(4 * (size_t)n); V.cg_g[1] = take(4 * (size_t)n);
     V.cg_t = take(m);

@@ -53,15 +53,17 @@ def cg_op_bytes(nnz, m, n, bval=8):
 
 
 def op_units(info):
-    """CG-operator equivalents one solve launch processes: every CG iteration
-    is one; every linear step adds two (the right-hand side A^T r_y with the
-    y-part product A x, and the first CG pass's product K u0; the start
-    r0 = rhs - K xw costs no product, and its recomputation from scratch every
-    64th iteration is not counted); every termination check adds one (A x and
-    A^T y)."""
+    """CG-operator equivalents (one product with A and one with A^T) one solve
+    launch processes: every CG iteration is one (the last step of a solve is
+    applied by its closing pass without products); every linear step adds one
+    (the right-hand side's A^T r_y and the closing pass's y-part product A x),
+    less a half for each u~ solve prestarted after a K1 step (its right-hand
+    side comes by linearity); every termination check adds one (A x and
+    A^T y).  The recomputation of r0 from scratch every 64th iteration is not
+    counted."""
     iters = info["iters"] + 1
     linear_steps = iters + (info["iters"] - info["k0"])
-    return info["cg_iters"] + 2 * linear_steps + iters
+    return info["cg_iters"] + linear_steps - 0.5 * info["k1"] + iters
 
 
 def outer_vector_bytes(info, N, mem=5):

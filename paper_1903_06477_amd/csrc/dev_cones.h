@@ -31,6 +31,9 @@ struct ConeDev {
     double* psd_vecs;         // per block: the eigenvectors of its last projection (kmax^2
                               // doubles each), or null: every projection starts cold
     int* psd_warm;            // per block: 1 once psd_vecs holds an orthogonal basis
+    int psd_lds;              // grid teams: bytes of dynamic LDS (at its start) holding the matrix
+                              // and eigenvectors of the blocks projected one per workgroup, 0: none
+    int psd_small;            // the largest order of those blocks (the LDS area holds 2 of its squares)
 };
 
 // ---------------------------------------------------------------- exponential cone
@@ -246,7 +249,9 @@ __device__ __forceinline__ PsdRound& psd_round_lds() {
 // position 0 stays, the others rotate; pair h is (pp[h], qq[h]) with p < q.
 // Fills rotation (cs, sn) from `mat` for pairs with q < k; counts active ones.
 // Called by the threads of one workgroup; ends with a workgroup barrier.
-__device__ __forceinline__ void psd_round_params(int k, int kk, int round, const double* mat, PsdRound& R) {
+template <bool L = false>
+__device__ __forceinline__ void psd_round_params(int k, int kk, int round, const double* mat_, PsdRound& R) {
+    const auto mat = vec_at<L>(mat_);
     if (threadIdx.x == 0) R.nact = 0;
     __syncthreads();
     int act = 0;
@@ -273,28 +278,32 @@ __device__ __forceinline__ void psd_round_params(int k, int kk, int round, const
     __syncthreads();
 }
 
-// One Jacobi round as C = J^T A J written to dst (dst != src): the rotations
-// are disjoint 2 x 2 blocks, so entry block (p1, q1) x (p2, q2) of C depends
-// only on the same block of A and on the two rotations; thread `r` of `nr`
-// takes blocks r, r + nr, ...  Rows p, q of Vt turn with J^T in place.
-__device__ __forceinline__ void psd_round_apply(int k, int np, const PsdRound& R, const double* __restrict__ src,
-                                                double* __restrict__ dst, double* __restrict__ vt, int r, int nr) {
+// One Jacobi round as A <- J^T A J, in place: the rotations are disjoint
+// 2 x 2 blocks, so entry block (p1, q1) x (p2, q2) of the result depends only
+// on the same block of A and on the two rotations, and each thread reads and
+// then overwrites only its own blocks; thread `r` of `nr` takes blocks r,
+// r + nr, ...  Rows p, q of Vt turn with J^T in place.  L: A and Vt in LDS.
+template <bool L = false>
+__device__ __forceinline__ void psd_round_apply(int k, int np, const PsdRound& R, double* mat_, double* vt_, int r,
+                                                int nr) {
+    const auto mat = vec_at<L>(mat_);
+    const auto vt = vec_at<L>(vt_);
     for (int idx = r; idx < np * np; idx += nr) {
         const int h1 = idx / np, h2 = idx - (idx / np) * np;
         const int p1 = R.pp[h1], q1 = R.qq[h1], p2 = R.pp[h2], q2 = R.qq[h2];
         const bool e1 = q1 < k, e2 = q2 < k;          // the dummy index has no row / column
         const double c1 = R.cs[h1], s1 = R.sn[h1], c2 = R.cs[h2], s2 = R.sn[h2];
-        const double app = src[p1 * k + p2];
-        const double apq = e2 ? src[p1 * k + q2] : 0.0;
-        const double aqp = e1 ? src[q1 * k + p2] : 0.0;
-        const double aqq = (e1 && e2) ? src[q1 * k + q2] : 0.0;
+        const double app = mat[p1 * k + p2];
+        const double apq = e2 ? mat[p1 * k + q2] : 0.0;
+        const double aqp = e1 ? mat[q1 * k + p2] : 0.0;
+        const double aqq = (e1 && e2) ? mat[q1 * k + q2] : 0.0;
         // B = J^T A (rows), then C = B J (columns)
         const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
         const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-        dst[p1 * k + p2] = c2 * bpp - s2 * bpq;
-        if (e2) dst[p1 * k + q2] = s2 * bpp + c2 * bpq;
-        if (e1) dst[q1 * k + p2] = c2 * bqp - s2 * bqq;
-        if (e1 && e2) dst[q1 * k + q2] = s2 * bqp + c2 * bqq;
+        mat[p1 * k + p2] = c2 * bpp - s2 * bpq;
+        if (e2) mat[p1 * k + q2] = s2 * bpp + c2 * bpq;
+        if (e1) mat[q1 * k + p2] = c2 * bqp - s2 * bqq;
+        if (e1 && e2) mat[q1 * k + q2] = s2 * bqp + c2 * bqq;
     }
     for (int idx = r; idx < np * k; idx += nr) {
         const int h = idx / k, j = idx - (idx / k) * k;
@@ -310,7 +319,8 @@ __device__ __forceinline__ void psd_round_apply(int k, int np, const PsdRound& R
 // `a`, `vm` and `tmp` hold k*k doubles each, `in` and `outv` the packed
 // block (in is consumed); V0 (k*k, rows are eigenvectors) and *warm persist
 // between calls, or V0 is null.
-template <typename Team>
+// L: a and vm are in LDS (tmp, the packed vectors and V0 are not).
+template <typename Team, bool L = false>
 __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, double* vm, double* tmp, double* in,
                                                double* outv, double* V0, int* warm) {
     const int t = threadIdx.x, nt = blockDim.x;
@@ -357,8 +367,9 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
             {
                 __shared__ double red2[2 * NWMAX];
                 double off = 0.0, tot = 0.0;
+                const auto ml = vec_at<L>(mat);
                 for (int idx = t; idx < k * k; idx += nt) {
-                    const double v = mat[idx] * mat[idx];
+                    const double v = ml[idx] * ml[idx];
                     tot += v;
                     if ((idx / k) != (idx % k)) off += v;
                 }
@@ -377,13 +388,10 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
             if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
             prev = cur;
             for (int round = 0; round < kk - 1; ++round) {
-                psd_round_params(k, kk, round, mat, R);
+                psd_round_params<L>(k, kk, round, mat, R);
                 if (R.nact == 0) continue;                  // uniform: nothing to rotate this round
-                psd_round_apply(k, kk / 2, R, mat, tmp, vm, t, nt);
+                psd_round_apply<L>(k, kk / 2, R, mat, vm, t, nt);
                 __syncthreads();
-                double* sw = mat;
-                mat = tmp;
-                tmp = sw;
             }
         }
     }
@@ -908,6 +916,16 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
         double* tmpm = vm + (size_t)K.psd_kmax * K.psd_kmax;
         double* pin = tmpm + (size_t)K.psd_kmax * K.psd_kmax;
         double* pout = pin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
+        // grid teams: the blocks projected one per workgroup keep their matrix
+        // and eigenvectors in LDS when the launch reserved the area
+        bool lds = false;
+        if constexpr (kGrid) {
+            if (K.psd_lds > 0) {
+                lds = true;
+                a = sscs_dyn_lds;
+                vm = a + (size_t)K.psd_small * K.psd_small;
+            }
+        }
         for (int c = tm.blk(); c < K.ns; c += tm.nblk()) {
             const int k = K.sord[c];
             if (kGrid && k > kPsdTeamOrder) continue;
@@ -915,9 +933,10 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
             const int len = k * (k + 1) / 2;
             for (int e = threadIdx.x; e < len; e += blockDim.x) pin[e] = in(o + e);
             __syncthreads();
-            psd_project_block(tm, k, a, vm, tmpm, pin, pout,
-                              K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
-                              K.psd_warm ? K.psd_warm + c : nullptr);
+            double* V0 = K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr;
+            int* wf = K.psd_warm ? K.psd_warm + c : nullptr;
+            if (lds) psd_project_block<Team, true>(tm, k, a, vm, tmpm, pin, pout, V0, wf);
+            else psd_project_block<Team, false>(tm, k, a, vm, tmpm, pin, pout, V0, wf);
             for (int e = threadIdx.x; e < len; e += blockDim.x) emit(o + e, pout[e]);
             __syncthreads();
         }

@@ -54,7 +54,7 @@ struct OpArgs {
 // and, when the operator fits, keeps them in LDS for the whole launch.
 template <bool LDS, typename TL, bool PT>
 __device__ inline void grid_team_init(GridTeam<LDS, TL, PT>& tm, const Prob& P) {
-    int off = 0;
+    int off = P.K.psd_lds;                   // the PSD blocks' area comes first
     load_part(tm.mp[0], op_mat<TL>(P, 0), P.partA, blockIdx.x, LDS, &off);
     load_part(tm.mp[1], op_mat<TL>(P, 1), P.partAt, blockIdx.x, LDS, &off);
     __syncthreads();
@@ -777,7 +777,9 @@ struct Inst {
     bool owns_A = true;
     std::vector<int> h_rpA, h_rpAt;        // host row pointers (partitioning)
     int *partA = nullptr, *partAt = nullptr;
-    int lds_bytes = 0;                     // dynamic LDS of the grid kernels (0: operator in HBM)
+    int lds_bytes = 0;                     // dynamic LDS of the grid kernels
+    bool op_lds = false;                   // the grid kernels hold their operator rows in LDS
+    int psd_small = 0;                     // largest PSD order projected one block per workgroup
     double *Minv = nullptr;                // direct linear step: (I + A^T A)^{-1}, n x n
 };
 
@@ -1020,6 +1022,8 @@ int upload_instance(Inst& I, const sscs_data* d, const sscs_cone* k, hipStream_t
     I.K.soc0 = h.soc0; I.K.psd0 = h.psd0; I.K.exp0 = h.exp0;
     I.K.psd_scratch = nullptr;
     I.K.psd_kmax = h.kmax;
+    I.psd_small = 0;
+    for (int o : h.sord) if (o <= kPsdTeamOrder) I.psd_small = std::max(I.psd_small, o);
     I.K.psd_vecs = nullptr;
     I.K.psd_warm = nullptr;
     I.K.psd_team = nullptr;
@@ -1052,7 +1056,7 @@ Prob make_prob(const Inst& I) {
     P.Af = Csr<float>{I.A_rp, I.A_ci, I.A_vf, I.m, I.n, I.segA, I.A_long, I.nlongA, I.lthrA};
     P.Atf = Csr<float>{I.At_rp, I.At_ci, I.At_vf, I.n, I.m, I.segAt, I.At_long, I.nlongAt, I.lthrAt};
     P.b = I.b; P.c = I.c; P.dinv = I.dinv; P.g = I.g;
-    P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.lds_bytes > 0 ? 1 : 0;
+    P.partA = I.partA; P.partAt = I.partAt; P.lds_cache = I.op_lds ? 1 : 0;
     P.delta = I.delta; P.nb = I.nb; P.nc = I.nc;
     P.K = I.K;
     P.Minv = I.Minv;
@@ -1272,7 +1276,7 @@ int run_op(sscs_work* w, int op, const double* in, double* out1, double* out2, d
     Prob P = make_prob(w->I);
     OpArgs a{op, in, out1, out2, w->scal, tol, maxit};
     void* args[] = {&P, &w->V, &a, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-    TRY(launch_grid_kernel(w, const_cast<void*>(op_grid_fn(w->I.lds_bytes > 0, w->I)), args));
+    TRY(launch_grid_kernel(w, const_cast<void*>(op_grid_fn(w->I.op_lds, w->I)), args));
     HIP_TRY(hipGetLastError());
     return check_abort(w);
 }
@@ -1359,16 +1363,22 @@ int set_partitions(sscs_work* w, bool try_lds) {
         stat = std::max<long long>(stat, (long long)fa.sharedSizeBytes);
     }
     const long long limit = (long long)lds_max - stat - 256;
+    // the PSD blocks projected one per workgroup get their matrix and
+    // eigenvectors in LDS first (their Jacobi rounds are the projection's
+    // critical path); the operator rows are cached after them if they fit
+    long long psd = ((2ll * I.psd_small * I.psd_small * 8) + 15) & ~15ll;
+    if (psd > limit) psd = 0;
     std::vector<int> pA, pAt;
     long long need = 0;
     const int vb = I.mixed ? 4 : 8;       // bytes per cached value
     for (int attempt = 0; attempt < 2; ++attempt) {
         pA = partition_rows(I.h_rpA, I.m, w->grid);
         pAt = partition_rows(I.h_rpAt, I.n, w->grid);
-        need = 0;
+        need = psd;
         for (int b = 0; b < w->grid; ++b)
-            need = std::max(need, part_lds_bytes(I.h_rpA, pA, b, vb) + part_lds_bytes(I.h_rpAt, pAt, b, vb));
-        I.lds_bytes = 0;
+            need = std::max(need, psd + part_lds_bytes(I.h_rpA, pA, b, vb) + part_lds_bytes(I.h_rpAt, pAt, b, vb));
+        I.lds_bytes = (int)psd;
+        I.op_lds = false;
         if (!try_lds || w->grid < 2 || need > limit) break;
         int o1 = 0, o2 = 0;
         HIP_TRY(hipFuncSetAttribute(solve_grid_fn(true, I), hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
@@ -1376,10 +1386,22 @@ int set_partitions(sscs_work* w, bool try_lds) {
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, solve_grid_fn(true, I), kBlock, (size_t)need));
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, op_grid_fn(true, I), kBlock, (size_t)need));
         const int cap = w->ncu * std::min(o1, o2);
-        if (cap >= w->grid) { I.lds_bytes = (int)need; break; }
+        if (cap >= w->grid) { I.lds_bytes = (int)need; I.op_lds = true; break; }
         if (cap < 2) break;
         w->grid = cap;                        // shrink to a co-resident grid and re-partition
     }
+    if (!I.op_lds && psd > 0) {
+        // the PSD area alone, on the kernels without the operator cache
+        int o1 = 0, o2 = 0;
+        HIP_TRY(hipFuncSetAttribute(solve_grid_fn(false, I), hipFuncAttributeMaxDynamicSharedMemorySize, (int)psd));
+        HIP_TRY(hipFuncSetAttribute(op_grid_fn(false, I), hipFuncAttributeMaxDynamicSharedMemorySize, (int)psd));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, solve_grid_fn(false, I), kBlock, (size_t)psd));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, op_grid_fn(false, I), kBlock, (size_t)psd));
+        if (w->ncu * std::min(o1, o2) < w->grid) psd = 0;     // not co-resident with it: keep the area global
+        I.lds_bytes = (int)psd;
+    }
+    I.K.psd_lds = (int)psd;
+    I.K.psd_small = I.psd_small;
     hipFree(I.partA);
     hipFree(I.partAt);
     TRY(dmalloc(&I.partA, pA.size()));
@@ -1647,7 +1669,7 @@ int sscs_solve(sscs_work* w, const double* u0, double* x, double* y, double* s, 
             k_solve_block<double><<<1, kBatchBlock, sd * sizeof(double), w->stream>>>(P, V, S, w->res, sd);
     } else {
         void* args[] = {&P, &V, &S, &w->res, &w->bar, &w->abort_flag, &w->part, &w->timeout_ticks};
-        TRY(launch_grid_kernel(w, const_cast<void*>(solve_grid_fn(w->I.lds_bytes > 0, w->I)), args));
+        TRY(launch_grid_kernel(w, const_cast<void*>(solve_grid_fn(w->I.op_lds, w->I)), args));
     }
     HIP_TRY(hipGetLastError());
     TRY(stage_out(w, x, V.out_x, n));

@@ -232,6 +232,30 @@ __device__ __forceinline__ void psd_transpose(int k, const double* __restrict__ 
     __syncthreads();
 }
 
+// Rotation (c, s) of a Jacobi step that zeroes apq in the symmetric 2 x 2
+// block [app apq; apq aqq]: the smaller of the two angles, t = tan = sign(d)
+// e / (|d| + sqrt(d^2 + e^2)) with d = aqq - app, e = 2 apq (the textbook
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), tau = d / e, multiplied through
+// by |e|), so that with w = |d| + sqrt(d^2 + e^2): c = w / sqrt(w^2 + e^2),
+// s = sign(d) e / sqrt(w^2 + e^2); one division.  Returns false (c = 1, s = 0)
+// when apq is below the rounding of the diagonal, where a rotation changes
+// nothing.  Branch-free (the identity is selected afterwards), so that a lane's
+// rotations overlap.
+__device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double w = fabs(d) + sqrt(d * d + e * e);
+    const double g = 1.0 / sqrt(w * w + e * e);
+    const bool act = apq != 0.0 && apq * apq > (2.2e-16 * 2.2e-16) * fabs(app * aqq);
+    c = act ? w * g : 1.0;
+    s = act ? (d >= 0.0 ? e : -e) * g : 0.0;
+    return act;
+}
+
+// Tile width of the grid-team block Jacobi (psd_project_team) and the order
+// of its subproblems (two tiles).
+constexpr int kPsdTile = 8;
+constexpr int kPsdSub = 2 * kPsdTile;
+
 // Rotation tables of one Jacobi round (LDS, shared by both PSD routines).
 struct PsdRound {
     double cs[512], sn[512];
@@ -240,10 +264,28 @@ struct PsdRound {
     int nact;
 };
 
-__device__ __forceinline__ PsdRound& psd_round_lds() {
-    __shared__ PsdRound r;
+// Inputs of one piece of a team block Jacobi round, gathered from global
+// memory in one burst (every load in flight together) and then read from
+// LDS: a submatrix of the matrix being turned (up to two pairs' slots by two
+// pairs' slots) and the two pairs' Q.  The team path runs after a workgroup's
+// one-workgroup blocks, so it shares the rotation tables' LDS.
+struct PsdStage {
+    double M[2 * kPsdSub][2 * kPsdSub + 1];
+    double Qa[kPsdSub][kPsdSub + 1];
+    double Qb[kPsdSub][kPsdSub + 1];
+};
+
+union PsdLds {
+    PsdRound round;
+    PsdStage stage;
+};
+
+__device__ __forceinline__ PsdLds& psd_lds() {
+    __shared__ PsdLds r;
     return r;
 }
+
+__device__ __forceinline__ PsdRound& psd_round_lds() { return psd_lds().round; }
 
 // Pairs of round `round` of the round-robin ordering over kk (even) indices:
 // position 0 stays, the others rotate; pair h is (pp[h], qq[h]) with p < q.
@@ -260,18 +302,7 @@ __device__ __forceinline__ void psd_round_params(int k, int kk, int round, const
         const int y = 1 + ((kk - 2 - h + round) % (kk - 1));
         const int p = x < y ? x : y, q = x < y ? y : x;
         double c = 1.0, s = 0.0;
-        if (q < k) {
-            const double apq = mat[p * k + q];
-            // a rotation smaller than the rounding of the diagonal changes nothing
-            if (apq != 0.0 && fabs(apq) > 2.2e-16 * sqrt(fabs(mat[p * k + p] * mat[q * k + q]))) {
-                const double app = mat[p * k + p], aqq = mat[q * k + q];
-                const double tau = (aqq - app) / (2.0 * apq);
-                const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                c = 1.0 / sqrt(1.0 + tt * tt);
-                s = tt * c;
-                act = 1;
-            }
-        }
+        if (q < k && jacobi_rotation(mat[p * k + p], mat[q * k + q], mat[p * k + q], c, s)) act = 1;
         R.pp[h] = p; R.qq[h] = q; R.cs[h] = c; R.sn[h] = s;
     }
     if (act) atomicAdd(&R.nact, 1);
@@ -288,31 +319,68 @@ __device__ __forceinline__ void psd_round_apply(int k, int np, const PsdRound& R
                                                 int nr) {
     const auto mat = vec_at<L>(mat_);
     const auto vt = vec_at<L>(vt_);
-    for (int idx = r; idx < np * np; idx += nr) {
-        const int h1 = idx / np, h2 = idx - (idx / np) * np;
-        const int p1 = R.pp[h1], q1 = R.qq[h1], p2 = R.pp[h2], q2 = R.qq[h2];
-        const bool e1 = q1 < k, e2 = q2 < k;          // the dummy index has no row / column
-        const double c1 = R.cs[h1], s1 = R.sn[h1], c2 = R.cs[h2], s2 = R.sn[h2];
-        const double app = mat[p1 * k + p2];
-        const double apq = e2 ? mat[p1 * k + q2] : 0.0;
-        const double aqp = e1 ? mat[q1 * k + p2] : 0.0;
-        const double aqq = (e1 && e2) ? mat[q1 * k + q2] : 0.0;
-        // B = J^T A (rows), then C = B J (columns)
-        const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
-        const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-        mat[p1 * k + p2] = c2 * bpp - s2 * bpq;
-        if (e2) mat[p1 * k + q2] = s2 * bpp + c2 * bpq;
-        if (e1) mat[q1 * k + p2] = c2 * bqp - s2 * bqq;
-        if (e1 && e2) mat[q1 * k + q2] = s2 * bqp + c2 * bqq;
+    // a thread's items are taken kCh at a time, all loads before any store
+    // (the items' entries are distinct), so their loads are in flight together
+    constexpr int kCh = 2;
+    for (int i0 = r; i0 < np * np; i0 += kCh * nr) {
+        int p1[kCh], q1[kCh], p2[kCh], q2[kCh];
+        double c1[kCh], s1[kCh], c2[kCh], s2[kCh], app[kCh], apq[kCh], aqp[kCh], aqq[kCh];
+#pragma unroll
+        for (int u = 0; u < kCh; ++u) {
+            const int idx = min(i0 + u * nr, np * np - 1);   // a repeated last item is not stored
+            const int h1 = idx / np, h2 = idx - (idx / np) * np;
+            p1[u] = R.pp[h1]; q1[u] = R.qq[h1]; p2[u] = R.pp[h2]; q2[u] = R.qq[h2];
+            c1[u] = R.cs[h1]; s1[u] = R.sn[h1]; c2[u] = R.cs[h2]; s2[u] = R.sn[h2];
+        }
+#pragma unroll
+        for (int u = 0; u < kCh; ++u) {
+            const bool e1 = q1[u] < k, e2 = q2[u] < k;   // the dummy index has no row / column
+            app[u] = mat[p1[u] * k + p2[u]];
+            apq[u] = e2 ? mat[p1[u] * k + q2[u]] : 0.0;
+            aqp[u] = e1 ? mat[q1[u] * k + p2[u]] : 0.0;
+            aqq[u] = (e1 && e2) ? mat[q1[u] * k + q2[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kCh; ++u) {
+            if (i0 + u * nr >= np * np) continue;
+            const bool e1 = q1[u] < k, e2 = q2[u] < k;
+            // B = J^T A (rows), then C = B J (columns)
+            const double bpp = c1[u] * app[u] - s1[u] * aqp[u], bpq = c1[u] * apq[u] - s1[u] * aqq[u];
+            const double bqp = s1[u] * app[u] + c1[u] * aqp[u], bqq = s1[u] * apq[u] + c1[u] * aqq[u];
+            mat[p1[u] * k + p2[u]] = c2[u] * bpp - s2[u] * bpq;
+            if (e2) mat[p1[u] * k + q2[u]] = s2[u] * bpp + c2[u] * bpq;
+            if (e1) mat[q1[u] * k + p2[u]] = c2[u] * bqp - s2[u] * bqq;
+            if (e1 && e2) mat[q1[u] * k + q2[u]] = s2[u] * bqp + c2[u] * bqq;
+        }
     }
-    for (int idx = r; idx < np * k; idx += nr) {
-        const int h = idx / k, j = idx - (idx / k) * k;
-        const int p = R.pp[h], q = R.qq[h];
-        if (q >= k || R.sn[h] == 0.0) continue;
-        const double c = R.cs[h], s_ = R.sn[h];
-        const double vp = vt[p * k + j], vq = vt[q * k + j];
-        vt[p * k + j] = c * vp - s_ * vq;
-        vt[q * k + j] = s_ * vp + c * vq;
+    constexpr int kChV = 4;
+    for (int i0 = r; i0 < np * k; i0 += kChV * nr) {
+        int pv[kChV], qv[kChV], jv[kChV];
+        double cv[kChV], sv[kChV], vp[kChV], vq[kChV];
+#pragma unroll
+        for (int u = 0; u < kChV; ++u) {
+            const int idx = min(i0 + u * nr, np * k - 1);
+            const int h = idx / k;
+            jv[u] = idx - h * k;
+            pv[u] = R.pp[h];
+            qv[u] = min(R.qq[h], k - 1);               // dummy partner: read in range, not stored
+            cv[u] = R.cs[h];
+            sv[u] = R.sn[h];
+        }
+#pragma unroll
+        for (int u = 0; u < kChV; ++u) {
+            vp[u] = vt[pv[u] * k + jv[u]];
+            vq[u] = vt[qv[u] * k + jv[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kChV; ++u) {
+            const int idx = i0 + u * nr;
+            if (idx >= np * k) continue;
+            const int h = idx / k;
+            if (R.qq[h] >= k || sv[u] == 0.0) continue;
+            vt[pv[u] * k + jv[u]] = cv[u] * vp[u] - sv[u] * vq[u];
+            vt[qv[u] * k + jv[u]] = sv[u] * vp[u] + cv[u] * vq[u];
+        }
     }
 }
 
@@ -426,8 +494,6 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
 // k/kPsdTile - 1 rounds per sweep, instead of one barrier per round over
 // k - 1 rounds (the round structure is described at psd_project_team).  Warm
 // start and stopping rule as in psd_project_block.
-constexpr int kPsdTile = 8;
-constexpr int kPsdSub = 2 * kPsdTile;
 
 struct PsdSub {
     double S[kPsdSub][kPsdSub + 1];
@@ -456,16 +522,21 @@ __device__ __forceinline__ void psd_tile_pair(int ntt, int round, int h, int& t1
     t2 = x < y ? y : x;
 }
 
-// Tile pair containing tile t in round `round`, and t's side (0: first tile).
+// Tile pair containing tile t in round `round`, and t's side (0: first tile):
+// psd_tile_pair inverted.  Tile 0 is in pair 0; a tile t > 0 is the moving
+// entry x of pair h = ((t - 1 - round) mod (ntt - 1)) + 1 when that h is a
+// pair, else the entry y of pair (ntt - 2 + round - (t - 1)) mod (ntt - 1).
 __device__ __forceinline__ int psd_tile_owner(int ntt, int round, int t, int& side) {
-    for (int h = 0; h < ntt / 2; ++h) {
-        int t1, t2;
-        psd_tile_pair(ntt, round, h, t1, t2);
-        if (t1 == t) { side = 0; return h; }
-        if (t2 == t) { side = 1; return h; }
+    int h = 0;
+    if (t > 0) {
+        const int m = ntt - 1, a = t - 1;
+        const int hx = ((a - round) % m + m) % m + 1;
+        h = hx <= ntt / 2 - 1 ? hx : (ntt - 2 + round - a) % m;
     }
-    side = 0;
-    return 0;
+    int t1, t2;
+    psd_tile_pair(ntt, round, h, t1, t2);
+    side = t == t1 ? 0 : 1;
+    return h;
 }
 
 // Orders LDS accesses between the lanes of one wavefront (a wavefront runs in
@@ -486,17 +557,19 @@ constexpr int kPsdInnerSweeps = 1;
 // Cyclic Jacobi on the symmetric kPsdSub x kPsdSub matrix in L.S (filled and
 // visible to the workgroup); writes its eigenvectors Q (slot x slot,
 // row-major, new column b = sum_a Q[a][b] old column a) to q.  Called by a
-// whole workgroup: the sweeps run on the first wavefront alone (eight
-// rotations of a round, parameters passed by lane shuffles, wavefront
-// ordering instead of workgroup barriers).
+// whole workgroup: the sweeps run on the first wavefront alone (the eight
+// rotations of a round, eight lanes per rotation, each lane computing its
+// rotation itself; wavefront ordering instead of workgroup barriers).
 __device__ __noinline__ void psd_sub_jacobi(double* q) {
     PsdSub& L = psd_sub_lds();
     const int t = threadIdx.x, n = blockDim.x;
     for (int e = t; e < kPsdSub * kPsdSub; e += n) L.Q[e / kPsdSub][e % kPsdSub] = (e / kPsdSub == e % kPsdSub) ? 1.0 : 0.0;
     __syncthreads();
     if (t < WAVE) {
-        constexpr int kHalf = kPsdSub / 2;
-        constexpr int kPer = kHalf * kPsdSub / WAVE;            // (pair, index) items per lane
+        constexpr int kHalf = kPsdSub / 2;                      // rotations per round
+        constexpr int kLanes = WAVE / kHalf;                    // lanes per rotation
+        constexpr int kPer = kPsdSub / kLanes;                  // indices per lane
+        static_assert(kLanes * kHalf == WAVE && kPer * kLanes == kPsdSub, "one wavefront per subproblem");
         const double tol2 = (1e-16 * kPsdSub) * (1e-16 * kPsdSub);
         double prev = 1.0;
         for (int sweep = 0; sweep < kPsdInnerSweeps; ++sweep) {
@@ -512,51 +585,49 @@ __device__ __noinline__ void psd_sub_jacobi(double* q) {
             if (cur <= tol2 || (cur <= 1e-24 && cur > 0.25 * prev)) break;
             prev = cur;
             for (int round = 0; round < kPsdSub - 1; ++round) {
-                // lane h < kHalf: rotation of pair h
-                int p = 0, qq = 0;
-                double c = 1.0, s_ = 0.0;
-                if (t < kHalf) {
-                    psd_tile_pair(kPsdSub, round, t, p, qq);
-                    const double apq = L.S[p][qq];
-                    if (apq != 0.0 && fabs(apq) > 2.2e-16 * sqrt(fabs(L.S[p][p] * L.S[qq][qq]))) {
-                        const double tau = (L.S[qq][qq] - L.S[p][p]) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
-                        s_ = tt * c;
-                    }
-                }
-                int ph[kPer], qh[kPer];
-                double ch[kPer], sh_[kPer];
-#pragma unroll
-                for (int r = 0; r < kPer; ++r) {
-                    const int h = (t + r * WAVE) / kPsdSub;
-                    ph[r] = __shfl(p, h, WAVE);
-                    qh[r] = __shfl(qq, h, WAVE);
-                    ch[r] = __shfl(c, h, WAVE);
-                    sh_[r] = __shfl(s_, h, WAVE);
-                }
+                // lane t serves pair h = t / kLanes (kLanes lanes per pair) at
+                // indices (t % kLanes) + r kLanes, r < kPer, and computes that
+                // pair's rotation itself (the lanes of a pair agree: same
+                // inputs).  Each step issues all its LDS loads before its
+                // stores (the items touch distinct entries), so they are in
+                // flight together.
+                int p, qq;
+                psd_tile_pair(kPsdSub, round, t / kLanes, p, qq);
+                double c, sn;
+                jacobi_rotation(L.S[p][p], L.S[qq][qq], L.S[p][qq], c, sn);
+                double x0[kPer], x1[kPer], x2[kPer], x3[kPer];
                 wave_lds_sync();
-                // rows p, q of S <- J^T S
+                // rows p, q of S <- J^T S (an identity rotation rewrites its
+                // entries unchanged: c x - 0 y = x)
 #pragma unroll
                 for (int r = 0; r < kPer; ++r) {
-                    if (sh_[r] == 0.0) continue;
-                    const int j = (t + r * WAVE) % kPsdSub;
-                    const double xp = L.S[ph[r]][j], xq = L.S[qh[r]][j];
-                    L.S[ph[r]][j] = ch[r] * xp - sh_[r] * xq;
-                    L.S[qh[r]][j] = sh_[r] * xp + ch[r] * xq;
+                    const int j = t % kLanes + r * kLanes;
+                    x0[r] = L.S[p][j];
+                    x1[r] = L.S[qq][j];
+                }
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    const int j = t % kLanes + r * kLanes;
+                    L.S[p][j] = c * x0[r] - sn * x1[r];
+                    L.S[qq][j] = sn * x0[r] + c * x1[r];
                 }
                 wave_lds_sync();
                 // columns p, q of S and of Q <- (.) J
 #pragma unroll
                 for (int r = 0; r < kPer; ++r) {
-                    if (sh_[r] == 0.0) continue;
-                    const int i = (t + r * WAVE) % kPsdSub;
-                    const double xp = L.S[i][ph[r]], xq = L.S[i][qh[r]];
-                    L.S[i][ph[r]] = ch[r] * xp - sh_[r] * xq;
-                    L.S[i][qh[r]] = sh_[r] * xp + ch[r] * xq;
-                    const double vp = L.Q[i][ph[r]], vq = L.Q[i][qh[r]];
-                    L.Q[i][ph[r]] = ch[r] * vp - sh_[r] * vq;
-                    L.Q[i][qh[r]] = sh_[r] * vp + ch[r] * vq;
+                    const int i = t % kLanes + r * kLanes;
+                    x0[r] = L.S[i][p];
+                    x1[r] = L.S[i][qq];
+                    x2[r] = L.Q[i][p];
+                    x3[r] = L.Q[i][qq];
+                }
+#pragma unroll
+                for (int r = 0; r < kPer; ++r) {
+                    const int i = t % kLanes + r * kLanes;
+                    L.S[i][p] = c * x0[r] - sn * x1[r];
+                    L.S[i][qq] = sn * x0[r] + c * x1[r];
+                    L.Q[i][p] = c * x2[r] - sn * x3[r];
+                    L.Q[i][qq] = sn * x2[r] + c * x3[r];
                 }
                 wave_lds_sync();
             }
@@ -567,9 +638,6 @@ __device__ __noinline__ void psd_sub_jacobi(double* q) {
     __syncthreads();
 }
 
-
-// Diagonalises the 2-tile submatrix for tile pair (t1, t2), entry (i, j) of
-// the matrix being at(i, j); Q to q.  Whole workgroup.
 template <typename At>
 __device__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
     PsdSub& L = psd_sub_lds();
@@ -584,39 +652,47 @@ __device__ void psd_sub_diag(int k, int nt, int t1, int t2, At at, double* q) {
 
 // Subproblem of tile pair h of round `nr`, taken from the matrix after round
 // r (B = Q_r^T A Q_r, A = mat, Q_r of every round-r pair at qr), computed from
-// A and Q_r directly: rows of the subproblem come from two round-r pairs, so
-// T = A[rows of those pairs, pair of column b] Q_r[:, b] (2 x 16 x 16, in the
-// LDS of L), then S[a][b] = sum_x Q_r[x][a'] T[x][b].  Then diagonalised; Q
-// to q.  Whole workgroup.
+// A and Q_r directly.  The two new tiles u1, u2 sit in two different round-r
+// pairs o1, o2 (a pair meets once per sweep), so B restricted to them needs
+// only A on the slots of o1 and o2 (32 x 32) and Q_o1, Q_o2: these are staged
+// in LDS first.  Then T = A[slots of o(u), slots of o(b)] Q_o(b)[:, b]
+// (2 x 16 x 16, in the LDS of L) and S[a][b] = sum_x Q_o(a)[x][a'] T[x][b],
+// with a', b the new slots' places in their round-r pairs.  Then diagonalised;
+// Q to q.  Whole workgroup.
 __device__ __noinline__ void psd_next_sub(int k, int nt, int ntt, int r, int nr, int h, const double* mat,
                                           const double* qr, double* q) {
     PsdSub& L = psd_sub_lds();
+    PsdStage& G = psd_lds().stage;
     double* T = &L.S[0][0];                        // 2 * kPsdSub * kPsdSub doubles over S and Q
     const int t = threadIdx.x, n = blockDim.x;
     int u1, u2;
     psd_tile_pair(ntt, nr, h, u1, u2);
+    int s1, s2;                                    // sides of u1, u2 in their round-r pairs
+    const int o1 = psd_tile_owner(ntt, r, u1, s1), o2 = psd_tile_owner(ntt, r, u2, s2);
+    int a1, a2, b1, b2;
+    psd_tile_pair(ntt, r, o1, a1, a2);
+    psd_tile_pair(ntt, r, o2, b1, b2);
+    for (int e = t; e < 4 * kPsdSub * kPsdSub; e += n) {
+        const int x = e / (2 * kPsdSub), y = e - (e / (2 * kPsdSub)) * (2 * kPsdSub);
+        const int gx = x < kPsdSub ? psd_slot_index(k, nt, a1, a2, x) : psd_slot_index(k, nt, b1, b2, x - kPsdSub);
+        const int gy = y < kPsdSub ? psd_slot_index(k, nt, a1, a2, y) : psd_slot_index(k, nt, b1, b2, y - kPsdSub);
+        G.M[x][y] = (gx >= 0 && gy >= 0) ? mat[(size_t)gx * k + gy] : 0.0;
+    }
+    for (int e = t; e < 2 * kPsdSub * kPsdSub; e += n) {
+        const int w = e / (kPsdSub * kPsdSub), f = e - w * (kPsdSub * kPsdSub);
+        const double v = qr[(size_t)(w ? o2 : o1) * kPsdSub * kPsdSub + f];
+        if (w) G.Qb[f / kPsdSub][f % kPsdSub] = v;
+        else G.Qa[f / kPsdSub][f % kPsdSub] = v;
+    }
+    __syncthreads();
     for (int e = t; e < 2 * kPsdSub * kPsdSub; e += n) {
         const int sr = e / (kPsdSub * kPsdSub), x = (e / kPsdSub) % kPsdSub, b = e % kPsdSub;
-        const int u = sr ? u2 : u1;
-        const int gb = psd_slot_index(k, nt, u1, u2, b);
+        const int cb = (b < kPsdTile ? s1 : s2) * kPsdTile + b % kPsdTile;
+        const int yo = b < kPsdTile ? 0 : kPsdSub;
         double v = 0.0;
-        if (u < nt && gb >= 0) {
-            int srow, scol;
-            const int hr = psd_tile_owner(ntt, r, u, srow);
-            const int hc = psd_tile_owner(ntt, r, gb / kPsdTile, scol);
-            int r1, r2, c1, c2;
-            psd_tile_pair(ntt, r, hr, r1, r2);
-            psd_tile_pair(ntt, r, hc, c1, c2);
-            const int gx = psd_slot_index(k, nt, r1, r2, x);
-            if (gx >= 0) {
-                const double* qc = qr + (size_t)hc * kPsdSub * kPsdSub;
-                const int cb = scol * kPsdTile + gb % kPsdTile;
-                for (int y = 0; y < kPsdSub; ++y) {
-                    const int gy = psd_slot_index(k, nt, c1, c2, y);
-                    if (gy >= 0) v += mat[(size_t)gx * k + gy] * qc[y * kPsdSub + cb];
-                }
-            }
-        }
+#pragma unroll
+        for (int y = 0; y < kPsdSub; ++y)
+            v += G.M[sr * kPsdSub + x][yo + y] * (b < kPsdTile ? G.Qa[y][cb] : G.Qb[y][cb]);
         T[e] = v;
     }
     __syncthreads();
@@ -625,12 +701,10 @@ __device__ __noinline__ void psd_next_sub(int k, int nt, int ntt, int r, int nr,
         const int a = t / kPsdSub, b = t % kPsdSub;
         const int ga = psd_slot_index(k, nt, u1, u2, a), gb = psd_slot_index(k, nt, u1, u2, b);
         if (ga >= 0 && gb >= 0) {
-            int sa;
-            const int hr = psd_tile_owner(ntt, r, ga / kPsdTile, sa);
-            const double* qa = qr + (size_t)hr * kPsdSub * kPsdSub;
-            const int ca = sa * kPsdTile + ga % kPsdTile;
+            const int ca = (a < kPsdTile ? s1 : s2) * kPsdTile + a % kPsdTile;
             const double* tr = T + (size_t)(a / kPsdTile) * kPsdSub * kPsdSub;
-            for (int x = 0; x < kPsdSub; ++x) s_ += qa[x * kPsdSub + ca] * tr[x * kPsdSub + b];
+#pragma unroll
+            for (int x = 0; x < kPsdSub; ++x) s_ += (a < kPsdTile ? G.Qa[x][ca] : G.Qb[x][ca]) * tr[x * kPsdSub + b];
         }
     }
     __syncthreads();
@@ -663,12 +737,16 @@ __device__ __noinline__ void psd_team_mm(int r0, int R, int k, const double* A, 
 }
 
 // Step (a) of a team block Jacobi round: output blocks (pair hi, pair hc) of
-// Q^T mat Q into out, one workgroup per block; on the sweep's last round also
-// the squared off-diagonal and total mass of the output (added to off, tot).
+// Q^T mat Q into out, one workgroup per block (workgroups blk, blk + nblk,
+// ... of the ones taking part); the input block and the two Q are staged in
+// LDS first.  On the sweep's last round also the squared off-diagonal and
+// total mass of the output (added to off, tot).
 __device__ __noinline__ void psd_team_blocks(int blk, int nblk, int k, int nt, int ntt, int np, int round, bool last,
                                              const double* mat, double* out, const double* qr, double* acc) {
     PsdSub& L = psd_sub_lds();
+    PsdStage& G = psd_lds().stage;
     double off = 0.0, tot = 0.0;
+    const int e = threadIdx.x;
     for (int bid = blk; bid < np * np; bid += nblk) {
         const int hi = bid / np, hc = bid - (bid / np) * np;
         int i1, i2, c1, c2;
@@ -676,18 +754,24 @@ __device__ __noinline__ void psd_team_blocks(int blk, int nblk, int k, int nt, i
         psd_tile_pair(ntt, round, hc, c1, c2);
         const double* qi = qr + (size_t)hi * kPsdSub * kPsdSub;
         const double* qc = qr + (size_t)hc * kPsdSub * kPsdSub;
-        const int e = threadIdx.x;
+        for (int f = e; f < 3 * kPsdSub * kPsdSub; f += blockDim.x) {
+            const int w = f / (kPsdSub * kPsdSub), g = f - w * (kPsdSub * kPsdSub);
+            const int x = g / kPsdSub, y = g % kPsdSub;
+            if (w == 0) {
+                const int gx = psd_slot_index(k, nt, i1, i2, x), gy = psd_slot_index(k, nt, c1, c2, y);
+                G.M[x][y] = (gx >= 0 && gy >= 0) ? mat[(size_t)gx * k + gy] : 0.0;
+            } else if (w == 1) {
+                G.Qa[x][y] = qi[g];
+            } else {
+                G.Qb[x][y] = qc[g];
+            }
+        }
+        __syncthreads();
         if (e < kPsdSub * kPsdSub) {               // L.S = mat[block] Q_c
             const int x = e / kPsdSub, cb = e % kPsdSub;
-            const int gx = psd_slot_index(k, nt, i1, i2, x);
             double v = 0.0;
-            if (gx >= 0) {
-#pragma unroll 4
-                for (int y = 0; y < kPsdSub; ++y) {
-                    const int gy = psd_slot_index(k, nt, c1, c2, y);
-                    if (gy >= 0) v += mat[(size_t)gx * k + gy] * qc[y * kPsdSub + cb];
-                }
-            }
+#pragma unroll
+            for (int y = 0; y < kPsdSub; ++y) v += G.M[x][y] * G.Qb[y][cb];
             L.S[x][cb] = v;
         }
         __syncthreads();
@@ -696,8 +780,8 @@ __device__ __noinline__ void psd_team_blocks(int blk, int nblk, int k, int nt, i
             const int gi = psd_slot_index(k, nt, i1, i2, ia), gc = psd_slot_index(k, nt, c1, c2, cb);
             if (gi >= 0 && gc >= 0) {
                 double v = 0.0;
-#pragma unroll 4
-                for (int x = 0; x < kPsdSub; ++x) v += qi[x * kPsdSub + ia] * L.S[x][cb];
+#pragma unroll
+                for (int x = 0; x < kPsdSub; ++x) v += G.Qa[x][ia] * L.S[x][cb];
                 out[(size_t)gi * k + gc] = v;
                 if (last) {
                     tot += v * v;
@@ -711,24 +795,30 @@ __device__ __noinline__ void psd_team_blocks(int blk, int nblk, int k, int nt, i
     acc[1] = tot;
 }
 
-// Step (b): vout = Q^T vin on the rows of each pair of the round.
-__device__ __noinline__ void psd_team_rows(int r0, int R, int k, int nt, int ntt, int round, const double* qr,
+// Step (b): vout = Q^T vin on the rows of each pair of the round, one row per
+// workgroup (rows w, w + nw, ... of the workgroups taking part), a thread per
+// column; the row's sixteen source rows are read in one burst.
+__device__ __noinline__ void psd_team_rows(int w, int nw, int k, int nt, int ntt, int round, const double* qr,
                                            const double* vin, double* vout) {
-    for (int idx = r0; idx < k * k; idx += R) {
-        const int rw = idx / k, j = idx - (idx / k) * k;
+    for (int rw = w; rw < k; rw += nw) {
         int side;
         const int h = psd_tile_owner(ntt, round, rw / kPsdTile, side);
         int t1, t2;
         psd_tile_pair(ntt, round, h, t1, t2);
         const double* q = qr + (size_t)h * kPsdSub * kPsdSub;
         const int ip = side * kPsdTile + rw % kPsdTile;
-        double sv = 0.0;
-#pragma unroll 4
-        for (int x = 0; x < kPsdSub; ++x) {
-            const int gx = psd_slot_index(k, nt, t1, t2, x);
-            if (gx >= 0) sv += q[x * kPsdSub + ip] * vin[(size_t)gx * k + j];
+        for (int j = threadIdx.x; j < k; j += blockDim.x) {
+            double src[kPsdSub];
+#pragma unroll
+            for (int x = 0; x < kPsdSub; ++x) {
+                const int gx = psd_slot_index(k, nt, t1, t2, x);
+                src[x] = gx >= 0 ? vin[(size_t)gx * k + j] : 0.0;
+            }
+            double sv = 0.0;
+#pragma unroll
+            for (int x = 0; x < kPsdSub; ++x) sv += q[x * kPsdSub + ip] * src[x];
+            vout[(size_t)rw * k + j] = sv;
         }
-        vout[idx] = sv;
     }
 }
 
@@ -814,19 +904,27 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
         tm.sync();
         double prev = 1.0;
         long long g = 0;                                  // rounds done; Q of round g is in qbuf[g & 1]
+        // (a) and (b) below run on the workgroups under `split`, (c) on the
+        // np from it: (c) is the longest piece, so its workgroups take no other
+        // work (with few workgroups, every one takes all three)
+        const int nb = tm.nblk(), wb = tm.blk();
+        const int split = nb > 2 * np ? nb - np : nb;
+        const int h0 = split < nb ? wb - split : wb, hs = split < nb ? np : nb;
         for (int sweep = 0; sweep < 30; ++sweep) {
             double acc[2] = {0.0, 0.0};
             for (int round = 0; round < ntt - 1; ++round, ++g) {
                 const double* qr = qbuf[g & 1];
                 const bool last = round == ntt - 2;
-                // (a) mat2 = Q^T mat Q, block by block: output block (pair hi, pair hc)
-                // needs input block (hi, hc) and the two pairs' Q only; (b) the
-                // pairs' rows of Vt
-                psd_team_blocks(tm.blk(), tm.nblk(), k, nt, ntt, np, round, last, mat, tmp, qr, acc);
-                psd_team_rows(r0, R_, k, nt, ntt, round, qr, vm, vm2);
+                if (wb < split) {
+                    // (a) mat2 = Q^T mat Q, block by block: output block (pair hi,
+                    // pair hc) needs input block (hi, hc) and the two pairs' Q
+                    // only; (b) the pairs' rows of Vt
+                    psd_team_blocks(wb, split, k, nt, ntt, np, round, last, mat, tmp, qr, acc);
+                    psd_team_rows(wb, split, k, nt, ntt, round, qr, vm, vm2);
+                }
                 // (c) Q of the next round (the next sweep's first after the last)
                 // from mat and this round's Q; unused if the sweeps stop here
-                for (int h = tm.blk(); h < np; h += tm.nblk())
+                for (int h = h0; h >= 0 && h < np; h += hs)
                     psd_next_sub(k, nt, ntt, round, last ? 0 : round + 1, h, mat, qr,
                                  qbuf[(g + 1) & 1] + (size_t)h * kPsdSub * kPsdSub);
                 double* sw = mat;

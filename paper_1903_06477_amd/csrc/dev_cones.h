@@ -197,39 +197,87 @@ __device__ __forceinline__ void psd_unpack_index(int k, int idx, int& i, int& j)
     i = j + (idx - (j * k - j * (j - 1) / 2));
 }
 
-// C = A B for k x k row-major matrices, by the whole workgroup.  A thread
-// computes rows i0 .. i0+3 of one column j: consecutive threads take
-// consecutive columns, so B and C coalesce, A is a broadcast, and each B load
-// feeds four products.
-__device__ __forceinline__ void psd_gemm(int k, const double* __restrict__ A, const double* __restrict__ B,
-                                         double* __restrict__ C) {
-    const int rb = (k + 3) / 4;
-    for (int idx = threadIdx.x; idx < rb * k; idx += blockDim.x) {
-        const int i0 = (idx / k) * 4, j = idx - (idx / k) * k;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        const int i1 = min(i0 + 1, k - 1), i2 = min(i0 + 2, k - 1), i3 = min(i0 + 3, k - 1);
-        for (int e = 0; e < k; ++e) {
-            const double b = B[e * k + j];
-            s0 += A[i0 * k + e] * b;
-            s1 += A[i1 * k + e] * b;
-            s2 += A[i2 * k + e] * b;
-            s3 += A[i3 * k + e] * b;
+// Dense products of the PSD projection (the warm start Vt0 X Vt0^T and the
+// reconstruction V max(lam, 0) V^T) on the FP64 matrix cores.
+typedef double psd_d4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 tile (rows i0.., columns j0..) of op(A) op(B) for k x k
+// row-major matrices, op(X) = X or X^T (TA, TB), by one wavefront with
+// v_mfma_f64_16x16x4 steps: for step s, lane l supplies A's entry (i0 + l % 16,
+// 4 s + l / 16) and B's entry (4 s + l / 16, j0 + l % 16), and the lane's
+// result r (r < 4) is row i0 + 4 r + l / 16 of column j0 + l % 16.  Entries
+// past k read as zero.  Eight steps' loads are issued before their products.
+// The whole wavefront must take part.  Out of line: its registers stay out of
+// the allocation of the projection routines that call it.
+template <bool TA, bool TB>
+__device__ __noinline__ psd_d4 psd_mfma_tile(int k, const double* A, const double* B, int i0, int j0) {
+    const int l = threadIdx.x & (WAVE - 1);
+    const int ia = i0 + (l & 15), jb = j0 + (l & 15), lk = l >> 4;
+    psd_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    constexpr int kBatch = 8;
+#pragma unroll 1
+    for (int k0 = 0; k0 < k; k0 += 4 * kBatch) {
+        double av[kBatch], bv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int kk = k0 + 4 * u + lk;
+            av[u] = (kk < k && ia < k) ? (TA ? A[(size_t)kk * k + ia] : A[(size_t)ia * k + kk]) : 0.0;
+            bv[u] = (kk < k && jb < k) ? (TB ? B[(size_t)jb * k + kk] : B[(size_t)kk * k + jb]) : 0.0;
         }
-        C[i0 * k + j] = s0;
-        if (i0 + 1 < k) C[(i0 + 1) * k + j] = s1;
-        if (i0 + 2 < k) C[(i0 + 2) * k + j] = s2;
-        if (i0 + 3 < k) C[(i0 + 3) * k + j] = s3;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Stores a tile from psd_mfma_tile into C (k x k, row-major).
+__device__ __forceinline__ void psd_tile_store(int k, const psd_d4& acc, int i0, int j0, double* C) {
+    const int l = threadIdx.x & (WAVE - 1);
+    const int col = j0 + (l & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * r + (l >> 4);
+        if (row < k && col < k) C[(size_t)row * k + col] = acc[r];
     }
 }
 
-// dst = src^T (k x k) by the workgroup (consecutive threads write
-// consecutive entries of dst); ends with a barrier.
-__device__ __forceinline__ void psd_transpose(int k, const double* __restrict__ src, double* __restrict__ dst) {
-    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
-        const int i = idx / k, j = idx - (idx / k) * k;
-        dst[idx] = src[j * k + i];
+// Stores the entries on and below the diagonal of a tile of V max(lam, 0) V^T
+// into the packed output (column-major lower triangle, off-diagonals times
+// sqrt(2)).
+__device__ __forceinline__ void psd_tile_store_packed(int k, const psd_d4& acc, int i0, int j0, double* outv) {
+    const int l = threadIdx.x & (WAVE - 1);
+    const int j = j0 + (l & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 4 * r + (l >> 4);
+        if (i < k && j <= i) {
+            const size_t idx = (size_t)j * k - (size_t)j * (j - 1) / 2 + (i - j);
+            outv[idx] = (i == j) ? acc[r] : acc[r] * 1.41421356237309504880;
+        }
     }
-    __syncthreads();
+}
+
+// C = op(A) op(B) (k x k) by the wavefronts of one workgroup, a tile each in turn.
+template <bool TA, bool TB>
+__device__ __forceinline__ void psd_block_mma(int k, const double* A, const double* B, double* C) {
+    const int nt = (k + 15) / 16, w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll 1
+    for (int t = w; t < nt * nt; t += nw) {
+        const int i0 = (t / nt) * 16, j0 = (t % nt) * 16;
+        psd_tile_store(k, psd_mfma_tile<TA, TB>(k, A, B, i0, j0), i0, j0, C);
+    }
+}
+
+// outv = svec(Wt^T Vt) by the wavefronts of one workgroup (tiles on and below
+// the diagonal).
+__device__ __forceinline__ void psd_block_recon(int k, const double* wt, const double* vt, double* outv) {
+    const int nt = (k + 15) / 16, w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll 1
+    for (int t = w; t < nt * nt; t += nw) {
+        const int ti = t / nt, tj = t % nt;
+        if (tj > ti) continue;
+        psd_tile_store_packed(k, psd_mfma_tile<true, false>(k, wt, vt, ti * 16, tj * 16), ti * 16, tj * 16, outv);
+    }
 }
 
 // Rotation (c, s) of a Jacobi step that zeroes apq in the symmetric 2 x 2
@@ -405,10 +453,9 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
     double* mat = a;        // the matrix being diagonalised; tmp is the transpose buffer
     const bool use_warm = V0 != nullptr && *warm != 0;
     if (use_warm) {
-        psd_gemm(k, V0, a, tmp);                       // tmp = Vt0 A
+        psd_block_mma<false, false>(k, V0, a, tmp);    // tmp = Vt0 A
         __syncthreads();
-        psd_transpose(k, tmp, vm);                     // vm = A Vt0^T (A symmetric)
-        psd_gemm(k, V0, vm, a);                        // a = Vt0 A Vt0^T
+        psd_block_mma<false, true>(k, tmp, V0, a);     // a = (Vt0 A) Vt0^T
         __syncthreads();
         for (int idx = t; idx < k * k; idx += nt) {     // symmetrise (rounding) and start from Vt0
             const int i = idx / k, j = idx - (idx / k) * k;
@@ -464,19 +511,12 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
         }
     }
     // reconstruct V max(lam, 0) V^T in packed form with Vt = V^T: lam into
-    // `in` (consumed), Wt = diag(lam+) Vt into tmp, entry (i, j) =
-    // sum_e Wt[e][i] Vt[e][j] (Wt coalesced, Vt a broadcast)
+    // `in` (consumed), Wt = diag(lam+) Vt into tmp, then Wt^T Vt
     for (int e = t; e < k; e += nt) in[e] = fmax(mat[e * k + e], 0.0);
     __syncthreads();
     for (int idx = t; idx < k * k; idx += nt) tmp[idx] = vm[idx] * in[idx / k];
     __syncthreads();
-    for (int idx = t; idx < k * (k + 1) / 2; idx += nt) {
-        int i, j;
-        psd_unpack_index(k, idx, i, j);
-        double s = 0.0;
-        for (int e = 0; e < k; ++e) s += tmp[e * k + i] * vm[e * k + j];
-        outv[idx] = (i == j) ? s : s * 1.41421356237309504880;
-    }
+    psd_block_recon(k, tmp, vm, outv);
     if (V0 != nullptr) {
         for (int idx = t; idx < k * k; idx += nt) V0[idx] = vm[idx];
         if (t == 0) *warm = 1;
@@ -719,20 +759,16 @@ __device__ __noinline__ void psd_next_sub(int k, int nt, int ntt, int r, int nr,
 // value in across the call, so the tree is kept small.  Each piece is run by
 // every thread of the team over the index range r0, r0 + R, ...
 
-// C = A B (transB = false) or A B^T (true), k x k row-major.
-__device__ __noinline__ void psd_team_mm(int r0, int R, int k, const double* A, const double* B, double* C,
-                                         bool transB) {
-    for (int idx = r0; idx < k * k; idx += R) {
-        const int i = idx / k, j = idx - (idx / k) * k;
-        double s_ = 0.0;
-        if (transB) {
-#pragma unroll 4
-            for (int e = 0; e < k; ++e) s_ += A[(size_t)i * k + e] * B[(size_t)j * k + e];
-        } else {
-#pragma unroll 4
-            for (int e = 0; e < k; ++e) s_ += A[(size_t)i * k + e] * B[(size_t)e * k + j];
-        }
-        C[idx] = s_;
+// C = op(A) op(B) (k x k, row-major) by the team's wavefronts, a 16 x 16
+// tile each: tile t goes to workgroup t % nblk, so a small product spreads
+// over the whole grid.
+template <bool TA, bool TB>
+__device__ __noinline__ void psd_team_mma(int blk, int nblk, int k, const double* A, const double* B, double* C) {
+    const int nt = (k + 15) / 16, w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll 1
+    for (int t = blk + nblk * w; t < nt * nt; t += nblk * nw) {
+        const int i0 = (t / nt) * 16, j0 = (t % nt) * 16;
+        psd_tile_store(k, psd_mfma_tile<TA, TB>(k, A, B, i0, j0), i0, j0, C);
     }
 }
 
@@ -822,15 +858,15 @@ __device__ __noinline__ void psd_team_rows(int w, int nw, int k, int nt, int ntt
     }
 }
 
-// Packed output: outv = svec(Wt^T Vt), Wt = diag(lam+) Vt.
-__device__ __noinline__ void psd_team_recon(int r0, int R, int k, const double* wt, const double* vt, double* outv) {
-    for (int idx = r0; idx < k * (k + 1) / 2; idx += R) {
-        int i, j;
-        psd_unpack_index(k, idx, i, j);
-        double s_ = 0.0;
-#pragma unroll 4
-        for (int e = 0; e < k; ++e) s_ += wt[(size_t)e * k + i] * vt[(size_t)e * k + j];
-        outv[idx] = (i == j) ? s_ : s_ * 1.41421356237309504880;
+// Packed output: outv = svec(Wt^T Vt), Wt = diag(lam+) Vt, by the team's
+// wavefronts (tiles on and below the diagonal).
+__device__ __noinline__ void psd_team_recon(int blk, int nblk, int k, const double* wt, const double* vt, double* outv) {
+    const int nt = (k + 15) / 16, w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll 1
+    for (int t = blk + nblk * w; t < nt * nt; t += nblk * nw) {
+        const int ti = t / nt, tj = t % nt;
+        if (tj > ti) continue;
+        psd_tile_store_packed(k, psd_mfma_tile<true, false>(k, wt, vt, ti * 16, tj * 16), ti * 16, tj * 16, outv);
     }
 }
 
@@ -862,9 +898,9 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     tm.sync();
     const bool use_warm = V0 != nullptr && *warm != 0;
     if (use_warm) {
-        psd_team_mm(r0, R_, k, V0, mat, tmp, false);     // tmp = Vt0 A
+        psd_team_mma<false, false>(tm.blk(), tm.nblk(), k, V0, mat, tmp);    // tmp = Vt0 A
         tm.sync();
-        psd_team_mm(r0, R_, k, tmp, V0, vm2, true);      // vm2 = (Vt0 A) Vt0^T
+        psd_team_mma<false, true>(tm.blk(), tm.nblk(), k, tmp, V0, vm2);     // vm2 = (Vt0 A) Vt0^T
         tm.sync();
         for (int idx = r0; idx < k * k; idx += R_) {
             const int i = idx / k, j = idx - (idx / k) * k;
@@ -951,7 +987,7 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
     tm.sync();
     for (int idx = r0; idx < k * k; idx += R_) tmp[idx] = vm[idx] * in[idx / k];
     tm.sync();
-    psd_team_recon(r0, R_, k, tmp, vm, outv);
+    psd_team_recon(tm.blk(), tm.nblk(), k, tmp, vm, outv);
     if (V0 != nullptr) {
         for (int idx = r0; idx < k * k; idx += R_) V0[idx] = vm[idx];
         if (r0 == 0) *warm = 1;

@@ -139,10 +139,13 @@ using BlockTeam = BlockTeamT<false>;
 // Words of the grid barrier, each on its own 128-byte line: the global
 // arrival counter, one arrival counter and one release word per group, one
 // workgroup count per group and the set-up counter.  Groups are the XCDs
-// (the hardware XCC_ID, four bits).
+// (the hardware XCC_ID, four bits).  From BAR_SUB, the same words (less the
+// set-up counter) of a second barrier among a subset of the workgroups (the
+// PSD sub-team, PsdSubTeam).
 constexpr int BAR_STRIDE = 16;
 constexpr int BAR_GROUPS = 16;
-constexpr int BAR_WORDS = BAR_STRIDE * (2 + 3 * BAR_GROUPS);
+constexpr int BAR_SUB = BAR_STRIDE * (2 + 3 * BAR_GROUPS);
+constexpr int BAR_WORDS = BAR_SUB + BAR_STRIDE * (1 + 3 * BAR_GROUPS);
 
 // The XCD (accelerator complex die) the calling wave runs on.
 __device__ __forceinline__ unsigned xcc_id() {
@@ -164,6 +167,27 @@ __device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned lo
         }
     }
     return true;
+}
+
+// Thread 0's part of the k-th barrier among a team with `members` workgroups
+// on this workgroup's XCD `grp` and `ngrp` XCDs in all, on the words from
+// `base` (laid out as at BAR_WORDS); see GridTeam::sync.
+__device__ __forceinline__ void xcd_barrier(unsigned long long* base, unsigned grp, unsigned long long members,
+                                            unsigned ngrp, unsigned long long k, int* abort_flag,
+                                            long long timeout_ticks) {
+    unsigned long long* cnt = base + BAR_STRIDE * (1 + grp);
+    unsigned long long* rel = base + BAR_STRIDE * (1 + BAR_GROUPS + grp);
+    const unsigned long long old = __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == k * members) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");     // the XCD's L2 written back
+        __hip_atomic_fetch_add(base, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        spin_until(base, k * ngrp, abort_flag, timeout_ticks);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");     // and the other XCDs' data acquired
+        __hip_atomic_store(rel, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        spin_until(rel, k, abort_flag, timeout_ticks);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
 }
 
 // Two-level grid barrier over the XCDs.  Each XCD has its own L2, which is
@@ -200,12 +224,19 @@ struct GridTeam {
     MatPart mp[2];              // this workgroup's rows of A and A^T
     unsigned long long* bar;    // BAR_WORDS words, zero at launch
     int* abort_flag;
-    double* part;               // [2][KMAX][gridDim.x] partials
+    double* part;               // [4][KMAX][gridDim.x] partials (2 and 3: the PSD sub-team's)
     unsigned long long k;       // barriers passed so far
     long long timeout_ticks;
     int flip;
     unsigned grp, ngrp;         // this workgroup's XCD; XCDs the grid occupies
     unsigned long long members; // workgroups on this XCD
+    // the PSD sub-team (workgroups sub0 .. gridDim.x - 1; none when sub0 is 0):
+    // its workgroups on this XCD, its XCDs, its barriers passed, its partials' buffer
+    int sub0 = 0;
+    unsigned long long sub_members = 0;
+    unsigned sub_ngrp = 0;
+    unsigned long long sub_k = 0;
+    int sub_flip = 0;
 
     __device__ int rank() const { return blockIdx.x * blockDim.x + threadIdx.x; }
     __device__ int size() const { return gridDim.x * blockDim.x; }
@@ -218,30 +249,42 @@ struct GridTeam {
         return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
 
-    // Counts the workgroups per XCD (one fully fenced rendezvous of the grid).
-    __device__ void set_up() {
-        __shared__ unsigned s_grp, s_ngrp;
-        __shared__ unsigned long long s_members;
+    // Counts the workgroups per XCD, of the grid and of the PSD sub-team
+    // (workgroups from `sub_start`, none when 0), in one fully fenced
+    // rendezvous of the grid.
+    __device__ void set_up(int sub_start = 0) {
+        __shared__ unsigned s_grp, s_ngrp, s_sub_ngrp;
+        __shared__ unsigned long long s_members, s_sub_members;
         unsigned long long* cnt = bar + BAR_STRIDE * (1 + 2 * BAR_GROUPS);
+        unsigned long long* scnt = bar + BAR_SUB + BAR_STRIDE * (1 + 2 * BAR_GROUPS);
         unsigned long long* arrived = bar + BAR_STRIDE * (1 + 3 * BAR_GROUPS);
         if (threadIdx.x == 0) {
             const unsigned x = xcc_id();
             __hip_atomic_fetch_add(cnt + BAR_STRIDE * x, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (sub_start > 0 && (int)blockIdx.x >= sub_start)
+                __hip_atomic_fetch_add(scnt + BAR_STRIDE * x, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_fetch_add(arrived, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             spin_until(arrived, gridDim.x, abort_flag, timeout_ticks);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            unsigned ng = 0;
-            for (int i = 0; i < BAR_GROUPS; ++i)
+            unsigned ng = 0, sng = 0;
+            for (int i = 0; i < BAR_GROUPS; ++i) {
                 ng += __hip_atomic_load(cnt + BAR_STRIDE * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+                sng += __hip_atomic_load(scnt + BAR_STRIDE * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+            }
             s_grp = x;
             s_ngrp = ng;
+            s_sub_ngrp = sng;
             s_members = __hip_atomic_load(cnt + BAR_STRIDE * x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_sub_members = __hip_atomic_load(scnt + BAR_STRIDE * x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         grp = s_grp;
         ngrp = s_ngrp;
         members = s_members;
+        sub0 = sub_start;
+        sub_ngrp = s_sub_ngrp;
+        sub_members = s_sub_members;
         __syncthreads();
     }
 
@@ -249,22 +292,7 @@ struct GridTeam {
         __builtin_amdgcn_s_waitcnt(0);          // this wave's stores acknowledged (in the XCD's L2)
         __syncthreads();
         ++k;
-        if (threadIdx.x == 0) {
-            unsigned long long* cnt = bar + BAR_STRIDE * (1 + grp);
-            unsigned long long* rel = bar + BAR_STRIDE * (1 + BAR_GROUPS + grp);
-            const unsigned long long old =
-                __hip_atomic_fetch_add(cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (old + 1 == k * members) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");     // the XCD's L2 written back
-                __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                spin_until(bar, k * ngrp, abort_flag, timeout_ticks);
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");     // and the other XCDs' data acquired
-                __hip_atomic_store(rel, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                spin_until(rel, k, abort_flag, timeout_ticks);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-        }
+        if (threadIdx.x == 0) xcd_barrier(bar, grp, members, ngrp, k, abort_flag, timeout_ticks);
         __syncthreads();
     }
 
@@ -285,6 +313,49 @@ struct GridTeam {
         }
         __syncthreads();
         flip ^= 1;
+    }
+};
+
+// The workgroups sub0 .. gridDim.x - 1 of a grid team as a team of their own
+// (same interface), with their own barrier (the words from BAR_SUB, the same
+// protocol as GridTeam::sync) and partial buffers: the order-256 PSD block is
+// projected by them while workgroups 0 .. sub0 - 1 project the small blocks,
+// one each.  Only members call its sync and reduce.
+template <typename GT>
+struct PsdSubTeam {
+    static constexpr bool kBlock = false;
+    static constexpr bool kPsdTeam = true;
+    GT& g;
+    __device__ int blk() const { return (int)blockIdx.x - g.sub0; }
+    __device__ int nblk() const { return (int)gridDim.x - g.sub0; }
+    __device__ int rank() const { return blk() * blockDim.x + threadIdx.x; }
+    __device__ int size() const { return nblk() * blockDim.x; }
+    __device__ bool aborted() const { return g.aborted(); }
+    __device__ void sync() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        ++g.sub_k;
+        if (threadIdx.x == 0)
+            xcd_barrier(g.bar + BAR_SUB, g.grp, g.sub_members, g.sub_ngrp, g.sub_k, g.abort_flag, g.timeout_ticks);
+        __syncthreads();
+    }
+    __device__ void reduce(Shared& sh, int K) {
+        __syncthreads();
+        const int G = gridDim.x;
+        double* p = g.part + (size_t)(2 + g.sub_flip) * KMAX * G;
+        for (int k = threadIdx.x; k < K; k += blockDim.x) p[(size_t)k * G + blockIdx.x] = block_total(sh, k);
+        sync();
+        // every member sums the members' partials in the same fixed order
+        const int lane = threadIdx.x & (WAVE - 1);
+        const int nw = blockDim.x / WAVE;
+        for (int k = threadIdx.x / WAVE; k < K; k += nw) {
+            double s = 0.0;
+            for (int j = g.sub0 + lane; j < G; j += WAVE) s += p[(size_t)k * G + j];
+            s = wave_sum(s);
+            if (lane == 0) sh.out[k] = s;
+        }
+        __syncthreads();
+        g.sub_flip ^= 1;
     }
 };
 

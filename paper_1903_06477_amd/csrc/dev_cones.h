@@ -998,6 +998,43 @@ __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, doubl
 // Blocks of order above this go to the whole grid team.
 constexpr int kPsdTeamOrder = 64;
 
+// First workgroup of the PSD sub-team (PsdSubTeam) for a grid of G
+// workgroups: when an instance has both blocks up to kPsdTeamOrder and larger
+// ones, workgroups 0 .. s - 1 project the s small blocks, one each, while the
+// others project the large blocks together, at the same time.  0 (the small
+// blocks first, then the large ones by the whole grid) when there are no
+// small blocks, or when they would leave the large blocks fewer than half the
+// grid or too few workgroups for a round's subproblems and turns.
+__device__ inline int psd_sub_start(const ConeDev& K, int G) {
+    if (K.ns == 0 || K.psd_kmax <= kPsdTeamOrder) return 0;
+    int small = 0;
+    for (int c = 0; c < K.ns; ++c) small += K.sord[c] <= kPsdTeamOrder ? 1 : 0;
+    const int nt = (K.psd_kmax + kPsdTile - 1) / kPsdTile, np = (nt + (nt & 1)) / 2;
+    if (small == 0 || G - small < max(2 * np + 1, G / 2)) return 0;
+    return small;
+}
+
+// The blocks above kPsdTeamOrder, projected by team t (the grid team, or its
+// PSD sub-team).
+template <typename T2, typename In, typename Emit>
+__device__ __forceinline__ void psd_project_large(T2& t, Shared& sh, int n, const ConeDev& K, In& in, Emit& emit) {
+    double* tb = K.psd_team;                     // 4 kmax^2 matrices, then input / output
+    double* tin = tb + 4 * (size_t)K.psd_kmax * K.psd_kmax;
+    double* tout = tin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
+    for (int c = 0; c < K.ns; ++c) {
+        const int k = K.sord[c];
+        if (k <= kPsdTeamOrder) continue;
+        const int o = n + K.psd0 + K.soff[c];
+        const int len = k * (k + 1) / 2;
+        t.sync();
+        for (int e = t.rank(); e < len; e += t.size()) tin[e] = in(o + e);
+        t.sync();
+        psd_project_team(t, sh, k, tb, tin, tout, K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
+                         K.psd_warm ? K.psd_warm + c : nullptr);
+        for (int e = t.rank(); e < len; e += t.size()) emit(o + e, tout[e]);
+    }
+}
+
 // ---------------------------------------------------------------- Pi_C pass
 
 template <typename Team, typename In, typename Emit>
@@ -1060,7 +1097,16 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
                 vm = a + (size_t)K.psd_small * K.psd_small;
             }
         }
-        for (int c = tm.blk(); c < K.ns; c += tm.nblk()) {
+        // with a PSD sub-team, the small blocks go to the workgroups before it
+        int cstride = tm.nblk();
+        bool small_here = true;
+        if constexpr (kGrid && Team::kPsdTeam) {
+            if (tm.sub0 > 0) {
+                cstride = tm.sub0;
+                small_here = tm.blk() < tm.sub0;
+            }
+        }
+        for (int c = small_here ? tm.blk() : K.ns; c < K.ns; c += cstride) {
             const int k = K.sord[c];
             if (kGrid && k > kPsdTeamOrder) continue;
             const int o = n + K.psd0 + K.soff[c];
@@ -1076,21 +1122,13 @@ __device__ __forceinline__ void project_C(Team& tm, Shared& sh, int n, int N, co
         }
         if constexpr (kGrid && Team::kPsdTeam) {
             if (K.psd_kmax > kPsdTeamOrder) {
-                double* tb = K.psd_team;                     // 4 kmax^2 matrices, then input / output
-                double* tin = tb + 4 * (size_t)K.psd_kmax * K.psd_kmax;
-                double* tout = tin + (size_t)K.psd_kmax * (K.psd_kmax + 1) / 2;
-                for (int c = 0; c < K.ns; ++c) {
-                    const int k = K.sord[c];
-                    if (k <= kPsdTeamOrder) continue;
-                    const int o = n + K.psd0 + K.soff[c];
-                    const int len = k * (k + 1) / 2;
-                    tm.sync();
-                    for (int e = tm.rank(); e < len; e += tm.size()) tin[e] = in(o + e);
-                    tm.sync();
-                    psd_project_team(tm, sh, k, tb, tin, tout,
-                                     K.psd_vecs ? K.psd_vecs + (size_t)c * K.psd_kmax * K.psd_kmax : nullptr,
-                                     K.psd_warm ? K.psd_warm + c : nullptr);
-                    for (int e = tm.rank(); e < len; e += tm.size()) emit(o + e, tout[e]);
+                if (tm.sub0 > 0) {
+                    if (tm.blk() >= tm.sub0) {
+                        PsdSubTeam<Team> st{tm};
+                        psd_project_large(st, sh, n, K, in, emit);
+                    }
+                } else {
+                    psd_project_large(tm, sh, n, K, in, emit);
                 }
             }
         }

@@ -58,7 +58,7 @@ __device__ inline void grid_team_init(GridTeam<LDS, TL, PT>& tm, const Prob& P) 
     load_part(tm.mp[0], op_mat<TL>(P, 0), P.partA, blockIdx.x, LDS, &off);
     load_part(tm.mp[1], op_mat<TL>(P, 1), P.partAt, blockIdx.x, LDS, &off);
     __syncthreads();
-    tm.set_up();
+    tm.set_up(PT ? psd_sub_start(P.K, gridDim.x) : 0);
 }
 
 // stage_doubles: dynamic LDS of the launch (in doubles) for the CG's gathered
@@ -1420,7 +1420,7 @@ int alloc_work_vectors(sscs_work* w) {
     TRY(dmalloc(&w->res, 1));
     TRY(dmalloc(&w->bar, BAR_WORDS));
     TRY(dmalloc(&w->abort_flag, 1));
-    TRY(dmalloc(&w->part, 2 * (size_t)KMAX * w->max_grid));
+    TRY(dmalloc(&w->part, 4 * (size_t)KMAX * w->max_grid));   // two buffers for the grid, two for its PSD sub-team
     if (w->I.K.ns > 0) {
         const size_t k = w->I.K.psd_kmax;
         const size_t per = psd_scratch_doubles((int)k);

@@ -239,6 +239,20 @@ int sscs_batch_update_bc(sscs_batch *bt, const double *b_packed, const double *c
 int sscs_batch_solve(sscs_batch *bt, const double *u0_packed, double *x_packed,
                      double *y_packed, double *s_packed, sscs_info *infos);
 int sscs_batch_destroy(sscs_batch *bt);
+/* Tunes the batch's SpMV segment width (lanes per row; Sec. IV-A's products
+ * by A and A^T inside the linear step) by timing, per size class: instances
+ * are classed by the width the mean-row-length rule gives their A (a power
+ * of two in 1..64); each class runs alone for `iters` iterations (cold
+ * start, eps 0 so that none stops early) at that width times 1/4, 1/2, 1, 2
+ * and 4 (powers of two within 1..64, A^T's width scaled alike), twice each,
+ * and keeps the fastest; later sscs_batch_solve calls use the kept widths.
+ * The timing runs' results are discarded.  Outputs (host): *n_classes; for
+ * class c < min(cap, *n_classes), in increasing rule width: class_seg[c] =
+ * the rule's width, chosen_seg[c] = the kept width, ms[5 c + j] = the better
+ * time in ms of candidate j (factor 2^(j-2); -1 outside 1..64).  class_seg,
+ * chosen_seg and ms may be NULL.  Returns SSCS_E_INVALID for iters < 1. */
+int sscs_batch_autotune(sscs_batch *bt, int32_t iters, int32_t cap, int32_t *n_classes,
+                        int32_t *class_seg, int32_t *chosen_seg, double *ms);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): one

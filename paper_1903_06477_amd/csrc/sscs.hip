@@ -21,6 +21,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/sscs.h"
@@ -154,8 +155,8 @@ struct BatchInst {
 // measured fastest (two and four slower).
 template <typename TV>
 __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) k_solve_batch(
-    const BatchInst* __restrict__ insts, const int* __restrict__ order, int count, Params S, Result* res, int* queue,
-    int stage_doubles) {
+    const BatchInst* __restrict__ insts, const int* __restrict__ order, int count, int nq, Params S, Result* res,
+    int* queue, int stage_doubles) {
     __shared__ Shared sh;
     __shared__ Desc d;
     BlockTeam tm;
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     for (;;) {
         if (threadIdx.x == 0) {
             const int q = atomicAdd(queue, 1);
-            sh.qhead = q < count ? order[q] : count;
+            sh.qhead = q < nq ? order[q] : count;
         }
         __syncthreads();
         const int idx = __builtin_amdgcn_readfirstlane(sh.qhead);
@@ -1978,8 +1979,8 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
     HIP_TRY(hipMemsetAsync(bt->queue, 0, sizeof(int), bt->stream));
     Params S = make_params(bt->st, bt->ticks_per_s);
     const size_t lds = bt->stage * sizeof(double);
-    k_solve_batch<double><<<bt->grid, kBatchBlock, lds, bt->stream>>>(bt->d_insts, bt->order, bt->count, S,
-                                                                      bt->res, bt->queue, bt->stage);
+    k_solve_batch<double><<<bt->grid, kBatchBlock, lds, bt->stream>>>(bt->d_insts, bt->order, bt->count, bt->count,
+                                                                      S, bt->res, bt->queue, bt->stage);
     HIP_TRY(hipGetLastError());
     if (!dev) {
         HIP_TRY(hipMemcpyAsync(x_packed, dio_x, bt->tot_x * sizeof(double), hipMemcpyDeviceToHost, bt->stream));
@@ -1993,6 +1994,97 @@ int sscs_batch_solve(sscs_batch* bt, const double* u0_packed, double* x_packed, 
     if (infos)
         for (int i = 0; i < bt->count; ++i) fill_info(&infos[i], r[i], bt->setup_s, el);
     return SSCS_OK;
+}
+
+int sscs_batch_autotune(sscs_batch* bt, int32_t iters, int32_t cap, int32_t* n_classes, int32_t* class_seg,
+                        int32_t* chosen_seg, double* ms) {
+    if (!bt || iters < 1 || cap < 0 || !n_classes) return SSCS_E_INVALID;
+    // classes: the width the mean-row-length rule gives each instance's A
+    std::map<int, std::vector<int>> cls;
+    for (int i = 0; i < bt->count; ++i) cls[bt->inst[i].segA].push_back(i);
+    *n_classes = (int32_t)cls.size();
+    int* d_ord = nullptr;
+    TRY(dmalloc(&d_ord, bt->count));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int r = SSCS_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = SSCS_E_HIP;
+    // timing runs: cold starts, outputs to the staging buffers, a fixed
+    // iteration count (eps 0: no instance stops early)
+    sscs_settings st = bt->st;
+    st.max_iters = iters;
+    st.eps = 0.0;
+    st.max_time_s = 0.0;
+    const Params S = make_params(st, bt->ticks_per_s);
+    for (int i = 0; i < bt->count; ++i) {
+        Vecs& V = bt->h_insts[i].V;
+        V.u0 = nullptr;
+        V.out_x = bt->io + bt->tot_u + bt->off_x[i];
+        V.out_y = bt->io + bt->tot_u + bt->tot_x + bt->off_y[i];
+        V.out_s = bt->io + bt->tot_u + bt->tot_x + bt->tot_y + bt->off_y[i];
+        V.tr_res = nullptr; V.tr_kind = nullptr; V.tr_ls = nullptr; V.tr_cap = 0;
+        V.tr_eta = nullptr; V.tr_rsafe = nullptr;
+    }
+    auto set_width = [&](const std::vector<int>& ids, int f2) {   // width x 2^f2, within 1..64
+        for (int i : ids) {
+            const Inst& I = bt->inst[i];
+            auto scale = [&](int w) { return f2 >= 0 ? std::min(64, w << f2) : std::max(1, w >> -f2); };
+            bt->h_insts[i].P.A.seg = scale(I.segA);
+            bt->h_insts[i].P.At.seg = scale(I.segAt);
+        }
+    };
+    auto run = [&](const std::vector<int>& ids, float* out_ms) -> int {
+        HIP_TRY(hipMemcpyAsync(bt->d_insts, bt->h_insts.data(), bt->count * sizeof(BatchInst),
+                               hipMemcpyHostToDevice, bt->stream));
+        HIP_TRY(hipMemcpyAsync(d_ord, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice, bt->stream));
+        HIP_TRY(hipMemsetAsync(bt->queue, 0, sizeof(int), bt->stream));
+        HIP_TRY(hipEventRecord(e0, bt->stream));
+        k_solve_batch<double><<<bt->grid, kBatchBlock, bt->stage * sizeof(double), bt->stream>>>(
+            bt->d_insts, d_ord, bt->count, (int)ids.size(), S, bt->res, bt->queue, bt->stage);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(e1, bt->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(out_ms, e0, e1));
+        return SSCS_OK;
+    };
+    int c = 0;
+    for (auto it = cls.begin(); it != cls.end() && r == SSCS_OK; ++it, ++c) {
+        const int w0 = it->first;
+        const std::vector<int>& ids = it->second;
+        float t = 0.0f;
+        double best = 1e300;
+        int best_f = 0;
+        set_width(ids, 0);
+        r = run(ids, &t);                       // warm-up at the rule's width
+        for (int f2 = -2; f2 <= 2 && r == SSCS_OK; ++f2) {
+            const int w = f2 >= 0 ? (w0 << f2) : (w0 >> -f2);
+            const bool in = w >= 1 && w <= 64 && (f2 >= 0 || (w << -f2) == w0);
+            double tm = -1.0;
+            if (in) {                           // the better of two timed runs
+                set_width(ids, f2);
+                float t1 = 0.0f, t2 = 0.0f;
+                r = run(ids, &t1);
+                if (r == SSCS_OK) r = run(ids, &t2);
+                tm = std::min(t1, t2);
+                if (r == SSCS_OK && tm < best) { best = tm; best_f = f2; }
+            }
+            if (ms && c < cap) ms[c * 5 + (f2 + 2)] = tm;
+        }
+        set_width(ids, best_f);
+        if (c < cap) {
+            if (class_seg) class_seg[c] = w0;
+            if (chosen_seg) chosen_seg[c] = best_f >= 0 ? std::min(64, w0 << best_f) : std::max(1, w0 >> -best_f);
+        }
+    }
+    if (r == SSCS_OK) {
+        hipError_t e = hipMemcpyAsync(bt->d_insts, bt->h_insts.data(), bt->count * sizeof(BatchInst),
+                                      hipMemcpyHostToDevice, bt->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+        if (e != hipSuccess) { g_last_hip = hipGetErrorString(e); r = SSCS_E_HIP; }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(d_ord);
+    return r;
 }
 
 }  // extern "C"
@@ -2247,8 +2339,8 @@ int sscs_solve_noalloc(const sscs_data* data, const sscs_cone* cone, const sscs_
         HIP_TRY(hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dv));
         Params P = make_params(*st, rate > 0 ? rate * 1000.0 : 1e8);
         const int stage = stage_doubles((long long)n + m);
-        k_solve_batch<double><<<1, kBatchBlock, stage * sizeof(double), strm>>>(d_bi, d_order, 1, P, d_res, d_queue,
-                                                                                stage);
+        k_solve_batch<double><<<1, kBatchBlock, stage * sizeof(double), strm>>>(d_bi, d_order, 1, 1, P, d_res,
+                                                                                d_queue, stage);
         HIP_TRY(hipGetLastError());
         if (!dev) {
             HIP_TRY(hipMemcpyAsync(x, d_io + N, n * sizeof(double), hipMemcpyDeviceToHost, strm));

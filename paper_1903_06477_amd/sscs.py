@@ -62,7 +62,7 @@ class _Info(ctypes.Structure):
 EXPORTS = ["sscs_default_settings", "sscs_create", "sscs_solve", "sscs_update_settings", "sscs_update_bc",
            "sscs_destroy", "sscs_linear_step", "sscs_project_dual_cone", "sscs_residual", "sscs_spmv",
            "sscs_spmv_bench", "sscs_get_trace", "sscs_batch_create", "sscs_batch_update_bc",
-           "sscs_batch_solve", "sscs_batch_destroy", "sscs_solve_noalloc", "sscs_error_string",
+           "sscs_batch_solve", "sscs_batch_destroy", "sscs_batch_autotune", "sscs_solve_noalloc", "sscs_error_string",
            "sscs_mlp_create", "sscs_mlp_destroy", "sscs_mlp_set_params", "sscs_mlp_get_params",
            "sscs_mlp_forward", "sscs_mlp_train_step", "sscs_mlp_gradients", "sscs_mlp_gemm_nt",
            "sscs_assemble_u0"]
@@ -98,6 +98,8 @@ def lib():
         L.sscs_batch_update_bc.argtypes = [vp, vp, vp]
         L.sscs_batch_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(_Info)]
         L.sscs_batch_destroy.argtypes = [vp]
+        L.sscs_batch_autotune.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, vp,
+                                          vp]
         L.sscs_solve_noalloc.argtypes = [ctypes.POINTER(_Data), ctypes.POINTER(_Cone), ctypes.POINTER(_Settings), vp,
                                          vp, vp, vp, vp, ctypes.POINTER(_Info)]
         _lib = L
@@ -369,6 +371,20 @@ class BatchSolver:
         infos = (_Info * self.count)()
         _check(lib().sscs_batch_solve(self._h, _vptr(u0_packed), _vptr(x), _vptr(y), _vptr(s), infos))
         return x, y, s, [_info_dict(infos[i]) for i in range(self.count)]
+
+    def autotune(self, iters: int = 20, cap: int = 8):
+        """Tunes the SpMV segment width per size class by timing
+        (sscs_batch_autotune); returns one dict per class: the rule's width,
+        the kept width and the candidates' times in ms (factor 2^(j-2), -1
+        where the width falls outside 1..64)."""
+        n = ctypes.c_int32()
+        cls, chosen = np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+        ms = np.zeros(5 * cap)
+        _check(lib().sscs_batch_autotune(self._h, int(iters), int(cap), ctypes.byref(n), _vptr(cls), _vptr(chosen),
+                                         _vptr(ms)))
+        k = min(cap, n.value)
+        return [{"class_seg": int(cls[c]), "chosen_seg": int(chosen[c]), "ms": [float(v) for v in ms[5 * c:5 * c + 5]]}
+                for c in range(k)]
 
     def split(self, x, y, s):
         """Per-instance views of packed outputs."""

@@ -18,9 +18,10 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_roofline_byte_model():
-    info = {"iters": 9, "k0": 4, "cg_iters": 30, "backtracks": 2}
-    # 30 CG iterations + 2 per linear step (10 u steps + 5 d steps) + 10 termination checks
-    assert bench.op_units(info) == 30 + 2 * 15 + 10
+    info = {"iters": 9, "k0": 4, "k1": 3, "cg_iters": 30, "backtracks": 2}
+    # 30 CG iterations + 1 per linear step (10 u steps + 5 d steps), less a
+    # half per u step prestarted after a K1 step (3), + 10 termination checks
+    assert bench.op_units(info) == 30 + 15 - 0.5 * 3 + 10
     n, m, nnz = 20, 50, 100
     per_spmv = nnz * 12 + 4 * (m + 1) + 8 * (m + n)
     assert bench.spmv_bytes(nnz, m, n) == per_spmv

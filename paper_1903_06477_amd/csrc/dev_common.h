@@ -169,6 +169,45 @@ __device__ __forceinline__ bool spin_until(unsigned long long* addr, unsigned lo
     return true;
 }
 
+// After a team reduction's barrier: sh.out[k] = sum over j in [j0, G) of
+// p[k * G + j], k < K, summed by every workgroup in the same fixed order (lane
+// l adds entries l, l + 64, ... in turn, then the wavefront sum).  A
+// wavefront issues the loads of kR sums by kJ entries per lane before adding
+// any, so they are in flight together: after the barrier the partials come
+// from the memory-side cache, and one round trip per sum in turn cost
+// microseconds.  Out of line, so its registers stay out of the callers'.
+__device__ __noinline__ void sum_partials(Shared& sh, const double* p, int K, int G, int j0) {
+    constexpr int kR = 3, kJ = 4;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    for (int k0 = w; k0 < K; k0 += kR * nw) {
+        double acc[kR];
+#pragma unroll
+        for (int r = 0; r < kR; ++r) acc[r] = 0.0;
+        for (int jb = j0 + lane; jb < G; jb += kJ * WAVE) {
+            double v[kR][kJ];
+#pragma unroll
+            for (int r = 0; r < kR; ++r)
+#pragma unroll
+                for (int q = 0; q < kJ; ++q) {
+                    const int k = k0 + r * nw, j = jb + q * WAVE;
+                    v[r][q] = (k < K && j < G) ? p[(size_t)k * G + j] : 0.0;
+                }
+#pragma unroll
+            for (int r = 0; r < kR; ++r)
+#pragma unroll
+                for (int q = 0; q < kJ; ++q)
+                    if (jb + q * WAVE < G) acc[r] += v[r][q];
+        }
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int k = k0 + r * nw;
+            const double t = wave_sum(acc[r]);
+            if (k < K && lane == 0) sh.out[k] = t;
+        }
+    }
+}
+
 // Thread 0's part of the k-th barrier among a team with `members` workgroups
 // on this workgroup's XCD `grp` and `ngrp` XCDs in all, on the words from
 // `base` (laid out as at BAR_WORDS); see GridTeam::sync.
@@ -302,15 +341,7 @@ struct GridTeam {
         double* p = part + (size_t)flip * KMAX * G;
         for (int k = threadIdx.x; k < K; k += blockDim.x) p[(size_t)k * G + blockIdx.x] = block_total(sh, k);
         sync();
-        // every workgroup sums all partials in the same fixed order
-        const int lane = threadIdx.x & (WAVE - 1);
-        const int nw = blockDim.x / WAVE;
-        for (int k = threadIdx.x / WAVE; k < K; k += nw) {
-            double s = 0.0;
-            for (int j = lane; j < G; j += WAVE) s += p[(size_t)k * G + j];
-            s = wave_sum(s);
-            if (lane == 0) sh.out[k] = s;
-        }
+        sum_partials(sh, p, K, G, 0);          // every workgroup, the same fixed order
         __syncthreads();
         flip ^= 1;
     }
@@ -345,15 +376,7 @@ struct PsdSubTeam {
         double* p = g.part + (size_t)(2 + g.sub_flip) * KMAX * G;
         for (int k = threadIdx.x; k < K; k += blockDim.x) p[(size_t)k * G + blockIdx.x] = block_total(sh, k);
         sync();
-        // every member sums the members' partials in the same fixed order
-        const int lane = threadIdx.x & (WAVE - 1);
-        const int nw = blockDim.x / WAVE;
-        for (int k = threadIdx.x / WAVE; k < K; k += nw) {
-            double s = 0.0;
-            for (int j = g.sub0 + lane; j < G; j += WAVE) s += p[(size_t)k * G + j];
-            s = wave_sum(s);
-            if (lane == 0) sh.out[k] = s;
-        }
+        sum_partials(sh, p, K, G, g.sub0);     // every member, the same fixed order
         __syncthreads();
         g.sub_flip ^= 1;
     }

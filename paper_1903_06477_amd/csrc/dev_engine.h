@@ -837,10 +837,10 @@ __device__ __noinline__ void termination_aa_pass(Team& tm, Shared& sh, const Pro
     const int slot = aa_push_dots(tm, sh, V, S, ds, P.N, base);
     const int k = ds.aa_k;
     tm.reduce(sh, base + aa_slots(k, slot));
-    if (threadIdx.x == 0) {
-        if (check) term_finish(sh, P, S, tau);
-        if (k > 0) aa_gram(sh, S, k, slot, base);
-    }
+    // the two serial parts (disjoint LDS fields) on different wavefronts, at
+    // the same time
+    if (threadIdx.x == 0 && check) term_finish(sh, P, S, tau);
+    if (threadIdx.x == (blockDim.x > WAVE ? WAVE : 0) && k > 0) aa_gram(sh, S, k, slot, base);
     __syncthreads();
 }
 

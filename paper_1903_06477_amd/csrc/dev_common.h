@@ -448,8 +448,19 @@ __device__ __forceinline__ void spmv_gather(Team& tm, const Csr<T>& M, Gx&& gx, 
 // f(r, sum_k v[k] gx(ci[k])) is called by the last lane of the segment that
 // owns r.  Same segment scheme and ROWS-way batching as spmv_gather, with the
 // row range local to the workgroup and the operator read from LDS when cached.
-template <int ROWS, bool LDS, typename T, typename Gx, typename F>
-__device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& mp, Gx&& gx, F&& f) {
+// pre(r), when given, is called by the reporting lane when row r is set up,
+// before its gathers, and its value is passed on as f(r, sum, pre(r)): the
+// per-row operands of f (the vectors it combines with the row's sum) are then
+// loaded while the gathers are in flight, not in a second round trip after
+// them (f's stores keep the compiler from moving later rows' loads above
+// earlier rows' f).
+struct NoPre {
+    __device__ int operator()(int) const { return 0; }
+};
+
+template <int ROWS, bool LDS, typename T, typename Gx, typename Pre, typename F>
+__device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& mp, Gx&& gx, Pre&& pre, F&& f) {
+    using PV = decltype(pre(0));
     const int S = M.seg;
     const int seg = threadIdx.x / S;
     const int nseg = blockDim.x / S;
@@ -462,6 +473,7 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
         int kb[ROWS], ke[ROWS];
         double acc[ROWS];
         bool own[ROWS];
+        PV pv[ROWS];
 #pragma unroll
         for (int q = 0; q < ROWS; ++q) {
             const int l = l0 + q * nseg;
@@ -478,6 +490,7 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
             kb[q] = own[q] ? b + ls : 0;
             ke[q] = own[q] ? e : 0;
             acc[q] = 0.0;
+            pv[q] = (own[q] && ls == S - 1) ? pre(mp.r0 + l) : PV{};
         }
         bool more = true;
         while (more) {
@@ -498,7 +511,7 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
             double a = acc[q];
             a = group_sum(a, S);
             const int l = l0 + q * nseg;
-            if (ls == S - 1 && own[q]) f(mp.r0 + l, a);
+            if (ls == S - 1 && own[q]) f(mp.r0 + l, a, pv[q]);
         }
     }
     if (M.nlong > 0) {
@@ -525,7 +538,7 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
             if (threadIdx.x == 0) {
                 double t = 0.0;
                 for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) t += lred[w];
-                f(r, t);
+                f(r, t, pre(r));
             }
             __syncthreads();
         }
@@ -536,7 +549,14 @@ __device__ __forceinline__ void spmv_part_impl(const Csr<T>& M, const MatPart& m
 template <int ROWS, typename Team, typename T, typename Gx, typename F>
 __device__ __forceinline__ void spmv_part(Team& tm, const Csr<T>& M, int which, Gx&& gx, F&& f) {
     constexpr bool kUse = Team::kLds && std::is_same<T, typename Team::lds_t>::value;
-    spmv_part_impl<ROWS, kUse>(M, tm.mp[which], gx, f);
+    spmv_part_impl<ROWS, kUse>(M, tm.mp[which], gx, NoPre{}, [&](int r, double s, int) { f(r, s); });
+}
+
+// The same with per-row operands prefetched: f(r, sum, pre(r)).
+template <int ROWS, typename Team, typename T, typename Gx, typename Pre, typename F>
+__device__ __forceinline__ void spmv_part_pre(Team& tm, const Csr<T>& M, int which, Gx&& gx, Pre&& pre, F&& f) {
+    constexpr bool kUse = Team::kLds && std::is_same<T, typename Team::lds_t>::value;
+    spmv_part_impl<ROWS, kUse>(M, tm.mp[which], gx, pre, f);
 }
 
 // Fills a workgroup's MatPart for rows [part[b], part[b+1]) and, when `cache`

@@ -321,6 +321,14 @@ __device__ __noinline__ int solve_direct(Team& tm, Shared& sh, const Prob& P, co
     return 0;
 }
 
+// Per-row operands a pass prefetches ahead of the row's gathers (spmv_part_pre).
+struct Row3 {
+    double a, b, c;
+};
+struct Row4 {
+    double a, b, c, d;
+};
+
 template <typename TV, typename Team>
 __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const Vecs& V, const double* r, double* out,
                        double* xw, double tol, int maxit, double thr_abs = 0.0, double* thr_used = nullptr,
@@ -371,12 +379,25 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
     double* const B = rb ? rb : V.cg_b;
     double a_bb = bb_part;
     if (!prestarted)
-        spmv_part<1>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; }, [&](int j, double s) {
-            const double bj = r[j] - s;
-            B[j] = bj;
-            a_bb += bj * bj;
-            if (use_q) start(j, bj - q[j]);
-        });
+        spmv_part_pre<4>(tm, P.At, 1, [&](int c_) { return (r + n)[c_]; },
+                         [&](int j) { return Row3{r[j], use_q ? q[j] : 0.0, use_q ? P.dinv[j] : 0.0}; },
+                         [&](int j, double s, const Row3& o) {     // o = (r_j, q_j, D_j)
+                             const double bj = o.a - s;
+                             B[j] = bj;
+                             a_bb += bj * bj;
+                             if (use_q) {                  // start(j, bj - q_j) with D_j prefetched
+                                 const double rj = bj - o.b;
+                                 V.cg_r[j] = rj;
+                                 V.cg_s[j] = 0.0;
+                                 V.cg_u[j] = 0.0;
+                                 V.cg_w[j] = 0.0;
+                                 V.cg_p[j] = 0.0;
+                                 double* g = V.cg_g[cur] + 4 * (size_t)j;
+                                 g[0] = o.c * rj;
+                                 g[1] = 0.0;
+                                 g[2] = 0.0;
+                             }
+                         });
     double thr = 0.0;
     int it = 0;
     const int rounds = cg_rounds<TV>();
@@ -422,17 +443,19 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
             // ---- phase Y
             double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
             double a_rw = 0.0, a_rs = 0.0, a_ww = 0.0, a_ws = 0.0, a_ss = 0.0;
-            spmv_part<4>(tm, KAt, 1, [&](int c) { return V.cg_t[c]; }, [&](int j, double s) {
-                const double uj = V.cg_u[j];
-                const double rj = V.cg_r[j];
+            spmv_part_pre<4>(tm, KAt, 1, [&](int c) { return V.cg_t[c]; },
+                             [&](int j) { return Row4{V.cg_u[j], V.cg_r[j], P.dinv[j], kPred ? V.cg_s[j] : 0.0}; },
+                             [&](int j, double s, const Row4& o) {     // o = (u_j, r_j, D_j, s_j)
+                const double uj = o.a;
+                const double rj = o.b;
                 const double wj = uj + s;
                 V.cg_w[j] = wj;
-                V.cg_g[cur][4 * (size_t)j + 2] = P.dinv[j] * wj;
+                V.cg_g[cur][4 * (size_t)j + 2] = o.c * wj;
                 a_g += rj * uj;
                 a_d += wj * uj;
                 a_rr += rj * rj;
                 if constexpr (kPred) {
-                    const double sj = V.cg_s[j];
+                    const double sj = o.d;
                     a_rw += rj * wj;
                     a_rs += rj * sj;
                     a_ww += wj * wj;
@@ -498,16 +521,16 @@ __device__ __noinline__ int solve_M(Team& tm, Shared& sh, const Prob& P, const V
     // column records (the owners overwrite x in this pass), p from its vector.
     double a_hp = 0.0;
     const double* gf = V.cg_g[cur];
-    spmv_part<1>(tm, P.A, 0, [&](int c_) {
+    spmv_part_pre<4>(tm, P.A, 0, [&](int c_) {
         if (pend) {
             const double* g = gf + 4 * (size_t)c_;
             return g[3] + fa * (g[0] + fb * V.cg_p[c_]);
         }
         return xw[c_];
-    }, [&](int i, double s) {
-        const double py = r[n + i] + s;
+    }, [&](int i) { return double2{r[n + i], P.b[i]}; }, [&](int i, double s, const double2& rb) {
+        const double py = rb.x + s;
         out[n + i] = py;
-        a_hp += P.b[i] * py;
+        a_hp += rb.y * py;
     });
     for (int j = tm.rank(); j < n; j += tm.size()) {
         double xj = xw[j], rj = V.cg_r[j];
@@ -620,23 +643,26 @@ __device__ __forceinline__ double term_partials(Team& tm, Shared& sh, const Prob
     const double tau = V.ub[P.N - 1];
     double a_p = 0.0, a_u = 0.0, a_d = 0.0, a_i = 0.0, a_cx = 0.0, a_by = 0.0;
     // <b, y> and <c, x> ride along with the products: every row of A and of
-    // A^T is reported exactly once
-    spmv_part<1>(tm, P.A, 0, [&](int c_) { return V.ub[c_]; }, [&](int i, double s) {
-        const double yb = V.ub[n + i];
-        const double sig = scs ? yb - V.u[n + i] : yb - 2.0 * V.ut[n + i] + V.u[n + i];
+    // A^T is reported exactly once; each row's operands are prefetched
+    spmv_part_pre<4>(tm, P.A, 0, [&](int c_) { return V.ub[c_]; },
+                     [&](int i) { return Row4{V.ub[n + i], scs ? 0.0 : V.ut[n + i], V.u[n + i], P.b[i]}; },
+                     [&](int i, double s, const Row4& o) {     // o = (ybar_i, ytilde_i, y_i, b_i)
+        const double yb = o.a;
+        const double sig = scs ? yb - o.c : yb - 2.0 * o.b + o.c;
         const double v = s + sig;
         a_u += v * v;
-        const double bi = P.b[i];
+        const double bi = o.d;
         const double w = v - bi * tau;
         a_p += w * w;
         a_by += bi * yb;
     });
-    spmv_part<1>(tm, P.At, 1, [&](int c_) { return V.ub[n + c_]; }, [&](int j, double s) {
+    spmv_part_pre<4>(tm, P.At, 1, [&](int c_) { return V.ub[n + c_]; },
+                     [&](int j) { return double2{P.c[j], V.ub[j]}; }, [&](int j, double s, const double2& o) {   // (c_j, xbar_j)
         a_i += s * s;
-        const double cj = P.c[j];
+        const double cj = o.x;
         const double w = s + cj * tau;
         a_d += w * w;
-        a_cx += cj * V.ub[j];
+        a_cx += cj * o.y;
     });
     put(sh, 0, a_p);
     put(sh, 1, a_u);

@@ -72,17 +72,24 @@ __device__ __forceinline__ double wave_sum(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// Writes the wave-sum of v into slot k of the per-wave partials.
+// A double in LDS (address space 3).
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// Writes the wave-sum of v into slot k of the per-wave partials.  (Shared
+// always lives in LDS: the kernels declare it __shared__.  Its fields are
+// reached through LDS-typed pointers where the callers hold a plain
+// reference, which would otherwise compile to generic accesses.)
 __device__ __forceinline__ void put(Shared& sh, int k, double v) {
     v = group_sum(v, WAVE);
-    if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) sh.red[k * NWMAX + (threadIdx.x / WAVE)] = v;
+    if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) ((lds_f64*)sh.red)[k * NWMAX + (threadIdx.x / WAVE)] = v;
 }
 
 // Sums the per-wave partials of slot k in wave order.
 __device__ __forceinline__ double block_total(const Shared& sh, int k) {
     const int nw = blockDim.x / WAVE;
+    const lds_f64* red = (const lds_f64*)sh.red;
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh.red[k * NWMAX + w];
+    for (int w = 0; w < nw; ++w) s += red[k * NWMAX + w];
     return s;
 }
 
@@ -101,7 +108,6 @@ extern __shared__ __attribute__((aligned(16))) double sscs_dyn_lds[];
 // descriptors) are cast back to LDS pointers where the code knows they live
 // there: LDS instructions then replace flat ones, which take the longer
 // vector-memory path even for LDS addresses.
-typedef __attribute__((address_space(3))) double lds_f64;
 template <bool L> struct VecPtr { using type = double*; };
 template <> struct VecPtr<true> { using type = lds_f64*; };
 template <bool L>

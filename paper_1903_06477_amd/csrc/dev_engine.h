@@ -677,22 +677,23 @@ __device__ __forceinline__ double term_partials(Team& tm, Shared& sh, const Prob
 // The measures and status from the reduced slots 0..6 into sh.term (thread 0).
 __device__ __forceinline__ void term_finish(Shared& sh, const Prob& P, const Params& S, double tau) {
     Term T;
-    const double cx = sh.out[4], by = sh.out[5];
+    const auto out = vec_at<true>(sh.out);     // LDS-typed (see small_chol_solve)
+    const double cx = out[4], by = out[5];
     T.tau = tau;
     T.cx = cx;
     T.by = by;
-    T.timeout = sh.out[6] > 0.0;
+    T.timeout = out[6] > 0.0;
     T.pr = T.dr = T.gap = T.ic = T.uc = INFINITY;
     T.pobj = T.dobj = NAN;
     if (tau > 0.0) {
-        T.pr = sqrt(sh.out[0]) / tau / (1.0 + P.nb);
-        T.dr = sqrt(sh.out[2]) / tau / (1.0 + P.nc);
+        T.pr = sqrt(out[0]) / tau / (1.0 + P.nb);
+        T.dr = sqrt(out[2]) / tau / (1.0 + P.nc);
         T.gap = fabs(cx + by) / tau / (1.0 + fabs(cx) / tau + fabs(by) / tau);
         T.pobj = cx / tau;
         T.dobj = -by / tau;
     }
-    if (by < 0.0) T.ic = P.nb * sqrt(sh.out[3]) / (-by);
-    if (cx < 0.0) T.uc = P.nc * sqrt(sh.out[1]) / (-cx);
+    if (by < 0.0) T.ic = P.nb * sqrt(out[3]) / (-by);
+    if (cx < 0.0) T.uc = P.nc * sqrt(out[1]) / (-cx);
     T.status = 0;
     if (tau > 0.0 && T.pr <= S.eps && T.dr <= S.eps && T.gap <= S.eps) T.status = ST_SOLVED;
     else if (T.ic < S.eps) T.status = ST_INFEASIBLE;
@@ -711,9 +712,18 @@ __device__ __noinline__ void termination_pass(Team& tm, Shared& sh, const Prob& 
 
 // ------------------------------------------------------------------ directions
 
-// Solves (G + mu I) t = rhs (k x k, SPD) by Cholesky into t; false if not finite.
-__device__ inline bool small_chol_solve(const double* G, int ld, int k, double mu, const double* rhs, double* t,
-                                        double* L) {
+// Solves (G + mu I) t = rhs (k x k, SPD) by Cholesky into t; false if not
+// finite.  Every array is in LDS (the workgroup's Shared); they are reached
+// through LDS-typed pointers, since a generic pointer would send each of the
+// routine's dependent accesses down the vector-memory path.  The forward
+// substitution's result is kept in t and overwritten in place by the
+// backward one.
+__device__ inline bool small_chol_solve(const double* G_, int ld, int k, double mu, const double* rhs_, double* t_,
+                                        double* L_) {
+    const auto G = vec_at<true>(G_);
+    const auto rhs = vec_at<true>(rhs_);
+    const auto t = vec_at<true>(t_);
+    const auto L = vec_at<true>(L_);
     for (int i = 0; i < k; ++i)
         for (int j = 0; j <= i; ++j) {
             double s = G[i * ld + j] + (i == j ? mu : 0.0);
@@ -725,14 +735,13 @@ __device__ inline bool small_chol_solve(const double* G, int ld, int k, double m
                 L[i * MEMMAX + j] = s / L[j * MEMMAX + j];
             }
         }
-    double y[MEMMAX];
     for (int i = 0; i < k; ++i) {
         double s = rhs[i];
-        for (int e = 0; e < i; ++e) s -= L[i * MEMMAX + e] * y[e];
-        y[i] = s / L[i * MEMMAX + i];
+        for (int e = 0; e < i; ++e) s -= L[i * MEMMAX + e] * t[e];
+        t[i] = s / L[i * MEMMAX + i];
     }
     for (int i = k - 1; i >= 0; --i) {
-        double s = y[i];
+        double s = t[i];
         for (int e = i + 1; e < k; ++e) s -= L[e * MEMMAX + i] * t[e];
         t[i] = s / L[i * MEMMAX + i];
         if (!isfinite(t[i])) return false;
@@ -817,16 +826,18 @@ __device__ __forceinline__ int aa_slots(int k, int slot) { return k == 0 ? 0 : (
 // (2) Thread 0: the Gram matrix's new column and t from the reduced slots
 // base.. ((Xi^T Xi + mu I) t = Xi^T Ru, by Cholesky) into sh.coef.
 __device__ __forceinline__ void aa_gram(Shared& sh, const Params& S, int k, int slot, int base) {
+    const auto G = vec_at<true>(sh.G);          // LDS-typed (see small_chol_solve)
+    const auto out = vec_at<true>(sh.out);
     if (slot >= 0)
         for (int i = 0; i < k; ++i) {
-            sh.G[slot * MEMMAX + i] = sh.out[base + k + i];
-            sh.G[i * MEMMAX + slot] = sh.out[base + k + i];
+            G[slot * MEMMAX + i] = out[base + k + i];
+            G[i * MEMMAX + slot] = out[base + k + i];
         }
     double tr = 0.0;
-    for (int i = 0; i < k; ++i) tr += sh.G[i * MEMMAX + i];
+    for (int i = 0; i < k; ++i) tr += G[i * MEMMAX + i];
     const bool ok = small_chol_solve(sh.G, MEMMAX, k, S.aa_reg * tr / k, sh.out + base, sh.coef, sh.L);
     if (!ok)
-        for (int i = 0; i < k; ++i) sh.coef[i] = 0.0;
+        for (int i = 0; i < k; ++i) vec_at<true>(sh.coef)[i] = 0.0;
 }
 
 // (3) d = -Ru - sum_i (Z_i - Y_i) t_i (d = -Ru with an empty memory); a K0

@@ -524,12 +524,13 @@ __device__ __noinline__ void psd_project_block(Team& tm, int k, double* a, doubl
     __syncthreads();
 }
 
-// The same projection computed by a whole grid team, for blocks too large for
-// one workgroup to turn over quickly (the order-256 block of the sparse-PCA
-// instance): a two-sided *block* Jacobi method.  The indices are cut into
-// tiles of kPsdTile; each round pairs the tiles round-robin, workgroup w
-// diagonalises (approximately: one inner sweep) pair w's 2-tile principal
-// submatrix in LDS, producing an orthogonal Q_w, and the team turns A into
+// The same projection computed by a team of workgroups (the grid, or its PSD
+// sub-team), for blocks too large for one workgroup to turn over quickly (the
+// order-256 block of the sparse-PCA instance): a two-sided *block* Jacobi
+// method.  The indices are cut into tiles of kPsdTile; each round pairs the
+// tiles round-robin, one workgroup per pair diagonalises (approximately: one
+// inner sweep) the pair's 2-tile principal submatrix in LDS, producing an
+// orthogonal Q_w, and the team turns A into
 // Q^T A Q and Vt into Q^T Vt, block by block.  One team barrier per round and
 // k/kPsdTile - 1 rounds per sweep, instead of one barrier per round over
 // k - 1 rounds (the round structure is described at psd_project_team).  Warm
@@ -873,11 +874,12 @@ __device__ __noinline__ void psd_team_recon(int blk, int nblk, int k, const doub
 // `buf` holds 4 k*k doubles (matrix, its turned copy, Vt and its turned copy);
 // `in` (packed input, filled by the caller) and `outv` are contiguous, with
 // room for two rounds' Q matrices (k (k + 1) doubles in all, k > 2 kPsdTile).
-// A round is: (1) each tile pair's submatrix diagonalised by one workgroup,
-// (2) the pairs' block rows of the matrix and of Vt turned, (3) the block
-// columns turned.  Step (1) of the next round builds its submatrices from the
-// output of (2) and this round's Q directly, so it runs alongside (3): two
-// grid barriers per round.
+// A round is one phase and one team barrier: (a) every 16 x 16 output block
+// of Q^T A Q turned from its input block and the two pairs' Q, (b) the pairs'
+// rows of Vt turned, and, at the same time on np workgroups of their own,
+// (c) the next round's subproblems built from A and this round's Q directly
+// and diagonalised (psd_next_sub).  `Team` is the grid team or its PSD
+// sub-team.
 template <typename Team>
 __device__ __noinline__ void psd_project_team(Team& tm, Shared& sh, int k, double* buf, double* in, double* outv, double* V0,
                                  int* warm) {

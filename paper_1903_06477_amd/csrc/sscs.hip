@@ -705,9 +705,6 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Lanes per row of the row-segmented SpMV: the smallest power of two that
-// gives each lane about `div` nonzeros of a mean-length row (more rows in
-// flight per wavefront, several independent loads per lane).
 // LDS (in doubles) the one-workgroup kernels stage the CG's gathered
 // vectors in, for an instance with `entries` = n + m; 0 when they do not fit
 // (the CG then gathers from global memory).  The dynamic-LDS limit is raised
@@ -748,6 +745,10 @@ int small_lds_budget() {
     return budget;
 }
 
+// Lanes per row of the row-segmented SpMV (the mean-row-length rule): the
+// smallest power of two that gives each lane about `div` nonzeros of a
+// mean-length row (more rows in flight per wavefront, several independent
+// loads per lane); sscs_batch_autotune can replace it per size class.
 int pow2_seg(double avg) {
     const double div = 4.0;
     int s = 1;

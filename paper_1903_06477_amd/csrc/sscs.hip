@@ -555,10 +555,21 @@ __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restr
     }
 }
 
+// y[r] = sum over panels p in order of part[p rows + r]; a thread loads eight
+// panels' partials before adding them (the same additions in the same order),
+// so its loads are in flight together instead of one round trip per panel.
 __global__ void k_panel_sum(const double* __restrict__ part, int P, int rows, double* __restrict__ y) {
+    constexpr int kB = 8;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         double a = 0.0;
-        for (int p = 0; p < P; ++p) a += part[(size_t)p * rows + r];
+        for (int p0 = 0; p0 < P; p0 += kB) {
+            double v[kB];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) v[q] = p0 + q < P ? part[(size_t)(p0 + q) * rows + r] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kB; ++q)
+                if (p0 + q < P) a += v[q];
+        }
         y[r] = a;
     }
 }

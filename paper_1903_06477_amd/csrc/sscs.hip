@@ -520,18 +520,21 @@ __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __re
 // (ci, v), column indices relative to the panel (one panel: the CSR itself).
 // With one panel the sums go to y; with several, row r's partial sum of panel
 // p goes to part[p rows + r], summed over the panels in order by k_panel_sum.
+// With R = 1 a segment walks its rows one at a time, the next row's pointers
+// loaded before the current row's entries, and takes a row's entries U steps
+// at a time (each lane's U loads in flight together, at constant offsets from
+// one address; the steps left over go one by one, in the same order).
+// Measured on a 5e6 x 2e4 operator with 20 entries per row: S = 4, U = 5 (a
+// row's 20 entries in one batch) 249 us against 306-321 us for S = 8 one
+// step at a time; loads past a row's end made branch-free, by clamping or by
+// branches, cost more than the batch gains (302 us).
 // With R > 1 a segment takes R of its rows at a time: each step loads the
-// next entry of all of them (at index min(k, nnz - 1) for a row already done,
-// so the loads need no branch and are in flight together), then adds those of
-// the rows still going (the same additions in the same order as one row at a
-// time).
-// Measured on the 1e8-nonzero operator: with several panels (A^T, 245
-// panels) four rows take 454 -> 408 us; with one panel (A) one row at a time
-// is faster (309 against 325 us), the loads past a row's end costing more
-// than the overlap gains.
+// next entry of all of them (at index min(k, nnz - 1) for a row already done),
+// then adds those of the rows still going (the same additions in the same
+// order as one row at a time).
 constexpr int kPanelCols = 20480;      // 160 KB of FP64 entries per panel
 constexpr int kPanelThreads = 1024;
-template <int S, int R>
+template <int S, int U, int R>
 __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restrict__ rp, const int* __restrict__ ci,
                                                               const double* __restrict__ v, int rows, int cols,
                                                               const int* __restrict__ items, int nitems, int P, int pc,
@@ -551,16 +554,40 @@ __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restr
         }
         const int* prp = rp + (size_t)p * rows;
         if constexpr (R == 1) {
-            for (int r = c * nseg + seg; r < rows; r += C * nseg) {
-                const int kb = prp[r], ke = prp[r + 1];
+            const int step = C * nseg;
+            int r = c * nseg + seg, kb = 0, ke = 0;
+            if (r < rows) {
+                kb = prp[r];
+                ke = prp[r + 1];
+            }
+            for (; r < rows; r += step) {
+                int kbn = 0, ken = 0;                // the next row's pointers, loaded ahead
+                if (r + step < rows) {
+                    kbn = prp[r + step];
+                    ken = prp[r + step + 1];
+                }
                 double acc = 0.0;
-                for (int k = kb + ls; k < ke; k += S) acc += v[k] * xs[ci[k]];
+                int k = kb + ls;
+                for (; k < ke - (U - 1) * S; k += U * S) {   // U steps whose loads are in flight together
+                    double vu[U];
+                    int cu[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        vu[u] = v[k + u * S];
+                        cu[u] = ci[k + u * S];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) acc += vu[u] * xs[cu[u]];
+                }
+                for (; k < ke; k += S) acc += v[k] * xs[ci[k]];
 #pragma unroll
                 for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
                 if (ls == 0) {
                     if (P == 1) y[r] = acc;
                     else part[(size_t)p * rows + r] = acc;
                 }
+                kb = kbn;
+                ke = ken;
             }
             continue;
         }
@@ -1165,7 +1192,7 @@ Vecs carve(double* base, int n, int m, int mem) {
 // stand-alone product).
 struct PanelPlan {
     bool built = false, use = false;
-    int P = 1, pc = 0, S = 8, nitems = 0;
+    int P = 1, pc = 0, S = 8, U = 1, R = 1, nitems = 0;
     int* items = nullptr;
     int* prp = nullptr;          // panel-major row pointers (P rows + 1), several panels
     int* pci = nullptr;          // panel-major column indices (panel-relative)
@@ -1239,17 +1266,32 @@ bool team_psd(const Inst& I) { return I.K.psd_kmax > kPsdTeamOrder; }
 const void* solve_grid_fn(bool lds, const Inst& I) { return pick_grid<SolveGridK>(lds, I.mixed, team_psd(I)); }
 const void* op_grid_fn(bool lds, const Inst& I) { return pick_grid<OpGridK>(lds, I.mixed, team_psd(I)); }
 
-// The column-panel kernel for S lanes per row; multi: the operator has
-// several panels (four rows per segment step, one otherwise).
-const void* panel_kernel(int S, bool multi) {
+// The column-panel kernel for S lanes per row, U steps per batch (U > 1
+// only with S = 4) and R rows per segment step (1 or 4).
+template <int S>
+const void* panel_kernel_s(int R) {
+    return R > 1 ? (const void*)k_spmv_panel<S, 1, 4> : (const void*)k_spmv_panel<S, 1, 1>;
+}
+const void* panel_kernel(int S, int U, int R) {
+    if (S == 4 && U > 1 && R == 1) {
+        switch (U) {
+            case 2: return (const void*)k_spmv_panel<4, 2, 1>;
+            case 3: return (const void*)k_spmv_panel<4, 3, 1>;
+            case 4: return (const void*)k_spmv_panel<4, 4, 1>;
+            case 5: return (const void*)k_spmv_panel<4, 5, 1>;
+            case 6: return (const void*)k_spmv_panel<4, 6, 1>;
+            case 7: return (const void*)k_spmv_panel<4, 7, 1>;
+            default: return (const void*)k_spmv_panel<4, 8, 1>;
+        }
+    }
     switch (S) {
-        case 1: return multi ? (const void*)k_spmv_panel<1, 4> : (const void*)k_spmv_panel<1, 1>;
-        case 2: return multi ? (const void*)k_spmv_panel<2, 4> : (const void*)k_spmv_panel<2, 1>;
-        case 4: return multi ? (const void*)k_spmv_panel<4, 4> : (const void*)k_spmv_panel<4, 1>;
-        case 8: return multi ? (const void*)k_spmv_panel<8, 4> : (const void*)k_spmv_panel<8, 1>;
-        case 16: return multi ? (const void*)k_spmv_panel<16, 4> : (const void*)k_spmv_panel<16, 1>;
-        case 32: return multi ? (const void*)k_spmv_panel<32, 4> : (const void*)k_spmv_panel<32, 1>;
-        default: return multi ? (const void*)k_spmv_panel<64, 4> : (const void*)k_spmv_panel<64, 1>;
+        case 1: return panel_kernel_s<1>(R);
+        case 2: return panel_kernel_s<2>(R);
+        case 4: return panel_kernel_s<4>(R);
+        case 8: return panel_kernel_s<8>(R);
+        case 16: return panel_kernel_s<16>(R);
+        case 32: return panel_kernel_s<32>(R);
+        default: return panel_kernel_s<64>(R);
     }
 }
 
@@ -1268,11 +1310,20 @@ int panel_plan(sscs_work* w, int which) {
     const int G = std::max(1, w->ncu);
     const int chunks = pl.P >= G ? 1 : (G + pl.P - 1) / pl.P;
     const double staging = (double)pl.P * chunks * pl.pc * 8.0;
-    pl.use = staging * 4.0 <= (double)nnz * 12.0;
+    // (and when a lane's entry index plus a batch, k + U S, stays within int32)
+    pl.use = staging * 4.0 <= (double)nnz * 12.0 && nnz <= (long long)INT_MAX - 1024;
     if (!pl.use) return SSCS_OK;
     const double mean = (double)nnz / std::max(1.0, (double)rows * pl.P);
-    pl.S = 1;
-    while (pl.S < 64 && pl.S < mean / 3.0) pl.S <<= 1;
+    if (mean >= 6.0 && mean <= 40.0) {           // four lanes per row, about a row per batch
+        pl.S = 4;
+        pl.U = std::min(8, std::max(2, (int)std::lround(mean / 4.0)));
+        pl.R = 1;
+    } else {                                      // S a power of two near a third of the row length
+        pl.S = 1;
+        while (pl.S < 64 && pl.S < mean / 3.0) pl.S <<= 1;
+        pl.U = 1;
+        pl.R = pl.P > 1 ? 4 : 1;
+    }
     std::vector<int> items;
     for (int p = 0; p < pl.P; ++p)
         for (int c = 0; c < chunks; ++c) items.insert(items.end(), {p, c, chunks});
@@ -1301,11 +1352,11 @@ int panel_plan(sscs_work* w, int which) {
     }
     static const bool attr = [] {
         bool ok = true;
-        for (const void* f : {panel_kernel(1, false), panel_kernel(2, false), panel_kernel(4, false),
-                              panel_kernel(8, false), panel_kernel(16, false), panel_kernel(32, false),
-                              panel_kernel(64, false), panel_kernel(1, true), panel_kernel(2, true),
-                              panel_kernel(4, true), panel_kernel(8, true), panel_kernel(16, true),
-                              panel_kernel(32, true), panel_kernel(64, true)})
+        std::vector<const void*> fns;
+        for (int S = 1; S <= 64; S <<= 1)
+            for (int R : {1, 4}) fns.push_back(panel_kernel(S, 1, R));
+        for (int U = 2; U <= 8; ++U) fns.push_back(panel_kernel(4, U, 1));
+        for (const void* f : fns)
             ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            kPanelCols * (int)sizeof(double)) == hipSuccess;
         return ok;
@@ -1333,7 +1384,7 @@ int launch_spmv(sscs_work* w, int transpose, const double* dx, double* dy) {
         double* part = pl.part;
         long long nnz = w->I.nnz;                // the panel-major copy holds the same entries
         void* args[] = {&rp, &ci, &v, &rows, &cols, &items, &nitems, &np, &pc, &dx, &dy, &part, &nnz};
-        HIP_TRY(hipLaunchKernel(panel_kernel(pl.S, pl.P > 1), dim3(grid), dim3(kPanelThreads), args,
+        HIP_TRY(hipLaunchKernel(panel_kernel(pl.S, pl.U, pl.R), dim3(grid), dim3(kPanelThreads), args,
                                 (size_t)pl.pc * sizeof(double), w->stream));
         if (pl.P > 1)
             k_panel_sum<<<std::max(1, std::min(65535, (M.rows + 255) / 256)), 256, 0, w->stream>>>(pl.part, pl.P, M.rows,

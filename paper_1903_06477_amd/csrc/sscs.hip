@@ -523,11 +523,13 @@ __global__ void k_spmv(Csr<double> M, const double* __restrict__ x, double* __re
 // With R = 1 a segment walks its rows one at a time, the next row's pointers
 // loaded before the current row's entries, and takes a row's entries U steps
 // at a time (each lane's U loads in flight together, at constant offsets from
-// one address; the steps left over go one by one, in the same order).
-// Measured on a 5e6 x 2e4 operator with 20 entries per row: S = 4, U = 5 (a
-// row's 20 entries in one batch) 249 us against 306-321 us for S = 8 one
-// step at a time; loads past a row's end made branch-free, by clamping or by
-// branches, cost more than the batch gains (302 us).
+// one address), then the at most U - 1 steps left over as one more batch
+// whose loads past the row's end read its last entry (and are not added);
+// the additions are in the same order as one step at a time.  Measured on
+// 5e6 x 2e4 operators: 20 entries per row, S = 4, U = 5 (a row in one batch)
+// 249 us against 306-321 us for S = 8 one step at a time (clamping every
+// batch's loads instead, 302 us); rows of 20.4 entries on average
+// (binomial), the left-over steps as a batch 316 us, one by one 346 us.
 // With R > 1 a segment takes R of its rows at a time: each step loads the
 // next entry of all of them (at index min(k, nnz - 1) for a row already done),
 // then adds those of the rows still going (the same additions in the same
@@ -579,7 +581,24 @@ __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restr
 #pragma unroll
                     for (int u = 0; u < U; ++u) acc += vu[u] * xs[cu[u]];
                 }
-                for (; k < ke; k += S) acc += v[k] * xs[ci[k]];
+                if constexpr (U > 1) {
+                    if (k < ke) {                    // at most U - 1 steps left: one batch as well
+                        const int kl = ke - 1;       // loads past the end read the row's last entry
+                        double vu[U - 1];
+                        int cu[U - 1];
+#pragma unroll
+                        for (int u = 0; u < U - 1; ++u) {
+                            const int kk = min(k + u * S, kl);
+                            vu[u] = v[kk];
+                            cu[u] = ci[kk];
+                        }
+#pragma unroll
+                        for (int u = 0; u < U - 1; ++u) {
+                            const double t = vu[u] * xs[cu[u]];
+                            if (k + u * S < ke) acc += t;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
                 if (ls == 0) {

@@ -309,6 +309,27 @@ def spmv_scaled(m: int = 5_000_000, n: int = 20_000, per_row: int = 20, seed: in
     return Problem(A=A, b=np.zeros(m), c=np.zeros(n), cone=Cone(l=m), name=f"spmv_{m}x{n}")
 
 
+def spmv_ragged(m: int, n: int, max_per_row: int, seed: int = 0) -> Problem:
+    """An m x n operator whose row lengths are uniform on 0..max_per_row
+    (empty rows included), columns distinct and sorted within each row,
+    values N(0,1); K = R+^m, b = c = 0.  For the SpMV's ragged-row cases; not
+    a solve workload."""
+    rng = rng_for(8, seed)
+    lens = rng.integers(0, max_per_row + 1, size=m)
+    indptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    nnz = int(indptr[-1])
+    row = np.repeat(np.arange(m), lens)
+    draw = rng.integers(0, n - np.repeat(lens, lens) + 1)
+    order = np.lexsort((draw, row))                # sorted within each row
+    pos = np.arange(nnz) - indptr[row]             # place within the row
+    cols = (draw[order] + pos).astype(np.int32)    # strictly increasing in a row
+    vals = rng.standard_normal(nnz)
+    A = sp.csr_matrix((vals, cols, indptr.astype(np.int32)), shape=(m, n))
+    A.has_sorted_indices = True
+    return Problem(A=A, b=np.zeros(m), c=np.zeros(n), cone=Cone(l=m), name=f"spmv_ragged_{m}x{n}")
+
+
 def lasso_dm_instance(n: int, kappa: float, mu: float, seed: int = 0) -> Problem:
     """One problem of the LASSO benchmark family of Sec. V-C: A in R^{m x n}
     with m = ceil(n/5) and condition number kappa (A = U diag(s) V^T, U, V

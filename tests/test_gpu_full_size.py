@@ -205,3 +205,28 @@ def test_spmv_column_panel_form(sscs, m, n, per_row):
         ref_t = p.A.T @ t
         bound_t = abs(p.A).T @ np.abs(t)
         assert np.all(np.abs(got_t - ref_t) <= 1e-13 * bound_t + 1e-300)
+
+
+@pytest.mark.parametrize("m,n,max_per_row", [(1_000_000, 20_000, 40), (4_000_000, 4000, 8)])
+def test_spmv_column_panel_ragged_rows(sscs, m, n, max_per_row):
+    """The column-panel SpMV on rows of 0..max_per_row entries (empty rows,
+    rows shorter and longer than one batch of four lanes' entries): the first
+    shape takes the batched row walk on A (one panel) and on A^T (49 panels,
+    binomial row lengths per panel), the second the one-step walk with two
+    lanes per row on A.  Same bound as the fixed-length case."""
+    p = G.spmv_ragged(m, n, max_per_row, seed=m % 97)
+    r = np.random.default_rng(m + n + 1)
+    print(f"column-panel SpMV, ragged rows, {m} x {n}, {p.A.nnz} nonzeros", flush=True)
+    with sscs.Solver(p, sscs.Settings(cg_tol=1e-10, cg_max=50)) as s:
+        x = r.standard_normal(n)
+        got = s.spmv(x)
+        ref = p.A @ x
+        bound = abs(p.A) @ np.abs(x)
+        assert np.all(np.abs(got - ref) <= 1e-13 * bound + 1e-300)
+        empty = np.diff(p.A.indptr) == 0
+        assert empty.any() and np.all(got[empty] == 0.0)
+        t = r.standard_normal(m)
+        got_t = s.spmv(t, transpose=True)
+        ref_t = p.A.T @ t
+        bound_t = abs(p.A).T @ np.abs(t)
+        assert np.all(np.abs(got_t - ref_t) <= 1e-13 * bound_t + 1e-300)

@@ -658,17 +658,32 @@ __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restr
     }
 }
 
-// y[r] = sum over panels p in order of part[p rows + r]; a thread loads eight
+// y[r] = sum over panels p in order of part[p rows + r].  A thread loads kB
 // panels' partials before adding them (the same additions in the same order),
-// so its loads are in flight together instead of one round trip per panel.
-__global__ void k_panel_sum(const double* __restrict__ part, int P, int rows, double* __restrict__ y) {
-    constexpr int kB = 8;
+// so its loads are in flight together instead of one round trip per panel;
+// the last, partial batch loads the row's last partial in place of those past
+// the end (not added).  Launched with small workgroups, so that a few
+// thousand rows still spread over every CU.  Measured on A^T of the 1e8-
+// nonzero operator (245 panels, 20 000 rows): 26.7 us with batches of eight,
+// branch-guarded, in 79 workgroups of 256.
+constexpr int kPanelSumThreads = 64;
+__global__ void __launch_bounds__(kPanelSumThreads) k_panel_sum(const double* __restrict__ part, int P, int rows,
+                                                                 double* __restrict__ y) {
+    constexpr int kB = 32;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
         double a = 0.0;
-        for (int p0 = 0; p0 < P; p0 += kB) {
+        int p0 = 0;
+        for (; p0 + kB <= P; p0 += kB) {
             double v[kB];
 #pragma unroll
-            for (int q = 0; q < kB; ++q) v[q] = p0 + q < P ? part[(size_t)(p0 + q) * rows + r] : 0.0;
+            for (int q = 0; q < kB; ++q) v[q] = part[(size_t)(p0 + q) * rows + r];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) a += v[q];
+        }
+        if (p0 < P) {
+            double v[kB];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) v[q] = part[(size_t)min(p0 + q, P - 1) * rows + r];
 #pragma unroll
             for (int q = 0; q < kB; ++q)
                 if (p0 + q < P) a += v[q];
@@ -1406,8 +1421,8 @@ int launch_spmv(sscs_work* w, int transpose, const double* dx, double* dy) {
         HIP_TRY(hipLaunchKernel(panel_kernel(pl.S, pl.U, pl.R), dim3(grid), dim3(kPanelThreads), args,
                                 (size_t)pl.pc * sizeof(double), w->stream));
         if (pl.P > 1)
-            k_panel_sum<<<std::max(1, std::min(65535, (M.rows + 255) / 256)), 256, 0, w->stream>>>(pl.part, pl.P, M.rows,
-                                                                                                  dy);
+            k_panel_sum<<<std::max(1, std::min(65535, (M.rows + kPanelSumThreads - 1) / kPanelSumThreads)),
+                          kPanelSumThreads, 0, w->stream>>>(pl.part, pl.P, M.rows, dy);
     } else {
         const long long threads = (long long)M.rows * M.seg;
         const int grid = (int)std::max<long long>(1, std::min<long long>(65535, (threads + 255) / 256));

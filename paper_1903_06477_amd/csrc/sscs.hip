@@ -548,9 +548,19 @@ __global__ void __launch_bounds__(kPanelThreads) k_spmv_panel(const int* __restr
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int p = items[3 * it], c = items[3 * it + 1], C = items[3 * it + 2];
         if (p != cur) {
+            // stage panel p of x: kStage loads per thread in flight before
+            // their stores (loads past the panel's end read its last entry)
+            constexpr int kStage = 8;
             __syncthreads();
             const int c0 = p * pc, len = min(pc, cols - c0);
-            for (int i = threadIdx.x; i < len; i += blockDim.x) xs[i] = x[c0 + i];
+            for (int i0 = threadIdx.x; i0 < len; i0 += kStage * blockDim.x) {
+                double t[kStage];
+#pragma unroll
+                for (int u = 0; u < kStage; ++u) t[u] = x[c0 + min(i0 + u * (int)blockDim.x, len - 1)];
+#pragma unroll
+                for (int u = 0; u < kStage; ++u)
+                    if (i0 + u * (int)blockDim.x < len) xs[i0 + u * blockDim.x] = t[u];
+            }
             __syncthreads();
             cur = p;
         }

@@ -285,11 +285,21 @@ def batched_leg(sscs, G, count=4096, precision="fp64", probs=None, autotune=True
     bs.close()
     its = np.array([i["iters"] for i in infos])
     ok = np.mean([i["status"] == sscs.SOLVED for i in infos])
+    # algorithmic bytes of the launch, with the solve kernel's unit accounting
+    # per instance (its CG-operator applications at its own operator's bytes,
+    # plus its outer vector passes), over the launch's wall-clock time (one
+    # kernel launch between two synchronisations)
+    alg = float(sum(op_units(f) * cg_op_bytes(p.A.nnz, p.m, p.n) + outer_vector_bytes(f, p.n + p.m + 1)
+                    for p, f in zip(probs, infos)))
+    gbs = alg / wall / 1e9
     res = {"workload": f"{count} LASSO-SOCP instances, n in 20..400, m in n/2..2n, density 0.05, one launch",
            "solves_per_s": count / wall if ok == 1.0 else 0.0, "iterations_per_s": float(its.sum()) / wall,
            "wall_s": wall, "solved_frac": float(ok), "iters_mean": float(its.mean()), "iters_max": int(its.max()),
            "cg_per_iter": float(sum(i["cg_iters"] for i in infos)) / max(1, int(its.sum())),
            "segment_widths": "mean-row-length rule",
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": alg, "timed": "launch wall clock",
+                        "note": "one workgroup per instance; bound by memory latency, not bandwidth"},
            "dtype": "f64" if precision == "fp64" else "f32 operator / f64"}
     if tuned is not None:
         res["autotuned_widths"] = tuned

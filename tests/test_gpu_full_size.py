@@ -230,3 +230,7 @@ def test_spmv_column_panel_ragged_rows(sscs, m, n, max_per_row):
         ref_t = p.A.T @ t
         bound_t = abs(p.A).T @ np.abs(t)
         assert np.all(np.abs(got_t - ref_t) <= 1e-13 * bound_t + 1e-300)
+        # the panels' partial sums are added in panel order whatever the
+        # launch order: a repeated product is the same bit for bit
+        assert np.array_equal(s.spmv(x), got)
+        assert np.array_equal(s.spmv(t, transpose=True), got_t)

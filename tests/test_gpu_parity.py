@@ -73,9 +73,10 @@ def cone_distances(prob, y, s):
 
 # ------------------------------------------------------------------ components
 
-@pytest.mark.parametrize("maker", ["lp", "socp", "mixed"])
+@pytest.mark.parametrize("maker", ["lp", "socp", "mixed", "holes"])
 def test_spmv_matches_scipy(sscs, maker):
-    prob = {"lp": G.config1_lp, "socp": lambda: G.small_socp(1), "mixed": mixed_cone_problem}[maker]()
+    prob = {"lp": G.config1_lp, "socp": lambda: G.small_socp(1), "mixed": mixed_cone_problem,
+            "holes": _holes_problem}[maker]()
     r = np.random.default_rng(1)
     with sscs.Solver(prob) as s:
         x = r.standard_normal(prob.n)
@@ -84,6 +85,25 @@ def test_spmv_matches_scipy(sscs, maker):
         np.testing.assert_allclose(s.spmv(x), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
         ref = prob.A.T @ y
         np.testing.assert_allclose(s.spmv(y, transpose=True), ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+        if maker == "holes":            # empty rows of A and of A^T give exact zeros
+            assert np.all(s.spmv(x)[np.diff(prob.A.indptr) == 0] == 0.0)
+            assert np.all(s.spmv(y, transpose=True)[np.asarray(abs(prob.A).sum(axis=0)).ravel() == 0] == 0.0)
+
+
+def _holes_problem(seed=0, m=400, n=90):
+    """A with empty rows (every 9th) and empty columns (every 7th): rows of
+    A and of A^T with no entries, their products exactly 0 and, in the
+    linear step, columns whose Jacobi weight is 1."""
+    r = G.rng_for(45, seed)
+    A = G.sprandn(m, n, 0.06, r).tocsr()
+    rmask = np.ones(m)
+    rmask[::9] = 0.0
+    cmask = np.ones(n)
+    cmask[::7] = 0.0
+    A = (sp.diags(rmask) @ A @ sp.diags(cmask)).tocsr()
+    A.eliminate_zeros()
+    A.sort_indices()
+    return G.Problem(A=A, b=r.standard_normal(m), c=r.standard_normal(n), cone=G.Cone(l=m), name="holes")
 
 
 def _long_column_problem(seed):
@@ -186,7 +206,7 @@ def test_project_exp_hard_points(sscs):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * (1 + np.abs(y).max()))
 
 
-@pytest.mark.parametrize("maker", ["lp", "socp", "mixed", "tall", "wide"])
+@pytest.mark.parametrize("maker", ["lp", "socp", "mixed", "tall", "wide", "holes"])
 def test_linear_step_matches_oracle(sscs, maker):
     oracle, _ = _oracle()
     r = G.rng_for(41, 0)
@@ -196,6 +216,7 @@ def test_linear_step_matches_oracle(sscs, maker):
                                   c=r.standard_normal(70), cone=G.Cone(l=500)),
         "wide": lambda: G.Problem(A=G.sprandn(60, 200, 0.1, r), b=r.standard_normal(60),
                                   c=r.standard_normal(200), cone=G.Cone(l=60)),
+        "holes": _holes_problem,
     }
     prob = makers[maker]()
     lin = oracle.DirectLinSys(prob.A, prob.b, prob.c)

@@ -111,3 +111,22 @@ def test_noalloc_rejects_instances_beyond_its_scratch():
         sscs.solve_noalloc(bad, sscs.Settings(precision="mixed"))
     with pytest.raises(sscs.SSCSError, match="unsupported"):
         sscs.solve_noalloc(bad, sscs.Settings(linsys="direct"))
+
+
+def test_batch_create_rejects_unsupported_forms_on_the_host():
+    # the batched engine's limits, checked before any device work: PSD blocks
+    # above order 64, the mixed-precision form, the direct linear step
+    import numpy as np
+    from paper_1903_06477_amd import generators as G
+    from paper_1903_06477_amd import sscs
+    r = np.random.default_rng(0)
+    cone = G.Cone(l=3, s=[65])
+    m = cone.rows()
+    psd65 = G.Problem(A=G.sprandn(m, 10, 0.05, r), b=r.standard_normal(m), c=r.standard_normal(10), cone=cone)
+    with pytest.raises(sscs.SSCSError, match="unsupported"):
+        sscs.BatchSolver([psd65])
+    lp = G.config1_lp()
+    with pytest.raises(sscs.SSCSError, match="unsupported"):
+        sscs.BatchSolver([lp, lp], sscs.Settings(precision="mixed"))
+    with pytest.raises(sscs.SSCSError, match="unsupported"):
+        sscs.BatchSolver([lp, lp], sscs.Settings(linsys="direct"))
